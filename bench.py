@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark: Torontonians/s and subset determinants/s at n = 30 (FP64).
+
+One step = one full Torontonian of the n = 30 precision workload (2n x 2n =
+60 x 60 complex128, squeezing r_i ~ U[0.3, 1.2], Haar interferometer, loss
+eta = 0.9, seed 0; 2^30 subsets) through the C ABI: host validation and
+packing, one persistent launch of the recursive kernel, the fixed-order
+reduction and the copy of the result.  The input is synthetic (seeded
+generator, no dataset).
+
+Printed as one JSON line, with
+* roofline: the recursive kernel's algorithmic FLOP (paper_2109_04528_amd/flops.py)
+  over its average duration, measured with HIP events on the stream the kernel
+  runs on, against the MI355X FP64 vector peak;
+* plain: the per-subset-Cholesky comparison kernel on a sampled mask range;
+* cpu_baseline: the CPU oracle timed on a bounded subtree of the same workload;
+* with --serve, p50/p99 latency of a Poisson stream of mixed-n requests.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Tor evals/s + subset dets/s at n=30 FP64; p50/p99 latency, mixed-n stream"
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
+
+
+def cpu_baseline(O, n, budget_s=15.0):
+    """The CPU oracle (as it stands) on a subtree of the workload: modes
+    0..k-1 fixed to an alternating include pattern, the rest enumerated."""
+    from oracle import oracle as orc
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+    def run(m):
+        k = n - m
+        fix_mask = (1 << k) - 1
+        fix_val = sum(1 << i for i in range(0, k, 2))
+        t0 = time.perf_counter()
+        r = orc.tor(O, mode=orc.F64, threads=cores, fix_mask=fix_mask, fix_val=fix_val)
+        return time.perf_counter() - t0, r.count, k
+
+    dt, cnt, _ = run(12)
+    rate = cnt / max(dt, 1e-9)
+    m = int(math.floor(math.log2(max(rate * budget_s, 1 << 12))))
+    m = max(12, min(m, n - 2))
+    dt, cnt, k = run(m)
+    dets = cnt / dt
+    return {"value": dets / float(1 << n), "unit": "Tor/s", "cores": cores, "kind": "oracle",
+            "subset_dets_per_s": dets, "seconds": dt,
+            "sample": f"{cnt} subsets of the n={n} workload (modes 0..{k - 1} fixed, alternating "
+                      f"include pattern), FP64 Cholesky per subset, __float128 sum, {cores} threads"}
+
+
+def serve_stream(ctx, count, seed, rate_hz):
+    """Poisson arrivals of click submatrices O_S of 40-mode states, n ~ U{8..32}."""
+    import numpy as np
+    from paper_2109_04528_amd import inputs as gen
+    rng = np.random.default_rng(seed)
+    states = [gen.random_O(40, 5000 + i, 0.5, 1.0, float(rng.uniform(0.3, 1.0))) for i in range(8)]
+    reqs = []
+    for i in range(count):
+        n = int(rng.integers(8, 33))
+        S = sorted(rng.choice(40, size=n, replace=False).tolist())
+        reqs.append(gen.click_submatrix(states[i % len(states)], S))
+    gaps = rng.exponential(1.0 / rate_hz, size=count)
+    t_sub = {}
+    lat = []
+    pending = {}
+    t0 = time.perf_counter()
+    nxt = t0
+    i = 0
+    while i < count or pending:
+        now = time.perf_counter()
+        while i < count and now >= nxt:
+            tk = ctx.submit(reqs[i])
+            t_sub[tk] = time.perf_counter()
+            pending[tk] = i
+            nxt += gaps[i]
+            i += 1
+        for tk in list(pending):
+            r = ctx.poll(tk)
+            if r is not None:
+                lat.append(time.perf_counter() - t_sub[tk])
+                del pending[tk]
+        time.sleep(0.0002)
+    wall = time.perf_counter() - t0
+    lat = sorted(lat)
+    return {"requests": count, "rate_hz": rate_hz, "wall_s": wall, "tor_per_s": count / wall,
+            "p50_ms": 1e3 * lat[len(lat) // 2], "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--plain-masks", type=int, default=1 << 18)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--serve", type=int, default=0, help="requests in the mixed-n stream (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "the subtree roots would shard across GPUs with one 16-byte reduction per Torontonian, "
+              "but no multi-GPU path is built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2109_04528_amd import Context, inputs, workspace_size
+    from paper_2109_04528_amd.flops import tor_flops
+
+    n = args.n
+    O = inputs.random_O(n, 0, 0.3, 1.2, 0.9)
+    print(f"bench: n={n} workload staged", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    ws = torch.empty(workspace_size(max(n, 32), 0, 4), dtype=torch.uint8, device=dev)
+    ctx = Context(device=0, stream=stream, workspace=ws)
+    for _ in range(args.warmup):
+        ctx.eval(O)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = ctx.eval(O)
+        kms.append(r.device_ms)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print(f"bench: {args.steps} steps done", file=sys.stderr, flush=True)
+    step_s = (t1 - t0) / args.steps
+    tor_per_s = 1.0 / step_s
+    kernel_ms = float(np.mean(kms))
+    flops = tor_flops(n)
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+
+    plain = None
+    if args.plain_masks > 0 and n <= 34:
+        m = min(args.plain_masks, 1 << n)
+        lo = (1 << n) // 2 - m // 2  # a contiguous mask range from the middle
+        ctx.eval_plain(O, lo, lo + m)
+        p = ctx.eval_plain(O, lo, lo + m)
+        plain_dets = m / (p.device_ms * 1e-3)
+        plain = {"masks": m, "kernel_ms": p.device_ms, "subset_dets_per_s": plain_dets,
+                 "recursive_speedup": ((1 << n) / (kernel_ms * 1e-3)) / plain_dets}
+        print("bench: plain comparison done", file=sys.stderr, flush=True)
+
+    serve = None
+    if args.serve > 0:
+        serve = serve_stream(ctx, args.serve, 5, rate_hz=200.0)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(O, n, args.cpu_budget)
+        print("bench: cpu baseline done", file=sys.stderr, flush=True)
+
+    ctx.close()
+    out = {
+        "metric": METRIC,
+        "value": tor_per_s,
+        "unit": "Tor/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"exact Torontonian, n={n} modes (60x60 complex128 for n=30), r~U[0.3,1.2], "
+                               f"Haar U, eta=0.9, seed 0, 2^{n} subsets per step", "n": n,
+                   "subsets_per_step": 1 << n, "path": "recursive, complex FP64 factor, double-double sum"},
+        "subset_dets_per_s": (1 << n) * tor_per_s,
+        "kernel_ms": kernel_ms,
+        "kernel_subset_dets_per_s": (1 << n) / (kernel_ms * 1e-3),
+        "tor": r.value,
+        "cancellation_R": r.cancellation,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "flop_per_launch": flops, "kernel": "tor_main (complex, T=3, B=6)"},
+        "plain": plain,
+        "serving": serve,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

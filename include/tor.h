@@ -1,0 +1,157 @@
+/*
+ * tor.h -- C ABI of the MI355X Torontonian library (libtor.so).
+ *
+ * The library evaluates the exact Torontonian of Eq. 2 of Kaposi et al.,
+ * "Polynomial speedup in Torontonian calculation by a scalable recursive
+ * algorithm":
+ *
+ *     Tor(O) = sum over Z subset {0..n-1} of (-1)^(n-|Z|) / sqrt(det(I - O)_Z)
+ *
+ * where (I - O)_Z keeps rows and columns {i, i+n : i in Z}.  The sum is
+ * evaluated the recursive way of Sec. 2 (Algorithm 2): the factorisation of a
+ * parent subset is reused and a child subset only adds the two rows of its new
+ * mode, here in right-looking form (the Schur complement of the included modes
+ * is carried down the include/exclude tree, so each child costs one rank-2
+ * update), on gfx950 in FP64 with double-double accumulation of the terms.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * O is complex128, row-major, 2n x 2n, stored as interleaved (re, im)
+ *    doubles; ld is the leading dimension in complex elements (ld >= 2n).
+ *    Rows and columns are in block order a_1..a_n, a_1^dag..a_n^dag, so mode i
+ *    owns rows {i, i+n} (the problem statement of Sec. 1).
+ *  * Only the lower triangle of I - O is read, as in Algorithm 1; the upper
+ *    triangle is taken as its conjugate transpose.
+ *  * I - O must be Hermitian positive definite.  Every principal submatrix of
+ *    an HPD matrix is HPD (Cauchy interlacing), so one Cholesky of the full
+ *    I - O on the host validates all 2^n subsets.  The paper takes |det| in
+ *    Eq. 2; for HPD input det > 0 and the two agree.
+ *  * n = 0 gives Tor = 1 (the empty subset only).
+ *  * Unless TOR_INPUT_DEVICE is set, O is a host pointer.  The caller owns its
+ *    inputs; the library copies what it needs before the call returns (for
+ *    tor_submit as well).  The context owns all device state.
+ *  * A context is internally serialised: calls on one context from several
+ *    threads are safe and run one at a time.
+ *  * Every function returns TOR_OK (0) or a negative TOR_E_* code; the output
+ *    structure is untouched on argument errors.
+ */
+#ifndef TOR_H
+#define TOR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define TOR_OK 0
+#define TOR_PENDING 1          /* tor_poll: the request is still running            */
+#define TOR_E_INVAL (-1)       /* null pointer, n < 0, n > max_n, ld < 2n, NaN/Inf  */
+#define TOR_E_NOT_PD (-2)      /* I - O is not Hermitian positive definite          */
+#define TOR_E_NUMERIC (-3)     /* a pivot <= 0 or NaN inside the walk               */
+#define TOR_E_BUSY (-4)        /* admission refused: serving queue is full          */
+#define TOR_E_NOMEM (-5)       /* device or host allocation failed                  */
+#define TOR_E_DEVICE (-6)      /* no usable GPU, or a HIP runtime error             */
+#define TOR_E_TIMEOUT (-7)     /* a host-side deadline passed                       */
+#define TOR_E_UNKNOWN (-8)     /* tor_poll on a ticket this context never issued    */
+
+/* ---- options ------------------------------------------------------------- */
+#define TOR_ACCUM_DD 0   /* double-double accumulation of the signed terms (default) */
+#define TOR_ACCUM_FP64 1 /* plain FP64 accumulation, for comparison                   */
+
+#define TOR_INPUT_DEVICE 0x1u    /* O points to device memory                          */
+#define TOR_CHECK_HERMITIAN 0x2u /* reject O whose upper triangle is not the conjugate
+                                    transpose of its lower triangle (rel. tol 1e-12)   */
+#define TOR_FORCE_COMPLEX 0x4u   /* never take the real quadrature path               */
+
+typedef struct tor_ctx tor_ctx;
+
+typedef struct {
+    int device;             /* HIP device ordinal                                     */
+    void *stream;           /* hipStream_t to run on (NULL: the library creates one)  */
+    void *workspace;        /* caller-owned device buffer or NULL (library allocates) */
+    size_t workspace_bytes; /* its size; see tor_workspace_size                       */
+    int max_n;              /* largest n this context accepts (0: 40)                 */
+    int split_k;            /* roots = 2^split_k per matrix (0: automatic)            */
+    int waves_per_cu;       /* persistent waves per CU (0: automatic)                 */
+    int accum;              /* TOR_ACCUM_DD or TOR_ACCUM_FP64                         */
+    unsigned flags;         /* TOR_INPUT_DEVICE | TOR_CHECK_HERMITIAN | ...           */
+} tor_options;
+
+typedef struct {
+    double tor;                /* Torontonian, high part                                */
+    double tor_lo;             /* low part of the double-double value                   */
+    double sum_abs;            /* sum of |term|; R = sum_abs / |tor| is the cancellation */
+    double err_est;            /* estimated relative error from FP64 term rounding       */
+    unsigned long long subsets;/* 2^n                                                   */
+    int status;                /* TOR_OK or an error for this matrix                    */
+    int path;                  /* 1 = real quadrature path, 2 = complex path            */
+    float device_ms;           /* device time of the launch that produced it            */
+} tor_result;
+
+/* Defaults for every field (device 0, library stream and workspace, max_n 40). */
+void tor_default_options(tor_options *opt);
+
+/* Create a context on opt->device.  *out receives the handle.
+ * Errors: TOR_E_INVAL (null out), TOR_E_DEVICE (no GPU), TOR_E_NOMEM. */
+int tor_create(tor_ctx **out, const tor_options *opt);
+
+/* Wait for in-flight work, then free every device and host resource. */
+void tor_destroy(tor_ctx *ctx);
+
+/* Device bytes a caller-provided workspace needs for matrices up to max_n
+ * with up to max_inflight concurrent serving requests. */
+size_t tor_workspace_size(int max_n, int split_k, int max_inflight);
+
+/* Torontonian of one 2n x 2n matrix (Eq. 2), recursive GPU path. */
+int tor_eval(tor_ctx *ctx, int n, const double *O, long ld, tor_result *out);
+
+/* Torontonians of count matrices of possibly different n in ONE persistent
+ * launch: one work queue over (matrix, subtree root) items, largest n first.
+ * out[i] corresponds to O[i] (input order).  Per-matrix failures are reported
+ * in out[i].status and make the call return the first such error. */
+int tor_eval_batch(tor_ctx *ctx, int count, const int *n, const double *const *O,
+                   const long *ld, tor_result *out);
+
+/* The comparison baseline (not the method): every subset gets a fresh Cholesky
+ * (Algorithm 1) on the GPU, one wavefront per subset.  Sums the subsets whose
+ * bitmask lies in [mask_begin, mask_end) (pass 0 and 2^n for all of them). */
+int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld,
+                   unsigned long long mask_begin, unsigned long long mask_end,
+                   tor_result *out);
+
+/* Verification aid: the recursive path's per-subtree partial sums.  Root r is
+ * the include/exclude decision on modes 0..k-1 given by the bits of r (bit i =
+ * mode i included); partial r sums the subsets Z with Z & (2^k - 1) == r.
+ * *k_out receives k; partials receives 2^k (hi, lo, sum_abs) triples and must
+ * hold 3 * 2^k doubles (k <= k_max; fails with TOR_E_INVAL otherwise). */
+int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max,
+                      int *k_out, double *partials, tor_result *out);
+
+/* Serving: enqueue one Torontonian request.  O is copied before return.
+ * *ticket identifies it for tor_poll.  TOR_E_BUSY when admission is refused. */
+int tor_submit(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long *ticket);
+
+/* Serving: non-blocking.  TOR_OK and *out filled once the request is done
+ * (the ticket is then released), TOR_PENDING while it runs, TOR_E_UNKNOWN for
+ * a ticket this context does not hold. */
+int tor_poll(tor_ctx *ctx, unsigned long long ticket, tor_result *out);
+
+/* Serving: block until every submitted request has finished or timeout_ms
+ * (< 0: no limit) passes (TOR_E_TIMEOUT). */
+int tor_drain(tor_ctx *ctx, int timeout_ms);
+
+/* Verification aid: the device's reciprocal square root and reciprocal (the
+ * hardware seeds refined by two Newton steps) for count host doubles x;
+ * out receives 2 * count doubles (rsqrt(x_i), 1/x_i). */
+int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out);
+
+/* Static description of a code. */
+const char *tor_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOR_H */

@@ -1,0 +1,292 @@
+"""ctypes binding of libtor.so (the C ABI declared in include/tor.h).
+
+Argument marshalling only: every step of the Torontonian runs in the HIP
+library.  If ``libtor.so`` is missing or cannot be loaded this module raises;
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtor.so")
+
+TOR_OK = 0
+TOR_PENDING = 1
+TOR_E_INVAL = -1
+TOR_E_NOT_PD = -2
+TOR_E_NUMERIC = -3
+TOR_E_BUSY = -4
+TOR_E_NOMEM = -5
+TOR_E_DEVICE = -6
+TOR_E_TIMEOUT = -7
+TOR_E_UNKNOWN = -8
+
+TOR_ACCUM_DD = 0
+TOR_ACCUM_FP64 = 1
+
+TOR_INPUT_DEVICE = 0x1
+TOR_CHECK_HERMITIAN = 0x2
+TOR_FORCE_COMPLEX = 0x4
+
+# every symbol include/tor.h declares
+EXPORTS = [
+    "tor_default_options", "tor_create", "tor_destroy", "tor_workspace_size", "tor_eval",
+    "tor_eval_batch", "tor_eval_plain", "tor_eval_partials", "tor_submit", "tor_poll",
+    "tor_drain", "tor_debug_math", "tor_strerror",
+]
+
+
+class tor_options(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("max_n", ctypes.c_int),
+        ("split_k", ctypes.c_int),
+        ("waves_per_cu", ctypes.c_int),
+        ("accum", ctypes.c_int),
+        ("flags", ctypes.c_uint),
+    ]
+
+
+class tor_result(ctypes.Structure):
+    _fields_ = [
+        ("tor", ctypes.c_double),
+        ("tor_lo", ctypes.c_double),
+        ("sum_abs", ctypes.c_double),
+        ("err_est", ctypes.c_double),
+        ("subsets", ctypes.c_ulonglong),
+        ("status", ctypes.c_int),
+        ("path", ctypes.c_int),
+        ("device_ms", ctypes.c_float),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libtor.so and declare the signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libtor.so not built at {path}; run __graft_entry__.build() or "
+                          "python -m paper_2109_04528_amd.build")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.tor_default_options.argtypes = [P(tor_options)]
+    lib.tor_default_options.restype = None
+    lib.tor_create.argtypes = [P(ctypes.c_void_p), P(tor_options)]
+    lib.tor_create.restype = ctypes.c_int
+    lib.tor_destroy.argtypes = [ctypes.c_void_p]
+    lib.tor_destroy.restype = None
+    lib.tor_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.tor_workspace_size.restype = ctypes.c_size_t
+    lib.tor_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long, P(tor_result)]
+    lib.tor_eval.restype = ctypes.c_int
+    lib.tor_eval_batch.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_void_p),
+                                   P(ctypes.c_long), P(tor_result)]
+    lib.tor_eval_batch.restype = ctypes.c_int
+    lib.tor_eval_plain.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long,
+                                   ctypes.c_ulonglong, ctypes.c_ulonglong, P(tor_result)]
+    lib.tor_eval_plain.restype = ctypes.c_int
+    lib.tor_eval_partials.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long,
+                                      ctypes.c_int, P(ctypes.c_int), P(ctypes.c_double), P(tor_result)]
+    lib.tor_eval_partials.restype = ctypes.c_int
+    lib.tor_submit.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long,
+                               P(ctypes.c_ulonglong)]
+    lib.tor_submit.restype = ctypes.c_int
+    lib.tor_poll.argtypes = [ctypes.c_void_p, ctypes.c_ulonglong, P(tor_result)]
+    lib.tor_poll.restype = ctypes.c_int
+    lib.tor_drain.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.tor_drain.restype = ctypes.c_int
+    lib.tor_debug_math.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]
+    lib.tor_debug_math.restype = ctypes.c_int
+    lib.tor_strerror.argtypes = [ctypes.c_int]
+    lib.tor_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class TorError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = load().tor_strerror(code).decode()
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+@dataclass
+class TorResult:
+    tor: float
+    tor_lo: float
+    sum_abs: float
+    err_est: float
+    subsets: int
+    status: int
+    path: int
+    device_ms: float
+
+    @property
+    def value(self) -> float:
+        return self.tor + self.tor_lo
+
+    @property
+    def cancellation(self) -> float:
+        v = abs(self.tor)
+        return float("inf") if v == 0 else self.sum_abs / v
+
+    @classmethod
+    def from_c(cls, r: tor_result) -> "TorResult":
+        return cls(r.tor, r.tor_lo, r.sum_abs, r.err_est, int(r.subsets), r.status, r.path, r.device_ms)
+
+
+def _host_c128(O) -> np.ndarray:
+    """Marshal O (numpy array or torch tensor) to a contiguous host complex128 array."""
+    try:
+        import torch  # noqa: F401
+        if hasattr(O, "detach") and hasattr(O, "device"):
+            O = O.detach()
+            if O.device.type != "cpu":
+                O = O.cpu()
+            O = O.numpy()
+    except ImportError:
+        pass
+    A = np.ascontiguousarray(np.asarray(O, dtype=np.complex128))
+    if A.ndim != 2 or A.shape[0] != A.shape[1] or A.shape[0] % 2:
+        raise ValueError("O must be a 2n x 2n matrix")
+    return A
+
+
+class Context:
+    """One libtor context (device state, stream, workspace)."""
+
+    def __init__(self, device: int = 0, stream=None, max_n: int = 40, split_k: int = 0,
+                 waves_per_cu: int = 0, accum: str = "dd", flags: int = 0, workspace=None):
+        lib = load()
+        opt = tor_options()
+        lib.tor_default_options(ctypes.byref(opt))
+        opt.device = device
+        if stream is not None:
+            opt.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        if workspace is not None:  # e.g. a torch uint8 tensor on the device
+            opt.workspace = ctypes.c_void_p(int(workspace.data_ptr()))
+            opt.workspace_bytes = int(workspace.numel() * workspace.element_size())
+            self._ws = workspace
+        opt.max_n = max_n
+        opt.split_k = split_k
+        opt.waves_per_cu = waves_per_cu
+        opt.accum = TOR_ACCUM_FP64 if accum == "fp64" else TOR_ACCUM_DD
+        opt.flags = flags
+        h = ctypes.c_void_p()
+        rc = lib.tor_create(ctypes.byref(h), ctypes.byref(opt))
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_create")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.tor_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def eval(self, O, check: bool = True) -> TorResult:
+        A = _host_c128(O)
+        n = A.shape[0] // 2
+        r = tor_result()
+        rc = self._lib.tor_eval(self._h, n, A.ctypes.data if n else None, max(2 * n, 1), ctypes.byref(r))
+        if check and rc != TOR_OK:
+            raise TorError(rc, "tor_eval")
+        return TorResult.from_c(r)
+
+    def eval_batch(self, Os: Sequence, check: bool = True) -> List[TorResult]:
+        arrs = [_host_c128(O) for O in Os]
+        cnt = len(arrs)
+        ns = (ctypes.c_int * cnt)(*[a.shape[0] // 2 for a in arrs])
+        ptrs = (ctypes.c_void_p * cnt)(*[a.ctypes.data for a in arrs])
+        lds = (ctypes.c_long * cnt)(*[max(a.shape[0], 1) for a in arrs])
+        res = (tor_result * cnt)()
+        rc = self._lib.tor_eval_batch(self._h, cnt, ns, ptrs, lds, res)
+        if check and rc != TOR_OK:
+            raise TorError(rc, "tor_eval_batch")
+        return [TorResult.from_c(res[i]) for i in range(cnt)]
+
+    def eval_plain(self, O, mask_begin: int = 0, mask_end: Optional[int] = None,
+                   check: bool = True) -> TorResult:
+        A = _host_c128(O)
+        n = A.shape[0] // 2
+        if mask_end is None:
+            mask_end = 1 << n
+        r = tor_result()
+        rc = self._lib.tor_eval_plain(self._h, n, A.ctypes.data, 2 * n, mask_begin, mask_end, ctypes.byref(r))
+        if check and rc != TOR_OK:
+            raise TorError(rc, "tor_eval_plain")
+        return TorResult.from_c(r)
+
+    def eval_partials(self, O, k_max: int):
+        A = _host_c128(O)
+        n = A.shape[0] // 2
+        parts = np.zeros(3 * (1 << k_max), dtype=np.float64)
+        k = ctypes.c_int()
+        r = tor_result()
+        rc = self._lib.tor_eval_partials(self._h, n, A.ctypes.data if n else None, max(2 * n, 1), k_max,
+                                         ctypes.byref(k), parts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         ctypes.byref(r))
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_eval_partials")
+        return k.value, parts[: 3 * (1 << k.value)].reshape(-1, 3), TorResult.from_c(r)
+
+    def submit(self, O) -> int:
+        A = _host_c128(O)
+        n = A.shape[0] // 2
+        t = ctypes.c_ulonglong()
+        rc = self._lib.tor_submit(self._h, n, A.ctypes.data if n else None, max(2 * n, 1), ctypes.byref(t))
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_submit")
+        return t.value
+
+    def poll(self, ticket: int) -> Optional[TorResult]:
+        r = tor_result()
+        rc = self._lib.tor_poll(self._h, ticket, ctypes.byref(r))
+        if rc == TOR_PENDING:
+            return None
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_poll")
+        return TorResult.from_c(r)
+
+    def drain(self, timeout_ms: int = -1) -> None:
+        rc = self._lib.tor_drain(self._h, timeout_ms)
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_drain")
+
+    def debug_math(self, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.zeros(2 * x.size, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = self._lib.tor_debug_math(self._h, x.size, x.ctypes.data_as(dp), out.ctypes.data_as(dp))
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_debug_math")
+        return out.reshape(-1, 2)
+
+
+def workspace_size(max_n: int, split_k: int = 0, max_inflight: int = 1) -> int:
+    return int(load().tor_workspace_size(max_n, split_k, max_inflight))

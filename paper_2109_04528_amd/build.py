@@ -1,0 +1,42 @@
+"""Build libtor.so (the HIP kernels and the C ABI) for gfx950, in-tree.
+
+``python -m paper_2109_04528_amd.build`` compiles ``csrc/tor_kernels.hip`` and
+``csrc/tor_runtime.cpp`` with hipcc into ``paper_2109_04528_amd/libtor.so``.
+Packed-FP32 instructions are disabled; no fast-math (the double-double
+accumulation relies on IEEE rounding and no reassociation).
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libtor.so")
+ARCH = os.environ.get("TOR_OFFLOAD_ARCH", "gfx950")
+
+SOURCES = ["tor_kernels.hip", "tor_runtime.cpp"]
+
+
+def hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
+        if c and (os.path.sep not in c or os.path.exists(c)):
+            return c
+    return "hipcc"
+
+
+def build(verbose: bool = False, extra=None) -> str:
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-fno-fast-math", "-Wall", "-Wno-unused-function",
+           "-I", os.path.join(HERE, "..", "include"),
+           "-x", "hip"] + [os.path.join(CSRC, s) for s in SOURCES] + \
+          ["-o", LIB + ".tmp", "-lpthread"] + list(extra or [])
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,61 @@
+"""CPU-side checks of the C ABI library: it builds, loads, exports every
+symbol include/tor.h declares, and rejects bad arguments without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2109_04528_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tor.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(tor_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = header_functions()
+    assert len(names) >= 13, names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in tor.h but not exported"
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_strerror_covers_codes():
+    lib = _lib.load()
+    for code in range(-8, 2):
+        s = lib.tor_strerror(code).decode()
+        assert s and s != "unrecognised status code", code
+    assert lib.tor_strerror(-99).decode() == "unrecognised status code"
+
+
+def test_struct_layouts_match_header():
+    # tor_options: int, ptr, ptr, size_t, 4 ints, unsigned -> 56 bytes on x86-64
+    assert ctypes.sizeof(_lib.tor_options) == 56
+    # tor_result: 4 doubles, ull, 2 ints, float (+pad) -> 56 bytes
+    assert ctypes.sizeof(_lib.tor_result) == 56
+
+
+def test_argument_errors_without_device():
+    lib = _lib.load()
+    assert lib.tor_create(None, None) == _lib.TOR_E_INVAL
+    r = _lib.tor_result()
+    assert lib.tor_eval(None, 1, None, 2, ctypes.byref(r)) == _lib.TOR_E_INVAL
+    assert lib.tor_poll(None, 1, ctypes.byref(r)) == _lib.TOR_E_INVAL
+    assert lib.tor_drain(None, 0) == _lib.TOR_E_INVAL
+    assert lib.tor_workspace_size(30, 0, 1) > 0
+    assert lib.tor_workspace_size(-1, 0, 1) == 0
+
+
+def test_create_reports_missing_device():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert _lib.load().tor_create(ctypes.byref(h), None) == _lib.TOR_E_DEVICE

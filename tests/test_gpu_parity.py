@@ -1,0 +1,234 @@
+"""GPU parity: the recursive HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances.  Every term t_Z = (-1)^(n-|Z|)/sqrt(det) is formed in FP64 by both
+sides, through different but backward-stable factorisation orders, so each
+term carries a relative error of at most a few units of roundoff per
+elimination step, amplified by the conditioning kappa of I - O.  The sums
+themselves are exact on both sides (every term is a double of magnitude >= 1
+and both sides add them without rounding), so the difference is bounded by
+    |Tor_gpu - Tor_oracle| <= c * N * kappa * u * sum_Z |t_Z|.
+Where that bound is below the benchmark spec's target of 1e-10 relative, the test
+asks for 1e-10.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2109_04528_amd import inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2109_04528_amd import Context
+    c = Context(device=0)
+    yield c
+    c.close()
+
+
+def kappa(O):
+    n2 = O.shape[0]
+    C = np.eye(n2) - O
+    C = np.tril(C) + np.tril(C, -1).conj().T
+    w = np.linalg.eigvalsh(C)
+    return float(w[-1] / w[0])
+
+
+def term_bound(O, sum_abs):
+    n = O.shape[0] // 2
+    return 8.0 * max(n, 9) * kappa(O) * U * sum_abs
+
+
+def check(ctx, O, mode=orc.QUAD, label=""):
+    say(f"case {label}: n={O.shape[0] // 2}")
+    r = ctx.eval(O)
+    q = orc.tor(O, mode=mode)
+    err = abs(r.value - q.value)
+    bound = term_bound(O, q.sum_abs)
+    rel = err / abs(q.value) if q.value else err
+    say(f"  gpu={r.value!r} oracle={q.value!r} rel={rel:.3e} R={q.cancellation:.3e} "
+        f"bound_rel={bound / max(abs(q.value), 1e-300):.3e} ms={r.device_ms:.3f}")
+    assert r.status == 0
+    assert err <= bound, (label, r.value, q.value, err, bound)
+    return r, q
+
+
+def test_math_probe(ctx):
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.uniform(1e-6, 1.0, 4000), 10.0 ** rng.uniform(-60, 0, 4000),
+                        np.array([1.0, 0.25, 0.5, 2.0 ** -40])])
+    say("case math_probe")
+    out = ctx.debug_math(x)
+    xl = x.astype(np.longdouble)
+    rs = (1 / np.sqrt(xl)).astype(np.float64)
+    rc = (1 / xl).astype(np.float64)
+
+    def ulps(a, b):
+        return np.abs(a.view(np.int64) - b.view(np.int64))
+
+    assert ulps(out[:, 0], rs).max() <= 1
+    assert ulps(out[:, 1], rc).max() <= 1
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 8, 9, 10, 11, 12, 13])
+def test_small_n_against_quad(ctx, n):
+    O = gen.random_O(n, 100 + n, 0.5, 1.0, 0.7) if n else gen.vacuum_O(0)
+    if n == 0:
+        r = ctx.eval(O)
+        assert r.value == 1.0
+        return
+    check(ctx, O, label=f"small n={n}")
+
+
+def test_first_workload_meets_1e10(ctx):
+    # n = 10, r ~ U[.5, 1], Haar U, eta = .5, seed 0: 1024 subsets
+    O = gen.random_O(10, 0, 0.5, 1.0, 0.5)
+    r, q = check(ctx, O, label="n=10 seed 0")
+    assert abs(r.value - q.value) <= 1e-10 * abs(q.value)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_precision_workload_n16_against_quad(ctx, seed):
+    # r ~ U[.3, 1.2], eta = .9: strong cancellation
+    O = gen.random_O(16, seed, 0.3, 1.2, 0.9)
+    check(ctx, O, label=f"n=16 eta=.9 seed {seed}")
+
+
+@pytest.mark.parametrize("n", [10, 12, 14])
+def test_generic_hermitian_input(ctx, n):
+    # no Gaussian-state structure: the general complex path
+    O = gen.random_hpd_O(n, 7 + n, 0.05, 0.9)
+    check(ctx, O, label=f"generic HPD n={n}")
+
+
+def test_vacuum_is_exactly_zero(ctx):
+    for n in (4, 9, 17, 30):
+        say(f"case vacuum n={n}")
+        assert ctx.eval(gen.vacuum_O(n)).value == 0.0
+
+
+def test_product_state_n30_closed_form(ctx):
+    rng = np.random.default_rng(30)
+    r = rng.uniform(0.3, 1.2, 30)
+    eta = 0.9
+    O = gen.product_state_O(r, eta, rng.uniform(0, 2 * np.pi, 30))
+    single = np.sqrt(1 + eta * (2 - eta) * np.sinh(r) ** 2)
+    want = float(np.prod(single - 1))
+    sum_abs = float(np.prod(single + 1))
+    say("case product state n=30")
+    res = ctx.eval(O)
+    say(f"  gpu={res.value!r} closed={want!r} ms={res.device_ms:.2f}")
+    assert abs(res.value - want) <= 8 * 30 * U * sum_abs + 1e-12 * abs(want)
+    assert abs(res.sum_abs - sum_abs) <= 1e-9 * sum_abs
+
+
+def test_n30_partials_sampled_against_oracle(ctx):
+    # full-size precision workload: n = 30, r ~ U[.3, 1.2], eta = .9, seed 0
+    O = gen.random_O(30, 0, 0.3, 1.2, 0.9)
+    say("case n=30 partials")
+    k, parts, res = ctx.eval_partials(O, 12)
+    say(f"  k={k} tor={res.value!r} R={res.cancellation:.3e} ms={res.device_ms:.2f}")
+    assert k == 12 and res.status == 0
+    # the partials are the exact pieces of the total
+    hi = 0.0
+    lo = 0.0
+    for h, l_, _ in parts:
+        s = hi + h
+        bb = s - hi
+        e = (hi - (s - bb)) + (h - bb)
+        hi = s
+        lo += e + l_
+    assert abs((hi + lo) - res.value) <= 1e-12 * res.sum_abs
+    rng = np.random.default_rng(1)
+    for root in [0, (1 << k) - 1] + [int(v) for v in rng.integers(1, (1 << k) - 1, 2)]:
+        q = orc.tor(O, mode=orc.F64, fix_mask=(1 << k) - 1, fix_val=root)
+        got = parts[root, 0] + parts[root, 1]
+        bound = term_bound(O, q.sum_abs)
+        say(f"  root {root}: gpu={got!r} oracle={q.value!r} diff={abs(got - q.value):.3e} bound={bound:.3e}")
+        assert q.count == 1 << (30 - k)
+        assert abs(got - q.value) <= bound
+        assert abs(parts[root, 2] - q.sum_abs) <= 1e-12 * q.sum_abs
+
+
+def test_batch_is_bitwise_equal_to_single(ctx):
+    ns = [12, 9, 15, 3, 11, 0, 14]
+    Os = [gen.random_O(n, 200 + i, 0.5, 1.0, 0.3 + 0.1 * i) if n else gen.vacuum_O(0) for i, n in enumerate(ns)]
+    say("case batch vs single")
+    batch = ctx.eval_batch(Os)
+    for O, b in zip(Os, batch):
+        s = ctx.eval(O)
+        assert (b.tor, b.tor_lo, b.status) == (s.tor, s.tor_lo, s.status)
+
+
+def test_repeat_is_bitwise_identical(ctx):
+    O = gen.random_O(18, 5, 0.5, 1.0, 0.7)
+    say("case repeat n=18")
+    a, b = ctx.eval(O), ctx.eval(O)
+    assert (a.tor, a.tor_lo, a.sum_abs) == (b.tor, b.tor_lo, b.sum_abs)
+
+
+@pytest.mark.parametrize("n", [6, 10])
+def test_plain_kernel_against_oracle(ctx, n):
+    O = gen.random_O(n, 300 + n, 0.5, 1.0, 0.7)
+    say(f"case plain n={n}")
+    p = ctx.eval_plain(O)
+    q = orc.tor(O, mode=orc.QUAD)
+    assert p.subsets == 1 << n
+    assert abs(p.value - q.value) <= term_bound(O, q.sum_abs)
+    # a sub-range of masks is a plain restricted sum
+    lo_, hi_ = 5, (1 << n) - 7
+    pr = ctx.eval_plain(O, lo_, hi_)
+    ts = [orc.det(O, Z)[1] for Z in range(lo_, hi_)]
+    assert abs(pr.value - math.fsum(ts)) <= term_bound(O, sum(abs(t) for t in ts))
+
+
+def test_error_codes(ctx):
+    from paper_2109_04528_amd import TorError, TOR_E_INVAL, TOR_E_NOT_PD
+    say("case error codes")
+    O = gen.random_O(6, 1) + 2.0 * np.eye(12)
+    with pytest.raises(TorError) as ei:
+        ctx.eval(O)
+    assert ei.value.code == TOR_E_NOT_PD
+    O = gen.random_O(6, 1)
+    O[3, 1] = np.nan
+    with pytest.raises(TorError) as ei:
+        ctx.eval(O)
+    assert ei.value.code == TOR_E_INVAL
+    with pytest.raises(TorError) as ei:
+        ctx.eval(gen.vacuum_O(41))
+    assert ei.value.code == TOR_E_INVAL
+
+
+def test_fp64_accumulation_mode():
+    from paper_2109_04528_amd import Context
+    O = gen.random_O(16, 0, 0.3, 1.2, 0.9)
+    say("case fp64 accumulation n=16")
+    with Context(device=0, accum="fp64") as c:
+        f = c.eval(O)
+    q = orc.tor(O, mode=orc.QUAD)
+    assert f.tor_lo == 0.0
+    assert abs(f.value - q.value) <= 2 * term_bound(O, q.sum_abs)
+
+
+def test_serving_results_equal_eval(ctx):
+    ns = [8, 13, 10, 16, 9]
+    Os = [gen.random_O(n, 400 + n, 0.5, 1.0, 0.6) for n in ns]
+    say("case serving submit/poll")
+    tickets = [ctx.submit(O) for O in Os]
+    ctx.drain(60000)
+    for O, t in zip(Os, tickets):
+        r = ctx.poll(t)
+        assert r is not None
+        s = ctx.eval(O)
+        assert (r.tor, r.tor_lo) == (s.tor, s.tor_lo)

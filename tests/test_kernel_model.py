@@ -1,0 +1,28 @@
+"""The kernel's work split and sign bookkeeping, modelled in numpy
+(tests/kernel_model.py), reproduces the oracle on small inputs."""
+import numpy as np
+import pytest
+
+from kernel_model import model_tor
+from oracle import oracle as orc
+from paper_2109_04528_amd import inputs as gen
+
+
+@pytest.mark.parametrize("n,k", [(0, 0), (1, 0), (5, 0), (9, 0), (10, 1), (11, 2), (12, 3)])
+def test_model_matches_oracle(n, k):
+    O = gen.random_O(n, 3 + n, 0.5, 1.0, 0.7) if n else gen.vacuum_O(0)
+    v, cnt = model_tor(O, 3, 6, k)
+    q = orc.tor(O, mode=orc.QUAD)
+    assert cnt == 1 << max(n, 9)
+    tol = 64 * 1.1e-16 * max(n, 9) * q.sum_abs
+    assert abs(v - q.value) <= tol, (v, q.value, tol)
+
+
+def test_model_product_state_closed_form():
+    r = np.array([0.6, 0.8, 1.0, 0.7, 0.9, 0.55, 0.65, 0.75, 0.85, 0.95, 0.5])
+    O = gen.product_state_O(r, 0.6, np.arange(11.0))
+    v, _ = model_tor(O, 3, 6, 1)
+    single = np.sqrt(1 + 0.6 * 1.4 * np.sinh(r) ** 2)
+    want = float(np.prod(single - 1))
+    sum_abs = float(np.prod(single + 1))  # sum of |terms| of a product state
+    assert abs(v - want) <= 64 * 1.1e-16 * 11 * sum_abs
