@@ -137,7 +137,8 @@ def main():
     step_s = (t1 - t0) / args.steps
     tor_per_s = 1.0 / step_s
     kernel_ms = float(np.mean(kms))
-    flops = tor_flops(n)
+    real_path = r.path == 1
+    flops = tor_flops(n, real=real_path)
     achieved = flops / (kernel_ms * 1e-3) / 1e12
 
     plain = None
@@ -176,7 +177,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"exact Torontonian, n={n} modes (60x60 complex128 for n=30), r~U[0.3,1.2], "
                                f"Haar U, eta=0.9, seed 0, 2^{n} subsets per step", "n": n,
-                   "subsets_per_step": 1 << n, "path": "recursive, complex FP64 factor, double-double sum"},
+                   "subsets_per_step": 1 << n,
+                   "path": ("recursive, real quadrature form" if real_path else "recursive, complex") +
+                           " FP64 factor, double-double sum"},
         "subset_dets_per_s": (1 << n) * tor_per_s,
         "kernel_ms": kernel_ms,
         "kernel_subset_dets_per_s": (1 << n) / (kernel_ms * 1e-3),
@@ -184,7 +187,8 @@ def main():
         "cancellation_R": r.cancellation,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "flop_per_launch": flops, "kernel": "tor_main (complex, T=3, B=6)"},
+                     "flop_per_launch": flops,
+                     "kernel": "tor_main<double, T=4, B=6>" if real_path else "tor_main<c64, T=3, B=6>"},
         "plain": plain,
         "serving": serve,
         "cpu_baseline": cpu,

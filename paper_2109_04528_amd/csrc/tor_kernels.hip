@@ -613,8 +613,13 @@ __global__ void tor_math_probe(const double *x, double *out, int count)
 // ---------------------------------------------------------------------------
 hipError_t launch_main(bool real_path, bool dd, const MainParams &p, int grid, hipStream_t s)
 {
-    if (real_path)
-        return hipErrorNotSupported;
+    if (real_path) {
+        if (dd)
+            hipLaunchKernelGGL((tor_main<double, REAL_T, REAL_B, AccDD>), dim3(grid), dim3(64), 0, s, p);
+        else
+            hipLaunchKernelGGL((tor_main<double, REAL_T, REAL_B, AccF64>), dim3(grid), dim3(64), 0, s, p);
+        return hipGetLastError();
+    }
     if (dd)
         hipLaunchKernelGGL((tor_main<c64, CPLX_T, CPLX_B, AccDD>), dim3(grid), dim3(64), 0, s, p);
     else
@@ -622,12 +627,17 @@ hipError_t launch_main(bool real_path, bool dd, const MainParams &p, int grid, h
     return hipGetLastError();
 }
 
+template <class S, int T, int B>
+constexpr int lds_bytes()
+{
+    constexpr int R = T + B;
+    return (int)(sizeof(S) * (offB<R>(B) + vec_entries<R, B>()) + sizeof(double) * (1 << (B - 1)) + 2 * E(R - 1) +
+                 (sizeof(double) + sizeof(int)) * (MAX_N + 1));
+}
+
 int main_lds_bytes(bool real_path)
 {
-    constexpr int R = CPLX_R;
-    (void)real_path;
-    return (int)(sizeof(c64) * (offB<R>(CPLX_B) + vec_entries<R, CPLX_B>()) + sizeof(double) * (1 << (CPLX_B - 1)) +
-                 2 * E(R - 1) + (sizeof(double) + sizeof(int)) * (MAX_N + 1));
+    return real_path ? lds_bytes<double, REAL_T, REAL_B>() : lds_bytes<c64, CPLX_T, CPLX_B>();
 }
 
 hipError_t launch_reduce(const ProblemDesc *probs, int nprob, const double *slots, double *results, bool dd,

@@ -39,8 +39,11 @@ constexpr double kU = 1.1102230246251565e-16;  // FP64 unit roundoff
 
 struct Staged {
     int n = 0;        // modes of the input
-    int N = 0;        // modes after padding
+    int N = 0;        // modes after padding (complex path)
     std::vector<c64> packed;
+    bool real = false;            // Gaussian-state structure found: real path
+    int Nr = 0;                   // modes after padding (real path)
+    std::vector<double> packed_r; // real symmetric form, same layout
     int status = TOR_OK;
 };
 
@@ -64,7 +67,8 @@ struct tor_ctx {
     tor_options opt{};
     int num_cu = 0;
     int waves_per_cu = 4;
-    int grid = 0;
+    int grid = 0;    // complex-path persistent grid
+    int grid_r = 0;  // real-path persistent grid
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::mutex mu;  // serialises device work on this context
 
@@ -111,6 +115,59 @@ bool hpd_check(int n2, const std::vector<double> &C)
         }
     }
     return true;
+}
+
+// Gaussian-state structure.  The sampling matrix of a Gaussian state in
+// block order has the form [[P, Q], [conj Q, conj P]] (Sec. 1: A = I - Sigma^-1
+// from the Husimi covariance), and so has C = I - O.  For such C the unitary
+// w = [[1, 1], [-i, i]] / sqrt(2) applied to every mode pair turns each 2x2
+// mode block [[p, q], [conj q, conj p]] into the real block
+// [[Re p + Re q, Im q - Im p], [Im p + Im q, Re p - Re q]]; the result is real
+// symmetric and every principal mode-submatrix keeps its determinant
+// (w is unitary and acts inside each mode), so the Torontonian is unchanged.
+// C is taken as structured when both defining relations hold to 64 units of
+// roundoff of max |C|; it is then symmetrised exactly (P <- (P + conj P')/2,
+// Q <- (Q + Q^T)/2) before the transform.
+void stage_real(int n, const std::vector<double> &C, Staged &st)
+{
+    const int n2 = 2 * n;
+    auto cre = [&](int a, int b) { return C[2 * ((size_t)a * n2 + b)]; };
+    auto cim = [&](int a, int b) { return C[2 * ((size_t)a * n2 + b) + 1]; };
+    double cmax = 0.0, dev = 0.0;
+    for (int a = 0; a < n2; a++)
+        for (int b = 0; b < n2; b++)
+            cmax = std::max(cmax, std::hypot(cre(a, b), cim(a, b)));
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) {
+            // lower-right block = conj(upper-left); lower-left block symmetric
+            dev = std::max(dev, std::hypot(cre(i + n, j + n) - cre(i, j), cim(i + n, j + n) + cim(i, j)));
+            dev = std::max(dev, std::hypot(cre(i + n, j) - cre(j + n, i), cim(i + n, j) - cim(j + n, i)));
+        }
+    if (!(dev <= 64.0 * kU * std::max(cmax, 1.0)))
+        return;
+    const int N = std::max(n, REAL_R);
+    st.Nr = N;
+    st.packed_r.assign((size_t)E(N), 0.0);
+    // real 2x2 block of modes (mi, mj), row component ci, column component cj
+    auto rblk = [&](int mi, int mj, int ci, int cj) -> double {
+        if (mi >= n || mj >= n)
+            return (mi == mj && ci == cj) ? 0.5 : 0.0;
+        const double pr = 0.5 * (cre(mi, mj) + cre(mi + n, mj + n));
+        const double pi = 0.5 * (cim(mi, mj) - cim(mi + n, mj + n));
+        // Q = upper-right block, symmetrised: (Q + Q^T)/2, with Q[i][j] = C[i][j+n]
+        const double qr = 0.5 * (cre(mi, mj + n) + cre(mj, mi + n));
+        const double qi = 0.5 * (cim(mi, mj + n) + cim(mj, mi + n));
+        if (ci == 0 && cj == 0) return pr + qr;
+        if (ci == 0 && cj == 1) return qi - pi;
+        if (ci == 1 && cj == 0) return pi + qi;
+        return pr - qr;
+    };
+    for (int x = 0; x < 2 * N; x++)
+        for (int y = 0; y <= x; y++) {
+            const int qi = 2 * N - 1 - x, qj = 2 * N - 1 - y;
+            st.packed_r[(size_t)pidx(x, y)] = rblk(qi / 2, qj / 2, qi % 2, qj % 2);
+        }
+    st.real = true;
 }
 
 // Validate, check, pack one matrix.  O is host memory.
@@ -171,6 +228,9 @@ int stage_matrix(int n, const double *O, long ld, unsigned flags, int min_modes,
                 v.y = 0.0;
             st.packed[(size_t)pidx(x, y)] = v;
         }
+    st.real = false;
+    if (!(flags & TOR_FORCE_COMPLEX) && n > 0)
+        stage_real(n, C, st);
     return TOR_OK;
 }
 
@@ -183,18 +243,23 @@ struct LaunchPlan {
     size_t bytes_C = 0;
 };
 
-int choose_k(const tor_ctx *ctx, int N, int R, long long total_subsets_log2_hint)
+int path_R(bool real) { return real ? REAL_R : CPLX_R; }
+int path_grid(const tor_ctx *ctx, bool real) { return real ? ctx->grid_r : ctx->grid; }
+int modes_of(const Staged &m, bool real) { return real ? m.Nr : m.N; }
+
+// split depth: about four subtree roots per persistent wave, never deeper than
+// the levels above the last R modes
+int choose_k(const tor_ctx *ctx, int N, bool real)
 {
-    (void)total_subsets_log2_hint;
-    const int LA = N - R;
+    const int LA = N - path_R(real);
     if (LA <= 0)
         return 0;
     if (ctx->opt.split_k > 0)
         return std::min(ctx->opt.split_k, LA);
     int g = 1;
-    while ((1 << g) < ctx->grid)
+    while ((1 << g) < path_grid(ctx, real))
         ++g;
-    return std::min(LA, g + 2);  // ~4 roots per wave
+    return std::min(LA, g + 2);
 }
 
 int ensure_ws(tor_ctx *ctx, size_t bytes)
@@ -218,31 +283,34 @@ int ensure_ws(tor_ctx *ctx, size_t bytes)
     return TOR_OK;
 }
 
-// Run the recursive path over already staged matrices.  results: 4 doubles
-// per matrix (input order).  slots_out (optional) receives the raw slots.
-int run_recursive(tor_ctx *ctx, std::vector<Staged *> &mats, std::vector<int> &ks, std::vector<double> &results,
-                  float *ms, std::vector<double> *slots_out)
+// Run the recursive path over already staged matrices that all take the same
+// path.  results: 4 doubles per matrix (input order).  slots_out (optional)
+// receives the raw slots.
+int run_recursive(tor_ctx *ctx, bool real, std::vector<Staged *> &mats, std::vector<int> &ks,
+                  std::vector<double> &results, float *ms, std::vector<double> *slots_out)
 {
-    const int R = CPLX_R;
+    const int R = path_R(real);
+    const size_t esz = real ? sizeof(double) : sizeof(c64);
+    const int grid = path_grid(ctx, real);
     const int count = (int)mats.size();
     LaunchPlan plan;
     plan.order.resize(count);
     for (int i = 0; i < count; i++)
         plan.order[i] = i;
     std::stable_sort(plan.order.begin(), plan.order.end(),
-                     [&](int a, int b) { return mats[a]->N > mats[b]->N; });
+                     [&](int a, int b) { return modes_of(*mats[a], real) > modes_of(*mats[b], real); });
     size_t off = 0;
     for (int s = 0; s < count; s++) {
         Staged *m = mats[plan.order[s]];
         ProblemDesc d{};
-        d.N = m->N;
+        d.N = modes_of(*m, real);
         d.k = ks[plan.order[s]];
         d.item_begin = plan.total_items;
         plan.total_items += 1ll << d.k;
         plan.c_off.push_back(off);
-        off = align_up(off + sizeof(c64) * (size_t)E(m->N), 256);
+        off = align_up(off + esz * (size_t)E(d.N), 256);
         plan.probs.push_back(d);
-        long long se = Fsum(m->N - 1) - Fsum(R - 1);
+        long long se = Fsum(d.N - 1) - Fsum(R - 1);
         plan.max_scratch_entries = std::max(plan.max_scratch_entries, se);
     }
     plan.bytes_C = off;
@@ -250,8 +318,8 @@ int run_recursive(tor_ctx *ctx, std::vector<Staged *> &mats, std::vector<int> &k
     const size_t b_counter = 256;
     const size_t b_slots = align_up(sizeof(double) * 4 * (size_t)plan.total_items, 256);
     const size_t b_res = align_up(sizeof(double) * 4 * (size_t)count, 256);
-    const long long stride = (long long)align_up(sizeof(c64) * (size_t)std::max(plan.max_scratch_entries, 1ll), 256);
-    const size_t b_scr = (size_t)stride * ctx->grid;
+    const long long stride = (long long)align_up(esz * (size_t)std::max(plan.max_scratch_entries, 1ll), 256);
+    const size_t b_scr = (size_t)stride * grid;
     const size_t total = plan.bytes_C + b_probs + b_counter + b_slots + b_res + b_scr;
     int rc = ensure_ws(ctx, total);
     if (rc != TOR_OK)
@@ -268,7 +336,10 @@ int run_recursive(tor_ctx *ctx, std::vector<Staged *> &mats, std::vector<int> &k
     std::vector<char> hbuf(plan.bytes_C + b_probs, 0);
     for (int s = 0; s < count; s++) {
         Staged *m = mats[plan.order[s]];
-        std::memcpy(hbuf.data() + plan.c_off[s], m->packed.data(), sizeof(c64) * m->packed.size());
+        if (real)
+            std::memcpy(hbuf.data() + plan.c_off[s], m->packed_r.data(), esz * m->packed_r.size());
+        else
+            std::memcpy(hbuf.data() + plan.c_off[s], m->packed.data(), esz * m->packed.size());
         plan.probs[s].C = dC + plan.c_off[s];
     }
     std::memcpy(hbuf.data() + plan.bytes_C, plan.probs.data(), sizeof(ProblemDesc) * count);
@@ -290,7 +361,7 @@ int run_recursive(tor_ctx *ctx, std::vector<Staged *> &mats, std::vector<int> &k
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev0, ctx->stream);
     if (e == hipSuccess)
-        e = launch_main(false, dd, mp, ctx->grid, ctx->stream);
+        e = launch_main(real, dd, mp, grid, ctx->stream);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev1, ctx->stream);  // device_ms: the main kernel alone
     if (e == hipSuccess)
@@ -316,7 +387,7 @@ int run_recursive(tor_ctx *ctx, std::vector<Staged *> &mats, std::vector<int> &k
     return TOR_OK;
 }
 
-void fill_result(const Staged &st, const double *r, float ms, tor_result *out)
+void fill_result(const Staged &st, bool real, const double *r, float ms, tor_result *out)
 {
     std::memset(out, 0, sizeof(*out));
     out->tor = r[0];
@@ -326,10 +397,10 @@ void fill_result(const Staged &st, const double *r, float ms, tor_result *out)
     // each term carries a relative rounding error of a few units of roundoff
     // per factorisation step; independent errors add in quadrature
     const double R = v > 0.0 ? r[2] / v : INFINITY;
-    out->err_est = kU * (double)std::max(st.N, 1) * R / std::sqrt(std::ldexp(1.0, st.n));
+    out->err_est = kU * (double)std::max(st.n, 1) * R / std::sqrt(std::ldexp(1.0, st.n));
     out->subsets = 1ull << st.n;
     out->status = (r[3] != 0.0 || !std::isfinite(r[0])) ? TOR_E_NUMERIC : TOR_OK;
-    out->path = 2;
+    out->path = real ? 1 : 2;
     out->device_ms = ms;
 }
 
@@ -348,12 +419,47 @@ int copy_input_to_host(int n, const double *O, long ld, unsigned flags, std::vec
     return TOR_OK;
 }
 
+// Launch the staged matrices, one launch per arithmetic path.  done[j] and
+// out[idx[j]] are filled for every staged matrix.
+int run_staged(tor_ctx *ctx, std::vector<Staged *> &mats, const std::vector<int> &idx, int fixed_k,
+               tor_result *out, std::vector<double> *slots_out, int *k_out)
+{
+    int first_err = TOR_OK;
+    for (int pass = 0; pass < 2; pass++) {
+        const bool real = pass == 0;
+        std::vector<Staged *> grp;
+        std::vector<int> gidx, ks;
+        for (size_t j = 0; j < mats.size(); j++)
+            if (mats[j]->real == real) {
+                grp.push_back(mats[j]);
+                gidx.push_back(idx[j]);
+                const int N = modes_of(*mats[j], real);
+                ks.push_back(fixed_k >= 0 ? std::min(fixed_k, std::max(N - path_R(real), 0)) : choose_k(ctx, N, real));
+            }
+        if (grp.empty())
+            continue;
+        std::vector<double> res;
+        float ms = 0.f;
+        int rc = run_recursive(ctx, real, grp, ks, res, &ms, slots_out);
+        if (rc != TOR_OK)
+            return rc;
+        for (size_t j = 0; j < grp.size(); j++) {
+            fill_result(*grp[j], real, &res[4 * j], ms, &out[gidx[j]]);
+            if (out[gidx[j]].status != TOR_OK && first_err == TOR_OK)
+                first_err = out[gidx[j]].status;
+        }
+        if (k_out)
+            *k_out = ks[0];
+    }
+    return first_err;
+}
+
 int eval_many(tor_ctx *ctx, int count, const int *n, const double *const *O, const long *ld, tor_result *out,
               int fixed_k, std::vector<double> *slots_out, int *k_out)
 {
     std::vector<Staged> st(count);
     std::vector<Staged *> ok;
-    std::vector<int> idx, ks;
+    std::vector<int> idx;
     int first_err = TOR_OK;
     for (int i = 0; i < count; i++) {
         if (n[i] > ctx->opt.max_n) {
@@ -377,22 +483,11 @@ int eval_many(tor_ctx *ctx, int count, const int *n, const double *const *O, con
         }
         ok.push_back(&st[i]);
         idx.push_back(i);
-        int k = fixed_k >= 0 ? std::min(fixed_k, std::max(st[i].N - CPLX_R, 0)) : choose_k(ctx, st[i].N, CPLX_R, 0);
-        ks.push_back(k);
     }
     if (!ok.empty()) {
-        std::vector<double> res;
-        float ms = 0.f;
-        int rc = run_recursive(ctx, ok, ks, res, &ms, slots_out);
-        if (rc != TOR_OK)
-            return rc;
-        for (size_t j = 0; j < ok.size(); j++) {
-            fill_result(*ok[j], &res[4 * j], ms, &out[idx[j]]);
-            if (out[idx[j]].status != TOR_OK && first_err == TOR_OK)
-                first_err = out[idx[j]].status;
-        }
-        if (k_out)
-            *k_out = ks[0];
+        int rc = run_staged(ctx, ok, idx, fixed_k, out, slots_out, k_out);
+        if (rc != TOR_OK && first_err == TOR_OK)
+            first_err = rc;
     }
     return first_err;
 }
@@ -474,12 +569,16 @@ int tor_create(tor_ctx **out, const tor_options *opt)
         return TOR_E_DEVICE;
     }
     ctx->num_cu = prop.multiProcessorCount;
-    const int lds = main_lds_bytes(false);
-    int fit = (int)(prop.maxSharedMemoryPerMultiProcessor / (size_t)std::max(lds, 1));
-    if (fit <= 0)
-        fit = 1;
-    ctx->waves_per_cu = o.waves_per_cu > 0 ? o.waves_per_cu : std::min(fit, 8);
-    ctx->grid = ctx->num_cu * ctx->waves_per_cu;
+    // persistent grid: as many one-wave workgroups per CU as the LDS allows
+    for (int real = 0; real < 2; real++) {
+        const int lds = main_lds_bytes(real != 0);
+        int fit = (int)(prop.maxSharedMemoryPerMultiProcessor / (size_t)std::max(lds, 1));
+        fit = std::max(1, std::min(fit, 8));
+        const int w = o.waves_per_cu > 0 ? o.waves_per_cu : fit;
+        (real ? ctx->grid_r : ctx->grid) = ctx->num_cu * w;
+        if (!real)
+            ctx->waves_per_cu = w;
+    }
     if (o.stream) {
         ctx->stream = (hipStream_t)o.stream;
     } else {
@@ -640,7 +739,7 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long 
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
     st.N = n;
-    fill_result(st, h, ms, out);
+    fill_result(st, false, h, ms, out);
     out->subsets = mask_end - mask_begin;
     return out->status;
 }
@@ -754,24 +853,23 @@ void serve_loop(tor_ctx *ctx)
             ctx->inflight += (int)batch.size();
         }
         std::vector<Staged *> mats;
-        std::vector<int> ks;
-        for (Request *r : batch) {
-            mats.push_back(&r->st);
-            ks.push_back(choose_k(ctx, r->st.N, CPLX_R, 0));
+        std::vector<int> idx;
+        std::vector<tor_result> res(batch.size());
+        for (size_t i = 0; i < batch.size(); i++) {
+            mats.push_back(&batch[i]->st);
+            idx.push_back((int)i);
         }
-        std::vector<double> res;
-        float ms = 0.f;
         int rc;
         {
             std::lock_guard<std::mutex> g(ctx->mu);
-            rc = run_recursive(ctx, mats, ks, res, &ms, nullptr);
+            rc = run_staged(ctx, mats, idx, -1, res.data(), nullptr, nullptr);
         }
         {
             std::lock_guard<std::mutex> g(ctx->smu);
             for (size_t i = 0; i < batch.size(); i++) {
                 Request *r = batch[i];
-                if (rc == TOR_OK) {
-                    fill_result(r->st, &res[4 * i], ms, &r->res);
+                if (rc == TOR_OK || rc == TOR_E_NUMERIC) {
+                    r->res = res[i];
                 } else {
                     r->res = tor_result{};
                     r->res.status = rc;

@@ -45,6 +45,32 @@ def pack(O: np.ndarray, min_modes: int):
     return out, N
 
 
+def pack_real(O: np.ndarray, min_modes: int):
+    """Real form of a Gaussian-state matrix: each mode block of I - O,
+    [[p, q], [conj q, conj p]], conjugated by w = [[1, 1], [-i, i]]/sqrt(2),
+    becomes [[Re p + Re q, Im q - Im p], [Im p + Im q, Re p - Re q]]."""
+    n = O.shape[0] // 2
+    C = np.eye(2 * n, dtype=np.complex128) - O
+    C = np.tril(C) + np.tril(C, -1).conj().T
+    w = np.array([[1, 1], [-1j, 1j]]) / np.sqrt(2)
+    N = max(n, min_modes)
+    M = np.zeros((2 * N, 2 * N))
+    for i in range(N):
+        for j in range(N):
+            if i < n and j < n:
+                blk = np.array([[C[i, j], C[i, j + n]], [C[i + n, j], C[i + n, j + n]]])
+                r = w @ blk @ w.conj().T
+                assert abs(r.imag).max() < 1e-12
+                M[2 * i:2 * i + 2, 2 * j:2 * j + 2] = r.real
+            elif i == j:
+                M[2 * i:2 * i + 2, 2 * j:2 * j + 2] = 0.5 * np.eye(2)
+    out = np.zeros(E(N))
+    for x in range(2 * N):
+        for y in range(x + 1):
+            out[pidx(x, y)] = M[2 * N - 1 - x, 2 * N - 1 - y]
+    return out, N
+
+
 def eliminate(src: np.ndarray, s: int):
     """Include the next mode of an s-mode view: returns (s-1)-mode node, pivot det."""
     p = 2 * s - 2
@@ -58,7 +84,7 @@ def eliminate(src: np.ndarray, s: int):
     r1 = np.array([src[pidx(p, y)] for y in range(p)])
     r2 = np.array([src[pidx(p + 1, y)] for y in range(p)]) - r1 * ba
     u1, u2 = r1 * inv_a, r2 * inv_g
-    dst = np.zeros(E(s - 1), dtype=np.complex128)
+    dst = np.zeros(E(s - 1), dtype=src.dtype)
     for x in range(p):
         for y in range(x + 1):
             v = src[pidx(x, y)] - np.conj(u1[x]) * r1[y] - np.conj(u2[x]) * r2[y]
@@ -75,9 +101,9 @@ def tail(h, M, det, sgn, terms):
     tail(hn, M - 1, det * pd, sgn, terms)
 
 
-def model_tor(O: np.ndarray, T: int = 3, B: int = 6, k: int = 0):
+def model_tor(O: np.ndarray, T: int = 3, B: int = 6, k: int = 0, real: bool = False):
     R = T + B
-    C, N = pack(O, R)
+    C, N = pack_real(O, R) if real else pack(O, R)
     LA = N - R
     k = min(k, LA)
     D = LA - k
@@ -134,7 +160,7 @@ def model_tor(O: np.ndarray, T: int = 3, B: int = 6, k: int = 0):
                 if inc:
                     hT, pd = eliminate(h, T + 1)
                 else:
-                    hT, pd = h[: E(T)], 1.0
+                    hT, pd = h[: E(T)].copy(), 1.0
                 includes = linc + bin(ip).count("1") + inc
                 excluded = (N - T) - includes
                 tail(hT, T, sdet_ * pd, -1.0 if excluded & 1 else 1.0, terms)

@@ -232,3 +232,32 @@ def test_serving_results_equal_eval(ctx):
         assert r is not None
         s = ctx.eval(O)
         assert (r.tor, r.tor_lo) == (s.tor, s.tor_lo)
+
+
+def test_path_choice_and_real_vs_complex(ctx):
+    from paper_2109_04528_amd import Context, TOR_FORCE_COMPLEX
+    O = gen.random_O(14, 9, 0.3, 1.2, 0.9)
+    G = gen.random_hpd_O(11, 3)
+    say("case path choice n=14 / generic n=11")
+    r_real = ctx.eval(O)
+    assert r_real.path == 1
+    assert ctx.eval(G).path == 2
+    with Context(device=0, flags=TOR_FORCE_COMPLEX) as c:
+        r_cplx = c.eval(O)
+    assert r_cplx.path == 2
+    q = orc.tor(O, mode=orc.QUAD)
+    b = term_bound(O, q.sum_abs)
+    assert abs(r_real.value - q.value) <= b
+    assert abs(r_cplx.value - q.value) <= b
+    say(f"  real={r_real.value!r} complex={r_cplx.value!r} quad={q.value!r}")
+
+
+def test_click_submatrices_of_a_40_mode_state(ctx):
+    # serving workload inputs: principal submatrices O_S of an M = 40 state
+    big = gen.random_O(40, 5000, 0.5, 1.0, 0.6)
+    rng = np.random.default_rng(11)
+    for n in (8, 12, 15):
+        S = sorted(rng.choice(40, size=n, replace=False).tolist())
+        O = gen.click_submatrix(big, S)
+        r, q = check(ctx, O, label=f"click pattern n={n}")
+        assert r.path == 1
