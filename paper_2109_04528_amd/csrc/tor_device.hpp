@@ -41,6 +41,10 @@ __device__ __forceinline__ c64 sub_mul(c64 a, c64 b, c64 c)
 {
     return c64{fma(b.y, c.y, fma(-b.x, c.x, a.x)), fma(-b.y, c.x, fma(-b.x, c.y, a.y))};
 }
+__device__ __forceinline__ double conj_of(double a) { return a; }
+__device__ __forceinline__ c64 conj_of(c64 a) { return c64{a.x, -a.y}; }
+__device__ __forceinline__ double fix_diag(double a) { return a; }
+__device__ __forceinline__ c64 fix_diag(c64 a) { return c64{a.x, 0.0}; }
 // h - conj(u1) r1 - conj(u2) r2   (one entry of the rank-2 update)
 __device__ __forceinline__ double upd(double h, double u1, double r1, double u2, double r2)
 {

@@ -11,7 +11,18 @@ struct __align__(16) c64 {
     double x, y;  // re, im
 };
 
-__host__ __device__ constexpr int E(int s) { return s * (2 * s + 1); }  // packed entries, s modes
+// Device layout of a node of s modes: the Hermitian (or real symmetric)
+// 2s x 2s matrix in mode-interleaved rows, REVERSED (the next mode to decide
+// owns the two highest rows), stored as its lower-triangular 2x2 mode blocks
+// (a, b), a >= b, at block index a(a+1)/2 + b; each block holds its 4 entries
+// [(2a,2b), (2a,2b+1), (2a+1,2b), (2a+1,2b+1)] (a diagonal block keeps its
+// upper entry as the conjugate of the lower one).  Dropping the highest mode
+// leaves a prefix of the array.
+__host__ __device__ constexpr int NB(int s) { return s * (s + 1) / 2; }        // blocks
+__host__ __device__ constexpr int NSZ(int s) { return 2 * s * (s + 1); }       // scalars
+__host__ __device__ constexpr int bidx(int a, int b) { return a * (a + 1) / 2 + b; }
+// packed lower triangle (registers of the per-lane tail): entry (x, y), y <= x
+__host__ __device__ constexpr int E(int s) { return s * (2 * s + 1); }
 __host__ __device__ constexpr int pidx(int x, int y) { return x * (x + 1) / 2 + y; }
 
 // One matrix in a launch.
@@ -41,10 +52,10 @@ struct PlainParams {
     int chunk;                    // subsets per queue pop
 };
 
-// sum_{i=1..s} i(2i+1): packed entries of all node sizes 1..s
-__host__ __device__ constexpr long long Fsum(long long s) { return s * (s + 1) * (4 * s + 5) / 6; }
-// entry offset of Tier-A stack slot l (covers modes [l, N)), slots 1..N-R
-__host__ __device__ constexpr long long slot_off(int N, int l) { return Fsum(N - 1) - Fsum(N - l); }
+// sum_{i=1..s} 2i(i+1): scalars of all node sizes 1..s
+__host__ __device__ constexpr long long Gsum(long long s) { return 2 * s * (s + 1) * (s + 2) / 3; }
+// scalar offset of tier-A stack slot l (covers modes [l, N)), slots 1..N-R
+__host__ __device__ constexpr long long slot_off(int N, int l) { return Gsum(N - 1) - Gsum(N - l); }
 
 // kernel configurations (modes handled per lane, levels expanded in LDS)
 constexpr int CPLX_T = 3;

@@ -40,168 +40,183 @@ namespace tor {
 
 // ---------------------------------------------------------------------------
 // LDS layout of tier B: node 0 (the tier-A leaf, R modes), then for each level
-// j = 1..B-1 the 2^(j-1) include nodes of R-j modes.
+// j = 1..B-1 the 2^(j-1) include nodes of R-j modes (block layout).
 template <int R>
 __host__ __device__ constexpr int offB(int j)
 {
-    int o = E(R);
+    int o = NSZ(R);
     for (int jj = 1; jj < j; ++jj)
-        o += (1 << (jj - 1)) * E(R - jj);
+        o += (1 << (jj - 1)) * NSZ(R - jj);
     return o;
 }
 
-template <int R, int B>
-__host__ __device__ constexpr int vec_entries()
+// 2x2 pivot of the highest mode m of a node, and the update of one output
+// block (a, b), a >= b, m > a:
+//   H'[x][y] = H[x][y] - conj(r1[x]) r1[y] / alpha - conj(r2'[x]) r2'[y] / gamma1
+// with r1 = row 2m, r2' = row 2m+1 - r1 beta/alpha (the LDL form of the 2x2
+// pivot); rows 2a, 2a+1 read r1, r2 from block (m, a), columns from (m, b).
+template <class S>
+__device__ __forceinline__ Piv<S> node_pivot(const S *node, int m)
 {
-    int m = 4 * 2 * (MAX_N - 1);  // tier-A elimination of the largest node
-    for (int j = 1; j < B; ++j) {
-        int v = (1 << (j - 1)) * 4 * (2 * (R - j));
-        if (v > m)
-            m = v;
-    }
-    return m;
-}
-
-// The node of level jl with id i (bit jl-1-m of i = decision on mode m, 1 =
-// include) is a prefix view of the deepest include node on its path.
-template <class S, int R>
-__device__ __forceinline__ void node_src(int jl, int i, S *bufB, const double *ndet, double leafDet,
-                                         const S *&src, double &det)
-{
-    if (i == 0) {
-        src = bufB;
-        det = leafDet;
-        return;
-    }
-    int t = __builtin_ctz(i);
-    int lev = jl - t;
-    int idx = (i >> t) >> 1;
-    int off = E(R);
-    // offB(lev) at run time (lev <= B-1, small loop)
-    for (int jj = 1; jj < lev; ++jj)
-        off += (1 << (jj - 1)) * E(R - jj);
-    src = bufB + off + idx * E(R - lev);
-    det = ndet[(1 << (lev - 1)) - 1 + idx];
+    const S *P = node + 4 * bidx(m, m);
+    return pivot(re(P[0]), P[2], re(P[3]));
 }
 
 template <class S>
-__device__ __forceinline__ S fix_diag(S v, bool d);
-template <>
-__device__ __forceinline__ double fix_diag<double>(double v, bool) { return v; }
-template <>
-__device__ __forceinline__ c64 fix_diag<c64>(c64 v, bool d) { return c64{v.x, d ? 0.0 : v.y}; }
+__device__ __forceinline__ void elim_block(const S *node, int m, int a, int b, const Piv<S> &pv, S *o)
+{
+    const S *pa = node + 4 * bidx(m, a);
+    const S *pb = node + 4 * bidx(m, b);
+    const S *hb = node + 4 * bidx(a, b);
+    const S ra0 = pa[0], ra1 = pa[1];
+    const S qa0 = sub_mul(pa[2], ra0, pv.ba), qa1 = sub_mul(pa[3], ra1, pv.ba);
+    const S rb0 = pb[0], rb1 = pb[1];
+    const S qb0 = sub_mul(pb[2], rb0, pv.ba), qb1 = sub_mul(pb[3], rb1, pv.ba);
+    const S ua0 = scale(ra0, pv.inv_a), ua1 = scale(ra1, pv.inv_a);
+    const S va0 = scale(qa0, pv.inv_g), va1 = scale(qa1, pv.inv_g);
+    o[0] = upd(hb[0], ua0, rb0, va0, qb0);
+    o[1] = upd(hb[1], ua0, rb1, va0, qb1);
+    o[2] = upd(hb[2], ua1, rb0, va1, qb0);
+    o[3] = upd(hb[3], ua1, rb1, va1, qb1);
+    if (a == b) {  // diagonal block: real diagonal, conjugate upper entry
+        o[0] = fix_diag(o[0]);
+        o[3] = fix_diag(o[3]);
+        o[1] = conj_of(o[2]);
+    }
+}
+
+// block index -> (a, b)
+__device__ __forceinline__ void block_ab(int bi, int &a, int &b)
+{
+    a = (int)((sqrtf(8.0f * (float)bi + 1.0f) - 1.0f) * 0.5f);
+    if (a * (a + 1) / 2 > bi)
+        --a;
+    if ((a + 1) * (a + 2) / 2 <= bi)
+        ++a;
+    b = bi - a * (a + 1) / 2;
+}
 
 // ---------------------------------------------------------------------------
-// one include step on global memory (tier A and root set-up): src is a view
-// of s modes (2s rows), dst receives the Schur complement of s-1 modes.
+// one include step on global memory (tier A and the root path): src is a view
+// of s modes, dst receives the Schur complement of s-1 modes.  Every lane
+// forms the pivot itself; lane l updates blocks l, l+64, ...
 template <class S>
-__device__ void elim_global(const S *__restrict__ src, S *__restrict__ dst, int s, S *vec, int lane,
-                            double &pdet, int &bad)
+__device__ void elim_global(const S *__restrict__ src, S *__restrict__ dst, int s, int lane, double &pdet,
+                            int &bad)
 {
-    const int p = 2 * s - 2;
-    const double a = re(src[pidx(p, p)]);
-    const S b = src[pidx(p + 1, p)];
-    const double g = re(src[pidx(p + 1, p + 1)]);
-    Piv<S> pv = pivot(a, b, g);
+    const int m = s - 1;
+    const Piv<S> pv = node_pivot(src, m);
     pdet = pv.pdet;
-    if (!(a > 0.0) || !(pv.pdet > 0.0))
+    if (!(pv.pdet > 0.0) || !(pv.inv_a > 0.0))
         bad = 1;
-    for (int y = lane; y < p; y += 64) {
-        S r1 = src[pidx(p, y)];
-        S r2 = sub_mul(src[pidx(p + 1, y)], r1, pv.ba);
-        vec[y] = scale(r1, pv.inv_a);
-        vec[p + y] = r1;
-        vec[2 * p + y] = scale(r2, pv.inv_g);
-        vec[3 * p + y] = r2;
+    const int nbo = NB(m);
+    for (int bi = lane; bi < nbo; bi += 64) {
+        int a, b;
+        block_ab(bi, a, b);
+        S o[4];
+        elim_block(src, m, a, b, pv, o);
+        S *d = dst + 4 * bi;
+        d[0] = o[0];
+        d[1] = o[1];
+        d[2] = o[2];
+        d[3] = o[3];
     }
     __syncthreads();
-    const int eo = p * (p + 1) / 2;
-    int x = 0, y = lane;
-    while (y > x) {
-        y -= x + 1;
-        ++x;
-    }
-    for (int e = lane; e < eo; e += 64) {
-        S h = src[e];
-        S v = upd(h, vec[x], vec[p + y], vec[2 * p + x], vec[3 * p + y]);
-        dst[e] = fix_diag(v, x == y);
-        y += 64;
-        while (y > x) {
-            y -= x + 1;
-            ++x;
+}
+
+// ---------------------------------------------------------------------------
+// tier B tables, built once per wave: for the node of level jl with id i
+// (bit jl-1-m of i = decision on the m-th mode below the tier-A leaf, 1 =
+// include; stored at (2^jl - 1) + i) the LDS offset of the include node it
+// is a prefix view of, and the slot of that node's determinant (0xff: the
+// tier-A leaf).  The include node (lev, idx) keeps its determinant at
+// (2^(lev-1) - 1) + idx.
+template <int R, int B>
+__device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcDet, uint16_t *blkAB, int lane)
+{
+    for (int t = lane; t < (1 << B) - 1; t += 64) {
+        int jl = 31 - __clz(t + 1);
+        int i = t + 1 - (1 << jl);
+        if (i == 0) {
+            srcOff[t] = 0;
+            srcDet[t] = 0xff;
+        } else {
+            int tz = __builtin_ctz(i);
+            int lev = jl - tz;
+            int idx = (i >> tz) >> 1;
+            int off = NSZ(R);
+            for (int jj = 1; jj < lev; ++jj)
+                off += (1 << (jj - 1)) * NSZ(R - jj);
+            srcOff[t] = (uint16_t)(off + idx * NSZ(R - lev));
+            srcDet[t] = (uint8_t)((1 << (lev - 1)) - 1 + idx);
         }
     }
-    __syncthreads();
+    for (int bi = lane; bi < NB(R - 1); bi += 64) {
+        int a, b;
+        block_ab(bi, a, b);
+        blkAB[bi] = (uint16_t)(a | (b << 8));
+    }
 }
 
-// ---------------------------------------------------------------------------
 // tier B, level J: every include node of level J from its parent of level J-1
 template <class S, int R, int J>
-__device__ __forceinline__ void tierB_level(S *bufB, S *vec, double *ndet, const uint16_t *tab,
-                                            double leafDet, int lane, int &bad)
+__device__ __forceinline__ void tierB_level(S *bufB, double *nInv, S *nBa, double *ndet, const uint16_t *srcOff,
+                                            const uint8_t *srcDet, const uint16_t *blkAB, double leafDet, int lane,
+                                            int &bad)
 {
-    constexpr int sp = R - (J - 1);  // modes of the parent view
-    constexpr int pv = 2 * sp - 2;   // first pivot row; rows of the child
-    constexpr int NN = 1 << (J - 1); // include nodes at level J
-    constexpr int EO = E(sp - 1);
+    constexpr int m = R - J;          // pivot mode of the parent (it has m+1 modes)
+    constexpr int NN = 1 << (J - 1);  // include nodes at level J
+    constexpr int NBO = NB(m);        // blocks of a child
     constexpr int OUT = offB<R>(J);
-#pragma unroll
-    for (int it0 = 0; it0 < NN * pv; it0 += 64) {
-        int it = it0 + lane;
-        if (it < NN * pv) {
-            int i = it / pv, y = it - i * pv;
-            const S *par;
-            double pdp;
-            node_src<S, R>(J - 1, i, bufB, ndet, leafDet, par, pdp);
-            double a = re(par[pidx(pv, pv)]);
-            S b = par[pidx(pv + 1, pv)];
-            double g = re(par[pidx(pv + 1, pv + 1)]);
-            Piv<S> pq = pivot(a, b, g);
-            S r1 = par[pidx(pv, y)];
-            S r2 = sub_mul(par[pidx(pv + 1, y)], r1, pq.ba);
-            S *v = vec + i * 4 * pv;
-            v[y] = scale(r1, pq.inv_a);
-            v[pv + y] = r1;
-            v[2 * pv + y] = scale(r2, pq.inv_g);
-            v[3 * pv + y] = r2;
-            if (y == 0) {
-                ndet[NN - 1 + i] = pdp * pq.pdet;
-                if (!(a > 0.0) || !(pq.pdet > 0.0))
-                    bad = 1;
-            }
-        }
+    if (lane < NN) {
+        const S *par = bufB + srcOff[NN - 1 + lane];
+        const int di = srcDet[NN - 1 + lane];
+        const double pdp = di == 0xff ? leafDet : ndet[di];
+        const Piv<S> pq = node_pivot(par, m);
+        nInv[2 * lane] = pq.inv_a;
+        nInv[2 * lane + 1] = pq.inv_g;
+        nBa[lane] = pq.ba;
+        ndet[NN - 1 + lane] = pdp * pq.pdet;
+        if (!(pq.pdet > 0.0) || !(pq.inv_a > 0.0))
+            bad = 1;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int it0 = 0; it0 < NN * EO; it0 += 64) {
-        int it = it0 + lane;
-        if (it < NN * EO) {
-            int i = it / EO, e = it - i * EO;
-            int xy = tab[e];
-            int x = xy & 0xff, y = xy >> 8;
-            const S *par;
-            double pdp;
-            node_src<S, R>(J - 1, i, bufB, ndet, leafDet, par, pdp);
-            const S *v = vec + i * 4 * pv;
-            S o = upd(par[e], v[x], v[pv + y], v[2 * pv + x], v[3 * pv + y]);
-            bufB[OUT + i * EO + e] = fix_diag(o, x == y);
+#pragma unroll 2
+    for (int it0 = 0; it0 < NN * NBO; it0 += 64) {
+        const int it = it0 + lane;
+        if (it < NN * NBO) {
+            const int i = it / NBO, bi = it - i * NBO;
+            const int ab = blkAB[bi];
+            const S *par = bufB + srcOff[NN - 1 + i];
+            Piv<S> pq;
+            pq.inv_a = nInv[2 * i];
+            pq.inv_g = nInv[2 * i + 1];
+            pq.ba = nBa[i];
+            S o[4];
+            elim_block(par, m, ab & 0xff, ab >> 8, pq, o);
+            S *d = bufB + OUT + i * NSZ(m) + 4 * bi;
+            d[0] = o[0];
+            d[1] = o[1];
+            d[2] = o[2];
+            d[3] = o[3];
         }
     }
     __syncthreads();
 }
 
 template <class S, int R, int J, int B>
-__device__ __forceinline__ void tierB(S *bufB, S *vec, double *ndet, const uint16_t *tab, double leafDet,
-                                      int lane, int &bad)
+__device__ __forceinline__ void tierB(S *bufB, double *nInv, S *nBa, double *ndet, const uint16_t *srcOff,
+                                      const uint8_t *srcDet, const uint16_t *blkAB, double leafDet, int lane, int &bad)
 {
     if constexpr (J < B) {
-        tierB_level<S, R, J>(bufB, vec, ndet, tab, leafDet, lane, bad);
-        tierB<S, R, J + 1, B>(bufB, vec, ndet, tab, leafDet, lane, bad);
+        tierB_level<S, R, J>(bufB, nInv, nBa, ndet, srcOff, srcDet, blkAB, leafDet, lane, bad);
+        tierB<S, R, J + 1, B>(bufB, nInv, nBa, ndet, srcOff, srcDet, blkAB, leafDet, lane, bad);
     }
 }
 
 // ---------------------------------------------------------------------------
-// register-resident include step: h has M modes, hn receives M-1 modes
+// register-resident include step (packed lower triangle): h has M modes, hn
+// receives M-1 modes
 template <class S, int M>
 __device__ __forceinline__ void elim_regs(const S *h, const Piv<S> &pq, S *hn)
 {
@@ -239,12 +254,12 @@ __device__ __forceinline__ void tail(const S *h, double det, double sgn, Acc &ac
         const S b = h[pidx(p + 1, p)];
         const double g = re(h[pidx(p + 1, p + 1)]);
         if constexpr (M == 1) {
-            double pd = fma(a, g, -abs2(b));  // det of the last 2x2 block
+            const double pd = fma(a, g, -abs2(b));  // det of the last 2x2 block
             if (!(a > 0.0) || !(pd > 0.0))
                 bad = 1;
             acc.add(sgn * rsqrt_nr(det * pd));
         } else {
-            Piv<S> pq = pivot(a, b, g);
+            const Piv<S> pq = pivot(a, b, g);
             if (!(a > 0.0) || !(pq.pdet > 0.0))
                 bad = 1;
             S hn[E(M - 1)];
@@ -254,20 +269,24 @@ __device__ __forceinline__ void tail(const S *h, double det, double sgn, Acc &ac
     }
 }
 
-// tier C: lane l finishes node l of level B
+// tier C: lane l finishes node l of level B from its parent of level B-1
 template <class S, int T, int B, class Acc>
-__device__ __forceinline__ void tierC(S *bufB, const double *ndet, double leafDet, int leafInc, int N,
-                                      int lane, Acc &acc, int &bad)
+__device__ __forceinline__ void tierC(const S *bufB, const double *ndet, const uint16_t *srcOff,
+                                      const uint8_t *srcDet, double leafDet, int leafInc, int N, int lane, Acc &acc,
+                                      int &bad)
 {
-    constexpr int R = T + B;
-    const int ip = lane >> 1;  // parent: node of level B-1
-    const S *src;
-    double sdet;
-    node_src<S, R>(B - 1, ip, bufB, ndet, leafDet, src, sdet);
+    constexpr int NP = (1 << (B - 1)) - 1;  // table base of level B-1
+    const int ip = lane >> 1;
+    const S *src = bufB + srcOff[NP + ip];
+    const int di = srcDet[NP + ip];
+    const double sdet = di == 0xff ? leafDet : ndet[di];
+    // block layout -> packed lower triangle in registers (T+1 modes)
     S h[E(T + 1)];
 #pragma unroll
-    for (int e = 0; e < E(T + 1); ++e)
-        h[e] = src[e];
+    for (int x = 0; x < 2 * (T + 1); ++x)
+#pragma unroll
+        for (int y = 0; y <= x; ++y)
+            h[pidx(x, y)] = src[4 * bidx(x >> 1, y >> 1) + ((x & 1) << 1) + (y & 1)];
     constexpr int p = 2 * T;
     const double a = re(h[pidx(p, p)]);
     const S b = h[pidx(p + 1, p)];
@@ -295,22 +314,19 @@ template <class S, int T, int B, class Acc>
 __global__ void __launch_bounds__(64) tor_main(MainParams prm)
 {
     constexpr int R = T + B;
+    constexpr int NN_MAX = 1 << (B - 2);  // include nodes of the last LDS level
     __shared__ S bufB[offB<R>(B)];
-    __shared__ S vec[vec_entries<R, B>()];
+    __shared__ S nBa[NN_MAX];
+    __shared__ double nInv[2 * NN_MAX];
     __shared__ double ndet[1 << (B - 1)];
-    __shared__ uint16_t tab[E(R - 1)];
+    __shared__ uint16_t srcOff[(1 << B) - 1];
+    __shared__ uint8_t srcDet[(1 << B) - 1];
+    __shared__ uint16_t blkAB[NB(R - 1)];
     __shared__ double sdet[MAX_N + 1];
     __shared__ int sinc[MAX_N + 1];
 
     const int lane = threadIdx.x;
-    for (int e = lane; e < E(R - 1); e += 64) {
-        int x = 0, y = e;
-        while (y > x) {
-            y -= x + 1;
-            ++x;
-        }
-        tab[e] = (uint16_t)(x | (y << 8));
-    }
+    build_tables<R, B>(srcOff, srcDet, blkAB, lane);
     __syncthreads();
     S *wscr = reinterpret_cast<S *>(prm.scratch + (long long)blockIdx.x * prm.scratch_stride);
 
@@ -343,7 +359,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
             if ((root >> l) & 1) {
                 S *dst = wscr + slot_off(N, l + 1);
                 double pd;
-                elim_global<S>(rsrc, dst, N - l, vec, lane, pd, bad);
+                elim_global<S>(rsrc, dst, N - l, lane, pd, bad);
                 rdet *= pd;
                 ++rinc;
                 rsrc = dst;
@@ -381,7 +397,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                 }
                 S *dst = wscr + slot_off(N, lvl + 1);
                 double pd;
-                elim_global<S>(s, dst, N - lvl, vec, lane, pd, bad);
+                elim_global<S>(s, dst, N - lvl, lane, pd, bad);
                 lsrc = dst;
                 ldet = sd * pd;
                 linc = si + 1;
@@ -390,16 +406,16 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                     sinc[lvl + 1] = linc;
                 }
             }
-            for (int e = lane; e < E(R); e += 64)
+            for (int e = lane; e < NSZ(R); e += 64)
                 bufB[e] = lsrc[e];
             __syncthreads();
-            tierB<S, R, 1, B>(bufB, vec, ndet, tab, ldet, lane, bad);
-            tierC<S, T, B, Acc>(bufB, ndet, ldet, linc, N, lane, acc, bad);
+            tierB<S, R, 1, B>(bufB, nInv, nBa, ndet, srcOff, srcDet, blkAB, ldet, lane, bad);
+            tierC<S, T, B, Acc>(bufB, ndet, srcOff, srcDet, ldet, linc, N, lane, acc, bad);
             __syncthreads();
         }
 
         double h = acc.hi, l = acc.lo, ab = acc.abs_sum;
-        constexpr bool is_dd = sizeof(Acc) == sizeof(AccDD) && std::is_same<Acc, AccDD>::value;
+        constexpr bool is_dd = std::is_same<Acc, AccDD>::value;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             double oh = __shfl_xor(h, off), ol = __shfl_xor(l, off), oa = __shfl_xor(ab, off);
@@ -512,7 +528,8 @@ __global__ void __launch_bounds__(64) tor_plain(PlainParams prm)
                     ++x;
                 }
                 for (int e = lane; e < ed; e += 64) {
-                    A[e] = C[pidx(rows[x], rows[y])];
+                    const int gx = rows[x], gy = rows[y];  // gx >= gy
+                    A[e] = C[4 * bidx(gx >> 1, gy >> 1) + ((gx & 1) << 1) + (gy & 1)];
                     y += 64;
                     while (y > x) {
                         y -= x + 1;
@@ -550,7 +567,7 @@ __global__ void __launch_bounds__(64) tor_plain(PlainParams prm)
                 }
                 for (int e = lane; e < eo; e += 64) {
                     S v = upd(A[e], vec[x], vec[p + y], vec[2 * p + x], vec[3 * p + y]);
-                    A[e] = fix_diag(v, x == y);
+                    A[e] = (x == y) ? fix_diag(v) : v;
                     y += 64;
                     while (y > x) {
                         y -= x + 1;
@@ -631,8 +648,8 @@ template <class S, int T, int B>
 constexpr int lds_bytes()
 {
     constexpr int R = T + B;
-    return (int)(sizeof(S) * (offB<R>(B) + vec_entries<R, B>()) + sizeof(double) * (1 << (B - 1)) + 2 * E(R - 1) +
-                 (sizeof(double) + sizeof(int)) * (MAX_N + 1));
+    return (int)(sizeof(S) * (offB<R>(B) + (1 << (B - 2))) + sizeof(double) * (2 * (1 << (B - 2)) + (1 << (B - 1))) +
+                 3 * ((1 << B) - 1) + 2 * NB(R - 1) + (sizeof(double) + sizeof(int)) * (MAX_N + 1));
 }
 
 int main_lds_bytes(bool real_path)

@@ -147,7 +147,7 @@ void stage_real(int n, const std::vector<double> &C, Staged &st)
         return;
     const int N = std::max(n, REAL_R);
     st.Nr = N;
-    st.packed_r.assign((size_t)E(N), 0.0);
+    st.packed_r.assign((size_t)NSZ(N), 0.0);
     // real 2x2 block of modes (mi, mj), row component ci, column component cj
     auto rblk = [&](int mi, int mj, int ci, int cj) -> double {
         if (mi >= n || mj >= n)
@@ -162,11 +162,12 @@ void stage_real(int n, const std::vector<double> &C, Staged &st)
         if (ci == 1 && cj == 0) return pi + qi;
         return pr - qr;
     };
-    for (int x = 0; x < 2 * N; x++)
-        for (int y = 0; y <= x; y++) {
-            const int qi = 2 * N - 1 - x, qj = 2 * N - 1 - y;
-            st.packed_r[(size_t)pidx(x, y)] = rblk(qi / 2, qj / 2, qi % 2, qj % 2);
-        }
+    for (int a = 0; a < N; a++)
+        for (int b = 0; b <= a; b++)
+            for (int e = 0; e < 4; e++) {
+                const int qi = 2 * N - 1 - (2 * a + (e >> 1)), qj = 2 * N - 1 - (2 * b + (e & 1));
+                st.packed_r[(size_t)4 * bidx(a, b) + e] = rblk(qi / 2, qj / 2, qi % 2, qj % 2);
+            }
     st.real = true;
 }
 
@@ -213,7 +214,7 @@ int stage_matrix(int n, const double *O, long ld, unsigned flags, int min_modes,
     // component q%2 -> block-order row (q/2) + (q%2) n; modes >= n are padding
     const int N = std::max(n, min_modes);
     st.N = N;
-    st.packed.assign((size_t)E(N), c64{0.0, 0.0});
+    st.packed.assign((size_t)NSZ(N), c64{0.0, 0.0});
     auto elem = [&](int qi, int qj) -> c64 {
         int mi = qi / 2, ci = qi % 2, mj = qj / 2, cj = qj % 2;
         if (mi >= n || mj >= n)
@@ -221,13 +222,15 @@ int stage_matrix(int n, const double *O, long ld, unsigned flags, int min_modes,
         int a = mi + ci * n, b = mj + cj * n;
         return c64{C[2 * ((size_t)a * n2 + b)], C[2 * ((size_t)a * n2 + b) + 1]};
     };
-    for (int x = 0; x < 2 * N; x++)
-        for (int y = 0; y <= x; y++) {
-            c64 v = elem(2 * N - 1 - x, 2 * N - 1 - y);
-            if (x == y)
-                v.y = 0.0;
-            st.packed[(size_t)pidx(x, y)] = v;
-        }
+    for (int a = 0; a < N; a++)
+        for (int b = 0; b <= a; b++)
+            for (int e = 0; e < 4; e++) {
+                const int x = 2 * a + (e >> 1), y = 2 * b + (e & 1);
+                c64 v = elem(2 * N - 1 - x, 2 * N - 1 - y);
+                if (x == y)
+                    v.y = 0.0;
+                st.packed[(size_t)4 * bidx(a, b) + e] = v;
+            }
     st.real = false;
     if (!(flags & TOR_FORCE_COMPLEX) && n > 0)
         stage_real(n, C, st);
@@ -308,9 +311,9 @@ int run_recursive(tor_ctx *ctx, bool real, std::vector<Staged *> &mats, std::vec
         d.item_begin = plan.total_items;
         plan.total_items += 1ll << d.k;
         plan.c_off.push_back(off);
-        off = align_up(off + esz * (size_t)E(d.N), 256);
+        off = align_up(off + esz * (size_t)NSZ(d.N), 256);
         plan.probs.push_back(d);
-        long long se = Fsum(d.N - 1) - Fsum(R - 1);
+        long long se = Gsum(d.N - 1) - Gsum(R - 1);
         plan.max_scratch_entries = std::max(plan.max_scratch_entries, se);
     }
     plan.bytes_C = off;
@@ -533,8 +536,8 @@ size_t tor_workspace_size(int max_n, int split_k, int max_inflight)
     const int k = split_k > 0 ? split_k : 14;
     const long long items = (1ll << std::min(k, std::max(N - CPLX_R, 0))) * std::max(max_inflight, 1);
     const size_t grid = 256 * 8;
-    const size_t scr = align_up(sizeof(c64) * (size_t)std::max(Fsum(N - 1) - Fsum(CPLX_R - 1), 1ll), 256) * grid;
-    return align_up(sizeof(c64) * (size_t)E(N), 256) * std::max(max_inflight, 1) + 4096 * (size_t)std::max(max_inflight, 1) +
+    const size_t scr = align_up(sizeof(c64) * (size_t)std::max(Gsum(N - 1) - Gsum(CPLX_R - 1), 1ll), 256) * grid;
+    return align_up(sizeof(c64) * (size_t)NSZ(N), 256) * std::max(max_inflight, 1) + 4096 * (size_t)std::max(max_inflight, 1) +
            256 + align_up(32 * (size_t)items, 256) + scr + (1 << 20);
 }
 
