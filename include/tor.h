@@ -142,9 +142,10 @@ int tor_poll(tor_ctx *ctx, unsigned long long ticket, tor_result *out);
  * (< 0: no limit) passes (TOR_E_TIMEOUT). */
 int tor_drain(tor_ctx *ctx, int timeout_ms);
 
-/* Verification aid: the device's reciprocal square root and reciprocal (the
- * hardware seeds refined by two Newton steps) for count host doubles x;
- * out receives 2 * count doubles (rsqrt(x_i), 1/x_i). */
+/* Verification aid: the device's reciprocal square root and reciprocal for
+ * count host doubles x.  out receives 4 * count doubles per input: rsqrt(x_i)
+ * and 1/x_i as the kernels form them (hardware seed refined by two Newton
+ * steps), then the two raw hardware seeds. */
 int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out);
 
 /* Static description of a code. */

@@ -280,12 +280,12 @@ class Context:
 
     def debug_math(self, x: np.ndarray) -> np.ndarray:
         x = np.ascontiguousarray(x, dtype=np.float64)
-        out = np.zeros(2 * x.size, dtype=np.float64)
+        out = np.zeros(4 * x.size, dtype=np.float64)
         dp = ctypes.POINTER(ctypes.c_double)
         rc = self._lib.tor_debug_math(self._h, x.size, x.ctypes.data_as(dp), out.ctypes.data_as(dp))
         if rc != TOR_OK:
             raise TorError(rc, "tor_debug_math")
-        return out.reshape(-1, 2)
+        return out.reshape(-1, 4)
 
 
 def workspace_size(max_n: int, split_k: int = 0, max_inflight: int = 1) -> int:

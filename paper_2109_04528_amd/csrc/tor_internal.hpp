@@ -58,11 +58,16 @@ __host__ __device__ constexpr long long Gsum(long long s) { return 2 * s * (s + 
 __host__ __device__ constexpr long long slot_off(int N, int l) { return Gsum(N - 1) - Gsum(N - l); }
 
 // kernel configurations (modes handled per lane, levels expanded in LDS)
+// T: modes a lane finishes alone; B: levels between the tier-A leaf and the
+// lanes (2^B = 64 lanes); L: the last of those levels taken by each lane in
+// registers (the first B - L are expanded in LDS).
 constexpr int CPLX_T = 3;
 constexpr int CPLX_B = 6;
+constexpr int CPLX_L = 1;
 constexpr int CPLX_R = CPLX_T + CPLX_B;
 constexpr int REAL_T = 4;
 constexpr int REAL_B = 6;
+constexpr int REAL_L = 2;
 constexpr int REAL_R = REAL_T + REAL_B;
 constexpr int MAX_N = 48;
 

@@ -269,64 +269,88 @@ __device__ __forceinline__ void tail(const S *h, double det, double sgn, Acc &ac
     }
 }
 
-// tier C: lane l finishes node l of level B from its parent of level B-1
-template <class S, int T, int B, class Acc>
-__device__ __forceinline__ void tierC(const S *bufB, const double *ndet, const uint16_t *srcOff,
-                                      const uint8_t *srcDet, double leafDet, int leafInc, int N, int lane, Acc &acc,
-                                      int &bad)
+// one lane-level decision on a register node of M modes: include its highest
+// mode (the rank-2 update) or exclude it (the same code with a zero update,
+// which copies the prefix exactly), so that both kinds of lanes run the same
+// instructions.
+template <class S, int M>
+__device__ __forceinline__ double lane_step(const S *h, bool inc, S *hn, int &bad)
 {
-    constexpr int NP = (1 << (B - 1)) - 1;  // table base of level B-1
-    const int ip = lane >> 1;
-    const S *src = bufB + srcOff[NP + ip];
-    const int di = srcDet[NP + ip];
-    const double sdet = di == 0xff ? leafDet : ndet[di];
-    // block layout -> packed lower triangle in registers (T+1 modes)
-    S h[E(T + 1)];
-#pragma unroll
-    for (int x = 0; x < 2 * (T + 1); ++x)
-#pragma unroll
-        for (int y = 0; y <= x; ++y)
-            h[pidx(x, y)] = src[4 * bidx(x >> 1, y >> 1) + ((x & 1) << 1) + (y & 1)];
-    constexpr int p = 2 * T;
+    constexpr int p = 2 * M - 2;
     const double a = re(h[pidx(p, p)]);
     const S b = h[pidx(p + 1, p)];
     const double g = re(h[pidx(p + 1, p + 1)]);
     Piv<S> pq = pivot(a, b, g);
-    const bool inc = lane & 1;
     if (inc && (!(a > 0.0) || !(pq.pdet > 0.0)))
         bad = 1;
-    if (!inc) {  // exclude: the update below becomes an exact copy
+    if (!inc) {
         pq.inv_a = 0.0;
         pq.inv_g = 0.0;
         pq.ba = zero_of(b);
         pq.pdet = 1.0;
     }
+    elim_regs<S, M>(h, pq, hn);
+    return pq.pdet;
+}
+
+// tier C: lane l finishes node l of level B.  Its ancestor of level B-L is an
+// LDS node; the lane takes the last L decisions itself (bit L-1-j of l is the
+// decision at level B-L+1+j) and then the last T modes.
+template <class S, int T, int B, int L, class Acc>
+__device__ __forceinline__ void tierC(const S *bufB, const double *ndet, const uint16_t *srcOff,
+                                      const uint8_t *srcDet, double leafDet, int leafInc, int N, int lane, Acc &acc,
+                                      int &bad)
+{
+    constexpr int NP = (1 << (B - L)) - 1;  // table base of level B-L
+    const int ip = lane >> L;
+    const S *src = bufB + srcOff[NP + ip];
+    const int di = srcDet[NP + ip];
+    double det = di == 0xff ? leafDet : ndet[di];
+    // block layout -> packed lower triangle in registers (T+L modes)
+    S h[E(T + L)];
+#pragma unroll
+    for (int x = 0; x < 2 * (T + L); ++x)
+#pragma unroll
+        for (int y = 0; y <= x; ++y)
+            h[pidx(x, y)] = src[4 * bidx(x >> 1, y >> 1) + ((x & 1) << 1) + (y & 1)];
+    int includes = leafInc + __popc(ip);
     S hT[E(T)];
-    elim_regs<S, T + 1>(h, pq, hT);
-    const int includes = leafInc + __popc(ip) + (inc ? 1 : 0);
+    if constexpr (L == 1) {
+        const bool inc = lane & 1;
+        det *= lane_step<S, T + 1>(h, inc, hT, bad);
+        includes += inc;
+    } else {
+        static_assert(L == 2, "one or two lane levels");
+        S h1[E(T + 1)];
+        const bool inc1 = (lane >> 1) & 1, inc0 = lane & 1;
+        det *= lane_step<S, T + 2>(h, inc1, h1, bad);
+        det *= lane_step<S, T + 1>(h1, inc0, hT, bad);
+        includes += inc1 + inc0;
+    }
     const int excluded = (N - T) - includes;
     const double sgn = (excluded & 1) ? -1.0 : 1.0;
-    tail<S, T, Acc>(hT, sdet * pq.pdet, sgn, acc, bad);
+    tail<S, T, Acc>(hT, det, sgn, acc, bad);
 }
 
 // ---------------------------------------------------------------------------
-template <class S, int T, int B, class Acc>
+template <class S, int T, int B, int L, class Acc>
 __global__ void __launch_bounds__(64) tor_main(MainParams prm)
 {
     constexpr int R = T + B;
-    constexpr int NN_MAX = 1 << (B - 2);  // include nodes of the last LDS level
-    __shared__ S bufB[offB<R>(B)];
+    constexpr int BL = B - L;                // levels expanded in LDS
+    constexpr int NN_MAX = 1 << (BL - 1);    // include nodes of the last LDS level
+    __shared__ S bufB[offB<R>(BL + 1)];
     __shared__ S nBa[NN_MAX];
     __shared__ double nInv[2 * NN_MAX];
-    __shared__ double ndet[1 << (B - 1)];
-    __shared__ uint16_t srcOff[(1 << B) - 1];
-    __shared__ uint8_t srcDet[(1 << B) - 1];
+    __shared__ double ndet[1 << BL];
+    __shared__ uint16_t srcOff[(1 << (BL + 1)) - 1];
+    __shared__ uint8_t srcDet[(1 << (BL + 1)) - 1];
     __shared__ uint16_t blkAB[NB(R - 1)];
     __shared__ double sdet[MAX_N + 1];
     __shared__ int sinc[MAX_N + 1];
 
     const int lane = threadIdx.x;
-    build_tables<R, B>(srcOff, srcDet, blkAB, lane);
+    build_tables<R, BL + 1>(srcOff, srcDet, blkAB, lane);
     __syncthreads();
     S *wscr = reinterpret_cast<S *>(prm.scratch + (long long)blockIdx.x * prm.scratch_stride);
 
@@ -409,8 +433,8 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
             for (int e = lane; e < NSZ(R); e += 64)
                 bufB[e] = lsrc[e];
             __syncthreads();
-            tierB<S, R, 1, B>(bufB, nInv, nBa, ndet, srcOff, srcDet, blkAB, ldet, lane, bad);
-            tierC<S, T, B, Acc>(bufB, ndet, srcOff, srcDet, ldet, linc, N, lane, acc, bad);
+            tierB<S, R, 1, BL + 1>(bufB, nInv, nBa, ndet, srcOff, srcDet, blkAB, ldet, lane, bad);
+            tierC<S, T, B, L, Acc>(bufB, ndet, srcOff, srcDet, ldet, linc, N, lane, acc, bad);
             __syncthreads();
         }
 
@@ -622,8 +646,10 @@ __global__ void tor_math_probe(const double *x, double *out, int count)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) {
-        out[2 * i] = rsqrt_nr(x[i]);
-        out[2 * i + 1] = rcp_nr(x[i]);
+        out[4 * i] = rsqrt_nr(x[i]);
+        out[4 * i + 1] = rcp_nr(x[i]);
+        out[4 * i + 2] = __builtin_amdgcn_rsq(x[i]);
+        out[4 * i + 3] = __builtin_amdgcn_rcp(x[i]);
     }
 }
 
@@ -632,29 +658,30 @@ hipError_t launch_main(bool real_path, bool dd, const MainParams &p, int grid, h
 {
     if (real_path) {
         if (dd)
-            hipLaunchKernelGGL((tor_main<double, REAL_T, REAL_B, AccDD>), dim3(grid), dim3(64), 0, s, p);
+            hipLaunchKernelGGL((tor_main<double, REAL_T, REAL_B, REAL_L, AccDD>), dim3(grid), dim3(64), 0, s, p);
         else
-            hipLaunchKernelGGL((tor_main<double, REAL_T, REAL_B, AccF64>), dim3(grid), dim3(64), 0, s, p);
+            hipLaunchKernelGGL((tor_main<double, REAL_T, REAL_B, REAL_L, AccF64>), dim3(grid), dim3(64), 0, s, p);
         return hipGetLastError();
     }
     if (dd)
-        hipLaunchKernelGGL((tor_main<c64, CPLX_T, CPLX_B, AccDD>), dim3(grid), dim3(64), 0, s, p);
+        hipLaunchKernelGGL((tor_main<c64, CPLX_T, CPLX_B, CPLX_L, AccDD>), dim3(grid), dim3(64), 0, s, p);
     else
-        hipLaunchKernelGGL((tor_main<c64, CPLX_T, CPLX_B, AccF64>), dim3(grid), dim3(64), 0, s, p);
+        hipLaunchKernelGGL((tor_main<c64, CPLX_T, CPLX_B, CPLX_L, AccF64>), dim3(grid), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 
-template <class S, int T, int B>
+template <class S, int T, int B, int L>
 constexpr int lds_bytes()
 {
-    constexpr int R = T + B;
-    return (int)(sizeof(S) * (offB<R>(B) + (1 << (B - 2))) + sizeof(double) * (2 * (1 << (B - 2)) + (1 << (B - 1))) +
-                 3 * ((1 << B) - 1) + 2 * NB(R - 1) + (sizeof(double) + sizeof(int)) * (MAX_N + 1));
+    constexpr int R = T + B, BL = B - L;
+    return (int)(sizeof(S) * (offB<R>(BL + 1) + (1 << (BL - 1))) +
+                 sizeof(double) * (2 * (1 << (BL - 1)) + (1 << BL)) + 3 * ((1 << (BL + 1)) - 1) + 2 * NB(R - 1) +
+                 (sizeof(double) + sizeof(int)) * (MAX_N + 1));
 }
 
 int main_lds_bytes(bool real_path)
 {
-    return real_path ? lds_bytes<double, REAL_T, REAL_B>() : lds_bytes<c64, CPLX_T, CPLX_B>();
+    return real_path ? lds_bytes<double, REAL_T, REAL_B, REAL_L>() : lds_bytes<c64, CPLX_T, CPLX_B, CPLX_L>();
 }
 
 hipError_t launch_reduce(const ProblemDesc *probs, int nprob, const double *slots, double *results, bool dd,

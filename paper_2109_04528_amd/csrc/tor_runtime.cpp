@@ -753,7 +753,7 @@ int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out)
         return TOR_E_INVAL;
     std::lock_guard<std::mutex> g(ctx->mu);
     const size_t bx = align_up(sizeof(double) * count, 256);
-    int rc = ensure_ws(ctx, 3 * bx);
+    int rc = ensure_ws(ctx, 5 * bx);
     if (rc != TOR_OK)
         return rc;
     double *dx = (double *)ctx->ws;
@@ -762,7 +762,7 @@ int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out)
     if (e == hipSuccess)
         e = launch_math_probe(dx, dout, count, ctx->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(out, dout, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, ctx->stream);
+        e = hipMemcpyAsync(out, dout, sizeof(double) * 4 * count, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(ctx->stream);
     return hip_status(e);

@@ -101,7 +101,7 @@ def tail(h, M, det, sgn, terms):
     tail(hn, M - 1, det * pd, sgn, terms)
 
 
-def model_tor(O: np.ndarray, T: int = 3, B: int = 6, k: int = 0, real: bool = False):
+def model_tor(O: np.ndarray, T: int = 3, B: int = 6, k: int = 0, real: bool = False, L: int = 1):
     R = T + B
     C, N = pack_real(O, R) if real else pack(O, R)
     LA = N - R
@@ -145,23 +145,27 @@ def model_tor(O: np.ndarray, T: int = 3, B: int = 6, k: int = 0, real: bool = Fa
                 lev = jl - t2
                 return nodes[(lev, (i >> t2) >> 1)]
 
-            for J in range(1, B):
+            for J in range(1, B - L + 1):
                 sp = R - (J - 1)
                 for i in range(1 << (J - 1)):
                     par, pdp = node_src(J - 1, i)
                     child, pd = eliminate(par, sp)
                     nodes[(J, i)] = (child, pdp * pd)
-            # tier C: lane l
-            for lane in range(64 if B == 6 else (1 << B)):
-                ip = lane >> 1
-                src, sdet_ = node_src(B - 1, ip)
-                h = src[: E(T + 1)]
-                inc = lane & 1
-                if inc:
-                    hT, pd = eliminate(h, T + 1)
-                else:
-                    hT, pd = h[: E(T)].copy(), 1.0
-                includes = linc + bin(ip).count("1") + inc
+            # tier C: lane l takes the last L levels, then the last T modes
+            for lane in range(1 << B):
+                ip = lane >> L
+                src, det = node_src(B - L, ip)
+                h = src[: E(T + L)].copy()
+                includes = linc + bin(ip).count("1")
+                for j in range(L):
+                    inc = (lane >> (L - 1 - j)) & 1
+                    M = T + L - j
+                    if inc:
+                        h, pd = eliminate(h, M)
+                        det *= pd
+                    else:
+                        h = h[: E(M - 1)].copy()
+                    includes += inc
                 excluded = (N - T) - includes
-                tail(hT, T, sdet_ * pd, -1.0 if excluded & 1 else 1.0, terms)
+                tail(h, T, det, -1.0 if excluded & 1 else 1.0, terms)
     return math.fsum(terms), len(terms)

@@ -31,7 +31,7 @@ def test_model_product_state_closed_form():
 @pytest.mark.parametrize("n,k", [(4, 0), (10, 0), (11, 1), (12, 2)])
 def test_real_form_model_matches_oracle(n, k):
     O = gen.random_O(n, 50 + n, 0.3, 1.2, 0.9)
-    v, cnt = model_tor(O, 4, 6, k, real=True)
+    v, cnt = model_tor(O, 4, 6, k, real=True, L=2)
     q = orc.tor(O, mode=orc.QUAD)
     assert cnt == 1 << max(n, 10)
     assert abs(v - q.value) <= 64 * 1.1e-16 * max(n, 10) * q.sum_abs, (v, q.value)
