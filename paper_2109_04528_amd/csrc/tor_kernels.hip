@@ -100,26 +100,37 @@ __device__ __forceinline__ void block_ab(int bi, int &a, int &b)
 // one include step on global memory (tier A and the root path): src is a view
 // of s modes, dst receives the Schur complement of s-1 modes.  Every lane
 // forms the pivot itself; lane l updates blocks l, l+64, ...
+// dst (global, may be null) receives the whole child; lds (may be null)
+// receives its first nlds blocks (the prefix that is the tier-A leaf).
 template <class S>
-__device__ void elim_global(const S *__restrict__ src, S *__restrict__ dst, int s, int lane, double &pdet,
-                            int &bad)
+__device__ void elim_global(const S *__restrict__ src, S *__restrict__ dst, S *lds, int nlds, int s, int lane,
+                            double &pdet, int &bad)
 {
     const int m = s - 1;
     const Piv<S> pv = node_pivot(src, m);
     pdet = pv.pdet;
     if (!(pv.pdet > 0.0) || !(pv.inv_a > 0.0))
         bad = 1;
-    const int nbo = NB(m);
+    const int nbo = dst ? NB(m) : nlds;
     for (int bi = lane; bi < nbo; bi += 64) {
         int a, b;
         block_ab(bi, a, b);
         S o[4];
         elim_block(src, m, a, b, pv, o);
-        S *d = dst + 4 * bi;
-        d[0] = o[0];
-        d[1] = o[1];
-        d[2] = o[2];
-        d[3] = o[3];
+        if (dst) {
+            S *d = dst + 4 * bi;
+            d[0] = o[0];
+            d[1] = o[1];
+            d[2] = o[2];
+            d[3] = o[3];
+        }
+        if (lds && bi < nlds) {
+            S *d = lds + 4 * bi;
+            d[0] = o[0];
+            d[1] = o[1];
+            d[2] = o[2];
+            d[3] = o[3];
+        }
     }
     __syncthreads();
 }
@@ -383,7 +394,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
             if ((root >> l) & 1) {
                 S *dst = wscr + slot_off(N, l + 1);
                 double pd;
-                elim_global<S>(rsrc, dst, N - l, lane, pd, bad);
+                elim_global<S>(rsrc, dst, nullptr, 0, N - l, lane, pd, bad);
                 rdet *= pd;
                 ++rinc;
                 rsrc = dst;
@@ -393,11 +404,11 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
         Acc acc;
         const long long nleaf = 1ll << D;
         for (long long x = 0; x < nleaf; ++x) {
-            const S *lsrc;
             double ldet;
             int linc;
             if (x == 0) {
-                lsrc = rsrc;
+                for (int e = lane; e < NSZ(R); e += 64)
+                    bufB[e] = rsrc[e];
                 ldet = rdet;
                 linc = rinc;
             } else {
@@ -419,10 +430,12 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                     sd = sdet[sl];
                     si = sinc[sl];
                 }
-                S *dst = wscr + slot_off(N, lvl + 1);
+                // the deepest slot (level LA) is never the source of a later
+                // step: that child goes to LDS only; shallower ones also go to
+                // their stack slot
+                S *dst = (lvl + 1 < LA) ? wscr + slot_off(N, lvl + 1) : nullptr;
                 double pd;
-                elim_global<S>(s, dst, N - lvl, lane, pd, bad);
-                lsrc = dst;
+                elim_global<S>(s, dst, bufB, NB(R), N - lvl, lane, pd, bad);
                 ldet = sd * pd;
                 linc = si + 1;
                 if (lane == 0) {
@@ -430,8 +443,6 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                     sinc[lvl + 1] = linc;
                 }
             }
-            for (int e = lane; e < NSZ(R); e += 64)
-                bufB[e] = lsrc[e];
             __syncthreads();
             tierB<S, R, 1, BL + 1>(bufB, nInv, nBa, ndet, srcOff, srcDet, blkAB, ldet, lane, bad);
             tierC<S, T, B, L, Acc>(bufB, ndet, srcOff, srcDet, ldet, linc, N, lane, acc, bad);
