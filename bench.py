@@ -56,17 +56,37 @@ def cpu_baseline(O, n, budget_s=15.0):
                       f"include pattern), FP64 Cholesky per subset, __float128 sum, {cores} threads"}
 
 
-def serve_stream(ctx, count, seed, rate_hz):
-    """Poisson arrivals of click submatrices O_S of 40-mode states, n ~ U{8..32}."""
+def serve_requests(count, seed):
+    """Click submatrices O_S of 40-mode Gaussian states (r ~ U[.5, 1],
+    eta ~ U[.3, 1], one state per 8 requests), S a uniform n-subset, n ~ U{8..32}."""
     import numpy as np
     from paper_2109_04528_amd import inputs as gen
     rng = np.random.default_rng(seed)
-    states = [gen.random_O(40, 5000 + i, 0.5, 1.0, float(rng.uniform(0.3, 1.0))) for i in range(8)]
+    states = [gen.random_O(40, 5000 + i, 0.5, 1.0, float(rng.uniform(0.3, 1.0))) for i in range(count // 8 + 1)]
     reqs = []
     for i in range(count):
         n = int(rng.integers(8, 33))
         S = sorted(rng.choice(40, size=n, replace=False).tolist())
-        reqs.append(gen.click_submatrix(states[i % len(states)], S))
+        reqs.append(gen.click_submatrix(states[i // 8], S))
+    return reqs
+
+
+def serve_saturated(ctx, reqs):
+    """All requests submitted at once: the stream's saturated throughput."""
+    t0 = time.perf_counter()
+    tickets = [ctx.submit(O) for O in reqs]
+    ctx.drain(-1)
+    wall = time.perf_counter() - t0
+    for t in tickets:
+        ctx.poll(t)
+    return len(reqs) / wall
+
+
+def serve_stream(ctx, reqs, seed, rate_hz):
+    """Poisson arrivals at rate_hz; latency = submit to completed poll."""
+    import numpy as np
+    count = len(reqs)
+    rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate_hz, size=count)
     t_sub = {}
     lat = []
@@ -78,7 +98,7 @@ def serve_stream(ctx, count, seed, rate_hz):
         now = time.perf_counter()
         while i < count and now >= nxt:
             tk = ctx.submit(reqs[i])
-            t_sub[tk] = time.perf_counter()
+            t_sub[tk] = nxt  # open loop: latency counts from the scheduled arrival
             pending[tk] = i
             nxt += gaps[i]
             i += 1
@@ -91,7 +111,8 @@ def serve_stream(ctx, count, seed, rate_hz):
     wall = time.perf_counter() - t0
     lat = sorted(lat)
     return {"requests": count, "rate_hz": rate_hz, "wall_s": wall, "tor_per_s": count / wall,
-            "p50_ms": 1e3 * lat[len(lat) // 2], "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))]}
+            "p50_ms": 1e3 * lat[len(lat) // 2], "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
+            "mean_ms": 1e3 * sum(lat) / len(lat), "max_ms": 1e3 * lat[-1]}
 
 
 def main():
@@ -103,7 +124,9 @@ def main():
     ap.add_argument("--plain-masks", type=int, default=1 << 18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--serve", type=int, default=0, help="requests in the mixed-n stream (0: skip)")
+    ap.add_argument("--serve", type=int, default=4096, help="requests in the mixed-n stream (0: skip)")
+    ap.add_argument("--batch", type=int, default=512, help="matrices in the batched launch (0: skip)")
+    ap.add_argument("--n34", type=int, default=1, help="also time one n=34 Torontonian")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -152,9 +175,37 @@ def main():
                  "recursive_speedup": ((1 << n) / (kernel_ms * 1e-3)) / plain_dets}
         print("bench: plain comparison done", file=sys.stderr, flush=True)
 
+    batch = None
+    if args.batch > 0:
+        ns, mats = inputs.batch_mix(args.batch, 12, 26, seed=4)
+        ctx.eval_batch(mats[:8])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.eval_batch(mats)
+        t1 = time.perf_counter()
+        subsets = sum(1 << n for n in ns)
+        batch = {"matrices": args.batch, "n_range": [12, 26], "seconds": t1 - t0,
+                 "tor_per_s": args.batch / (t1 - t0), "subset_dets_per_s": subsets / (t1 - t0),
+                 "kernel_ms": max(r.device_ms for r in res), "launches": len({r.path for r in res})}
+        print("bench: batch done", file=sys.stderr, flush=True)
+
+    big = None
+    if args.n34:
+        O34 = inputs.random_O(34, 0, 0.5, 1.0, 0.7)
+        r34 = ctx.eval(O34)
+        big = {"n": 34, "kernel_ms": r34.device_ms, "subset_dets_per_s": (1 << 34) / (r34.device_ms * 1e-3),
+               "tor": r34.value, "cancellation_R": r34.cancellation}
+        print("bench: n=34 done", file=sys.stderr, flush=True)
+
     serve = None
     if args.serve > 0:
-        serve = serve_stream(ctx, args.serve, 5, rate_hz=200.0)
+        reqs = serve_requests(args.serve, 5)
+        sat = serve_saturated(ctx, reqs)
+        rate = 0.7 * sat
+        serve = serve_stream(ctx, reqs, 6, rate_hz=rate)
+        serve["saturated_tor_per_s"] = sat
+        serve["arrivals"] = "Poisson at 0.7 x saturated throughput of the same mix"
+        print("bench: serving done", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -190,6 +241,8 @@ def main():
                      "flop_per_launch": flops,
                      "kernel": "tor_main<double, T=4, B=6>" if real_path else "tor_main<c64, T=3, B=6>"},
         "plain": plain,
+        "batch": batch,
+        "n34": big,
         "serving": serve,
         "cpu_baseline": cpu,
     }

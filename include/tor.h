@@ -144,9 +144,27 @@ int tor_drain(tor_ctx *ctx, int timeout_ms);
 
 /* Verification aid: the device's reciprocal square root and reciprocal for
  * count host doubles x.  out receives 4 * count doubles per input: rsqrt(x_i)
- * and 1/x_i as the kernels form them (hardware seed refined by two Newton
- * steps), then the two raw hardware seeds. */
+ * and 1/x_i as the kernels form them (hardware seed refined by one
+ * third-order correction), then the two raw hardware seeds. */
 int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out);
+
+/* Autotuner.  For every n in [n_min, n_max] and each selected path
+ * (TOR_TUNE_REAL: Gaussian-state matrices, TOR_TUNE_COMPLEX: general ones)
+ * time the recursive kernel over split depths k and persistent waves per CU
+ * and keep the fastest pair for that size in the context; later evaluations
+ * (single, batched and served) use it.  Timing does not depend on the matrix
+ * values, so the tuner uses its own synthetic matrices.  Blocks for the
+ * duration of the timing runs. */
+#define TOR_TUNE_REAL 0x1u
+#define TOR_TUNE_COMPLEX 0x2u
+int tor_autotune(tor_ctx *ctx, int n_min, int n_max, unsigned paths);
+
+/* Write the context's tuning table as JSON (arch, CU count, entries). */
+int tor_tune_save(tor_ctx *ctx, const char *path);
+
+/* Load a table written by tor_tune_save; rejected (TOR_E_INVAL) when it was
+ * made for another architecture or CU count. */
+int tor_tune_load(tor_ctx *ctx, const char *path);
 
 /* Static description of a code. */
 const char *tor_strerror(int code);

@@ -38,8 +38,11 @@ TOR_FORCE_COMPLEX = 0x4
 EXPORTS = [
     "tor_default_options", "tor_create", "tor_destroy", "tor_workspace_size", "tor_eval",
     "tor_eval_batch", "tor_eval_plain", "tor_eval_partials", "tor_submit", "tor_poll",
-    "tor_drain", "tor_debug_math", "tor_strerror",
+    "tor_drain", "tor_debug_math", "tor_strerror", "tor_autotune", "tor_tune_save", "tor_tune_load",
 ]
+
+TOR_TUNE_REAL = 0x1
+TOR_TUNE_COMPLEX = 0x2
 
 
 class tor_options(ctypes.Structure):
@@ -110,6 +113,12 @@ def load(path: str = LIB_PATH):
     lib.tor_drain.restype = ctypes.c_int
     lib.tor_debug_math.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]
     lib.tor_debug_math.restype = ctypes.c_int
+    lib.tor_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint]
+    lib.tor_autotune.restype = ctypes.c_int
+    lib.tor_tune_save.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+    lib.tor_tune_save.restype = ctypes.c_int
+    lib.tor_tune_load.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+    lib.tor_tune_load.restype = ctypes.c_int
     lib.tor_strerror.argtypes = [ctypes.c_int]
     lib.tor_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -277,6 +286,21 @@ class Context:
         rc = self._lib.tor_drain(self._h, timeout_ms)
         if rc != TOR_OK:
             raise TorError(rc, "tor_drain")
+
+    def autotune(self, n_min: int, n_max: int, paths: int = TOR_TUNE_REAL | TOR_TUNE_COMPLEX) -> None:
+        rc = self._lib.tor_autotune(self._h, n_min, n_max, paths)
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_autotune")
+
+    def save_tuning(self, path: str) -> None:
+        rc = self._lib.tor_tune_save(self._h, path.encode())
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_tune_save")
+
+    def load_tuning(self, path: str) -> None:
+        rc = self._lib.tor_tune_load(self._h, path.encode())
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_tune_load")
 
     def debug_math(self, x: np.ndarray) -> np.ndarray:
         x = np.ascontiguousarray(x, dtype=np.float64)

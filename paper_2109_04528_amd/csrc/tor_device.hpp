@@ -76,25 +76,26 @@ __device__ __forceinline__ c64 upd_diag(c64 h, c64 u1, c64 r1, c64 u2, c64 r2)
     return c64{xr, 0.0};
 }
 
-// ---- reciprocal and reciprocal square root: hardware seed + two Newton steps
+// ---- reciprocal and reciprocal square root ---------------------------------
+// The hardware seeds (v_rcp_f64, v_rsq_f64) are good to about 2^-24; one
+// correction of third order brings them to within one unit in the last place:
+//   1/x:        e = 1 - x y,    y' = y + y (e + e^2)
+//   1/sqrt(x):  d = 1 - x y^2,  y' = y + y d (1/2 + 3/8 d)
+// (the Taylor series of (1 - e)^-1 and (1 - d)^-1/2 to second order; the
+// neglected terms are O(e^3), O(d^3) ~ 2^-72).
 __device__ __forceinline__ double rcp_nr(double x)
 {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, y, 1.0);
+    return fma(y, fma(e, e, e), y);
 }
 
 __device__ __forceinline__ double rsqrt_nr(double x)
 {
-    double y = __builtin_amdgcn_rsq(x);
-    double h = x * y;
-    double r = fma(-h, y, 1.0);  // 1 - x y^2
-    y = fma(0.5 * y, r, y);
-    h = x * y;
-    r = fma(-h, y, 1.0);
-    return fma(0.5 * y, r, y);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double h = x * y;
+    const double d = fma(-h, y, 1.0);
+    return fma(y * d, fma(d, 0.375, 0.5), y);
 }
 
 // ---- wave-uniform broadcast ------------------------------------------------

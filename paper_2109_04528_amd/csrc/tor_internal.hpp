@@ -25,12 +25,15 @@ __host__ __device__ constexpr int bidx(int a, int b) { return a * (a + 1) / 2 + 
 __host__ __device__ constexpr int E(int s) { return s * (2 * s + 1); }
 __host__ __device__ constexpr int pidx(int x, int y) { return x * (x + 1) / 2 + y; }
 
-// One matrix in a launch.
+// One matrix (or a contiguous range of its subtree roots) in a launch.
 struct ProblemDesc {
-    const void *C;         // packed reversed Hermitian (c64) or symmetric (double) matrix, N modes
+    const void *C;         // device layout of I - O (c64 or double), N modes
+    double *slots;         // this matrix's partial slots, 4 doubles per root
     int N;                 // modes after padding (>= R of the kernel)
-    int k;                 // split depth: 2^k subtree roots
-    long long item_begin;  // first queue item (= first partial slot) of this matrix
+    int k;                 // split depth: 2^k subtree roots in total
+    long long root_begin;  // first root handled by this launch
+    long long item_begin;  // queue item of that root in this launch
+    long long nroots;      // roots handled by this launch
 };
 
 struct MainParams {
@@ -38,7 +41,6 @@ struct MainParams {
     int nprob;
     long long total_items;
     unsigned long long *counter;  // queue head, zero before the launch
-    double *slots;                // 4 doubles per item: hi, lo, sum|t|, numeric-failure flag
     char *scratch;                // per-wave stack of the upper include levels
     long long scratch_stride;     // bytes per wave
 };
@@ -73,8 +75,7 @@ constexpr int MAX_N = 48;
 
 // host-side launchers (defined in tor_kernels.hip)
 hipError_t launch_main(bool real_path, bool dd, const MainParams &p, int grid, hipStream_t s);
-hipError_t launch_reduce(const ProblemDesc *probs, int nprob, const double *slots, double *results,
-                         bool dd, hipStream_t s);
+hipError_t launch_reduce(const ProblemDesc *probs, int nprob, double *results, bool dd, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, int count, hipStream_t s);
 hipError_t launch_plain(const PlainParams &p, int grid, hipStream_t s);
 hipError_t launch_plain_reduce(const double *partials, int nwaves, double *result, hipStream_t s);

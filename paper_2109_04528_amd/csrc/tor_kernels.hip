@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                 hi = mid - 1;
         }
         const ProblemDesc P = prm.probs[lo];
-        const long long root = (long long)item - P.item_begin;
+        const long long root = P.root_begin + ((long long)item - P.item_begin);
         const int N = P.N, k = P.k, LA = N - R, D = LA - k;
         const S *C = reinterpret_cast<const S *>(P.C);
         int bad = 0;
@@ -462,7 +462,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
         }
         const int anybad = __any(bad);
         if (lane == 0) {
-            double *sl = prm.slots + 4 * item;
+            double *sl = P.slots + 4 * root;
             sl[0] = h;
             sl[1] = l;
             sl[2] = ab;
@@ -474,15 +474,14 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
 // ---------------------------------------------------------------------------
 // per-matrix sum of the root slots, in index order
 template <bool DD>
-__global__ void __launch_bounds__(64) tor_reduce(const ProblemDesc *probs, const double *slots,
-                                                 double *results)
+__global__ void __launch_bounds__(64) tor_reduce(const ProblemDesc *probs, double *results)
 {
     const int q = blockIdx.x, lane = threadIdx.x;
     const ProblemDesc P = probs[q];
     const long long nroots = 1ll << P.k;
     double h = 0.0, l = 0.0, ab = 0.0, bad = 0.0;
     for (long long r = lane; r < nroots; r += 64) {
-        const double *s = slots + 4 * (P.item_begin + r);
+        const double *s = P.slots + 4 * r;
         if (DD)
             dd_add2(h, l, s[0], s[1]);
         else
@@ -695,13 +694,12 @@ int main_lds_bytes(bool real_path)
     return real_path ? lds_bytes<double, REAL_T, REAL_B, REAL_L>() : lds_bytes<c64, CPLX_T, CPLX_B, CPLX_L>();
 }
 
-hipError_t launch_reduce(const ProblemDesc *probs, int nprob, const double *slots, double *results, bool dd,
-                         hipStream_t s)
+hipError_t launch_reduce(const ProblemDesc *probs, int nprob, double *results, bool dd, hipStream_t s)
 {
     if (dd)
-        hipLaunchKernelGGL((tor_reduce<true>), dim3(nprob), dim3(64), 0, s, probs, slots, results);
+        hipLaunchKernelGGL((tor_reduce<true>), dim3(nprob), dim3(64), 0, s, probs, results);
     else
-        hipLaunchKernelGGL((tor_reduce<false>), dim3(nprob), dim3(64), 0, s, probs, slots, results);
+        hipLaunchKernelGGL((tor_reduce<false>), dim3(nprob), dim3(64), 0, s, probs, results);
     return hipGetLastError();
 }
 

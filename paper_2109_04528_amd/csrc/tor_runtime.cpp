@@ -6,12 +6,18 @@
 //      FP64 Cholesky of the full matrix: positive definiteness of I - O
 //      implies it for every principal submatrix (Cauchy interlacing), so
 //      this single check covers all 2^n subsets;
-//   3. pack the matrix in the device layout (mode-interleaved, reversed,
-//      lower-packed; see tor_device.hpp), padded to the kernel's minimum size
-//      with decoupled modes of (I - O) block I/2 -- such a mode multiplies
-//      the Torontonian by 1/sqrt(1/4) - 1 = 1 exactly;
+//   3. pack the matrix in the device layout (tor_internal.hpp), padded to the
+//      kernel's minimum size with decoupled modes whose block of I - O is
+//      I/2 -- such a mode multiplies the Torontonian by 1/sqrt(1/4) - 1 = 1;
+//      Gaussian-state matrices are also packed in their real form;
 //   4. one persistent launch over all (matrix, subtree root) items, then the
-//      fixed-order per-matrix reduction, one device-to-host copy.
+//      fixed-order per-matrix reduction of the root slots, one copy back.
+//
+// Serving (tor_submit / tor_poll) keeps each admitted request's matrix and
+// root slots in a device pool and runs them in chunked launches: every launch
+// takes a bounded number of subsets from the admitted requests, smallest
+// remaining work first, so requests that arrive while others run join the
+// next launch instead of waiting for the longest one to finish.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,8 +28,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -38,21 +46,34 @@ namespace {
 constexpr double kU = 1.1102230246251565e-16;  // FP64 unit roundoff
 
 struct Staged {
-    int n = 0;        // modes of the input
-    int N = 0;        // modes after padding (complex path)
-    std::vector<c64> packed;
+    int n = 0;                    // modes of the input
+    int N = 0;                    // modes after padding (complex path)
+    std::vector<c64> packed;      // complex device layout
     bool real = false;            // Gaussian-state structure found: real path
     int Nr = 0;                   // modes after padding (real path)
     std::vector<double> packed_r; // real symmetric form, same layout
-    int status = TOR_OK;
 };
 
 struct Request {
-    unsigned long long ticket;
+    unsigned long long ticket = 0;
     Staged st;
-    tor_result res;
+    tor_result res{};
     bool done = false;
-    std::chrono::steady_clock::time_point t_submit;
+    // device state once admitted
+    bool real = false;
+    int N = 0, k = 0;
+    long long nroots = 0, next_root = 0;
+    long long root_work = 0;  // subsets per root
+    size_t pool_off = 0, pool_len = 0;
+    char *dC = nullptr;
+    double *dSlots = nullptr;
+    float device_ms = 0.f;
+};
+
+struct TuneEntry {
+    bool valid = false;
+    int k = 0, waves = 0;
+    float ms = 0.f;
 };
 
 }  // namespace
@@ -66,11 +87,14 @@ struct tor_ctx {
     bool own_ws = false;
     tor_options opt{};
     int num_cu = 0;
+    int fit[2] = {1, 1};  // one-wave workgroups per CU the LDS allows (complex, real)
     int waves_per_cu = 4;
-    int grid = 0;    // complex-path persistent grid
-    int grid_r = 0;  // real-path persistent grid
+    int grid = 0;         // complex-path persistent grid
+    int grid_r = 0;       // real-path persistent grid
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::mutex mu;  // serialises device work on this context
+    std::mutex mu;        // serialises device work on this context
+    TuneEntry tune[2][MAX_N + 1];
+    std::string arch;
 
     // serving
     std::mutex smu;
@@ -80,8 +104,12 @@ struct tor_ctx {
     unsigned long long next_ticket = 1;
     std::thread worker;
     bool stop = false;
-    int inflight = 0;
-    int max_queue = 65536;
+    int admitted = 0;
+    int max_queue = 1 << 16;
+    long long chunk_subsets = 1ll << 29;  // work per serving launch
+    char *pool = nullptr;
+    size_t pool_bytes = 256ull << 20;
+    std::map<size_t, size_t> pool_free;  // offset -> length
 };
 
 namespace {
@@ -237,21 +265,25 @@ int stage_matrix(int n, const double *O, long ld, unsigned flags, int min_modes,
     return TOR_OK;
 }
 
-struct LaunchPlan {
-    std::vector<int> order;  // problem index (input order) for each launch slot
-    std::vector<ProblemDesc> probs;
-    std::vector<size_t> c_off;
-    long long total_items = 0;
-    long long max_scratch_entries = 0;
-    size_t bytes_C = 0;
-};
 
 int path_R(bool real) { return real ? REAL_R : CPLX_R; }
-int path_grid(const tor_ctx *ctx, bool real) { return real ? ctx->grid_r : ctx->grid; }
 int modes_of(const Staged &m, bool real) { return real ? m.Nr : m.N; }
 
-// split depth: about four subtree roots per persistent wave, never deeper than
-// the levels above the last R modes
+int default_grid(const tor_ctx *ctx, bool real) { return real ? ctx->grid_r : ctx->grid; }
+
+// launch grid for a set of matrices: the tuned waves/CU of the largest one,
+// else as many one-wave workgroups as the LDS allows (at most 8 per CU)
+int launch_grid(const tor_ctx *ctx, bool real, int Nmax)
+{
+    const int n = std::min(Nmax, MAX_N);
+    const TuneEntry &t = ctx->tune[real][n];
+    if (ctx->opt.waves_per_cu <= 0 && t.valid)
+        return ctx->num_cu * std::min(t.waves, ctx->fit[real]);
+    return default_grid(ctx, real);
+}
+
+// split depth: the tuned value for this size, else about four subtree roots
+// per persistent wave, never deeper than the levels above the last R modes
 int choose_k(const tor_ctx *ctx, int N, bool real)
 {
     const int LA = N - path_R(real);
@@ -259,8 +291,11 @@ int choose_k(const tor_ctx *ctx, int N, bool real)
         return 0;
     if (ctx->opt.split_k > 0)
         return std::min(ctx->opt.split_k, LA);
+    const TuneEntry &t = ctx->tune[real][std::min(N, MAX_N)];
+    if (t.valid)
+        return std::min(t.k, LA);
     int g = 1;
-    while ((1 << g) < path_grid(ctx, real))
+    while ((1 << g) < default_grid(ctx, real))
         ++g;
     return std::min(LA, g + 2);
 }
@@ -286,96 +321,91 @@ int ensure_ws(tor_ctx *ctx, size_t bytes)
     return TOR_OK;
 }
 
-// Run the recursive path over already staged matrices that all take the same
-// path.  results: 4 doubles per matrix (input order).  slots_out (optional)
-// receives the raw slots.
-int run_recursive(tor_ctx *ctx, bool real, std::vector<Staged *> &mats, std::vector<int> &ks,
-                  std::vector<double> &results, float *ms, std::vector<double> *slots_out)
+// Workspace bytes a launch needs after its matrices and slots: descriptors,
+// reduction descriptors, queue counter, results, per-wave tier-A stacks.
+struct LaunchLayout {
+    size_t b_probs, b_red, b_counter, b_res;
+    long long stride;
+    size_t total(int grid) const { return b_probs + b_red + b_counter + b_res + (size_t)stride * grid; }
+};
+
+LaunchLayout launch_layout(bool real, int count, int nred, int Nmax)
 {
-    const int R = path_R(real);
     const size_t esz = real ? sizeof(double) : sizeof(c64);
-    const int grid = path_grid(ctx, real);
-    const int count = (int)mats.size();
-    LaunchPlan plan;
-    plan.order.resize(count);
-    for (int i = 0; i < count; i++)
-        plan.order[i] = i;
-    std::stable_sort(plan.order.begin(), plan.order.end(),
-                     [&](int a, int b) { return modes_of(*mats[a], real) > modes_of(*mats[b], real); });
-    size_t off = 0;
-    for (int s = 0; s < count; s++) {
-        Staged *m = mats[plan.order[s]];
-        ProblemDesc d{};
-        d.N = modes_of(*m, real);
-        d.k = ks[plan.order[s]];
-        d.item_begin = plan.total_items;
-        plan.total_items += 1ll << d.k;
-        plan.c_off.push_back(off);
-        off = align_up(off + esz * (size_t)NSZ(d.N), 256);
-        plan.probs.push_back(d);
-        long long se = Gsum(d.N - 1) - Gsum(R - 1);
-        plan.max_scratch_entries = std::max(plan.max_scratch_entries, se);
+    LaunchLayout L;
+    L.b_probs = align_up(sizeof(ProblemDesc) * std::max(count, 1), 256);
+    L.b_red = align_up(sizeof(ProblemDesc) * std::max(nred, 1), 256);
+    L.b_counter = 256;
+    L.b_res = align_up(sizeof(double) * 4 * std::max(nred, 1), 256);
+    L.stride = (long long)align_up(esz * (size_t)std::max(Gsum(Nmax - 1) - Gsum(path_R(real) - 1), 1ll), 256);
+    return L;
+}
+
+// One persistent launch over the root ranges in descs (C, slots, N, k,
+// root_begin, nroots filled in), followed by the reduction of the matrices
+// listed in reduce (indices into descs, or none), into results (4 doubles
+// each).  The workspace from byte ws_off on holds descriptors, counter,
+// results and the per-wave tier-A stacks.  When ws_off > 0 the bytes below it
+// hold data the descriptors point to, and the caller has already sized the
+// workspace (a reallocation here would move that data).
+int run_launch(tor_ctx *ctx, bool real, std::vector<ProblemDesc> &descs, const std::vector<int> &reduce,
+               size_t ws_off, int grid, std::vector<double> *results, float *ms)
+{
+    const int count = (int)descs.size();
+    long long total = 0;
+    int Nmax = 0;
+    for (auto &d : descs) {
+        d.item_begin = total;
+        total += d.nroots;
+        Nmax = std::max(Nmax, d.N);
     }
-    plan.bytes_C = off;
-    const size_t b_probs = align_up(sizeof(ProblemDesc) * count, 256);
-    const size_t b_counter = 256;
-    const size_t b_slots = align_up(sizeof(double) * 4 * (size_t)plan.total_items, 256);
-    const size_t b_res = align_up(sizeof(double) * 4 * (size_t)count, 256);
-    const long long stride = (long long)align_up(esz * (size_t)std::max(plan.max_scratch_entries, 1ll), 256);
-    const size_t b_scr = (size_t)stride * grid;
-    const size_t total = plan.bytes_C + b_probs + b_counter + b_slots + b_res + b_scr;
-    int rc = ensure_ws(ctx, total);
+    std::vector<ProblemDesc> red;
+    for (int i : reduce)
+        red.push_back(descs[i]);
+    const int nred = (int)red.size();
+    const LaunchLayout Lo = launch_layout(real, count, nred, Nmax);
+    const size_t need = ws_off + Lo.total(grid);
+    if (ws_off > 0 && need > ctx->ws_bytes)
+        return TOR_E_NOMEM;  // the caller sizes the workspace first
+    int rc = ensure_ws(ctx, need);
     if (rc != TOR_OK)
         return rc;
-    char *base = ctx->ws;
-    char *dC = base;
-    ProblemDesc *dProbs = (ProblemDesc *)(dC + plan.bytes_C);
-    unsigned long long *dCounter = (unsigned long long *)((char *)dProbs + b_probs);
-    double *dSlots = (double *)((char *)dCounter + b_counter);
-    double *dRes = (double *)((char *)dSlots + b_slots);
-    char *dScr = (char *)dRes + b_res;
-
-    // host staging buffer for C and descriptors
-    std::vector<char> hbuf(plan.bytes_C + b_probs, 0);
-    for (int s = 0; s < count; s++) {
-        Staged *m = mats[plan.order[s]];
-        if (real)
-            std::memcpy(hbuf.data() + plan.c_off[s], m->packed_r.data(), esz * m->packed_r.size());
-        else
-            std::memcpy(hbuf.data() + plan.c_off[s], m->packed.data(), esz * m->packed.size());
-        plan.probs[s].C = dC + plan.c_off[s];
-    }
-    std::memcpy(hbuf.data() + plan.bytes_C, plan.probs.data(), sizeof(ProblemDesc) * count);
+    char *dProbs = ctx->ws + ws_off;
+    char *dRed = dProbs + Lo.b_probs;
+    unsigned long long *dCounter = (unsigned long long *)(dRed + Lo.b_red);
+    double *dRes = (double *)((char *)dCounter + Lo.b_counter);
+    char *dScr = (char *)dRes + Lo.b_res;
+    const long long stride = Lo.stride;
+    // descriptors and reduction descriptors at their exact byte offsets
+    std::vector<char> hdesc(Lo.b_probs + Lo.b_red, 0);
+    std::memcpy(hdesc.data(), descs.data(), sizeof(ProblemDesc) * count);
+    if (nred)
+        std::memcpy(hdesc.data() + Lo.b_probs, red.data(), sizeof(ProblemDesc) * nred);
 
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(dC, hbuf.data(), hbuf.size(), hipMemcpyHostToDevice, ctx->stream);
+        e = hipMemcpyAsync(dProbs, hdesc.data(), hdesc.size(), hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess)
         e = launch_zero(dCounter, 1, ctx->stream);
     MainParams mp{};
-    mp.probs = dProbs;
+    mp.probs = (const ProblemDesc *)dProbs;
     mp.nprob = count;
-    mp.total_items = plan.total_items;
+    mp.total_items = total;
     mp.counter = dCounter;
-    mp.slots = dSlots;
     mp.scratch = dScr;
     mp.scratch_stride = stride;
     const bool dd = ctx->opt.accum != TOR_ACCUM_FP64;
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev0, ctx->stream);
-    if (e == hipSuccess)
+    if (e == hipSuccess && total > 0)
         e = launch_main(real, dd, mp, grid, ctx->stream);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev1, ctx->stream);  // device_ms: the main kernel alone
-    if (e == hipSuccess)
-        e = launch_reduce(dProbs, count, dSlots, dRes, dd, ctx->stream);
-    std::vector<double> hres(4 * (size_t)count);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hres.data(), dRes, sizeof(double) * 4 * count, hipMemcpyDeviceToHost, ctx->stream);
-    if (slots_out && e == hipSuccess) {
-        slots_out->resize(4 * (size_t)plan.total_items);
-        e = hipMemcpyAsync(slots_out->data(), dSlots, sizeof(double) * 4 * plan.total_items,
-                           hipMemcpyDeviceToHost, ctx->stream);
+    std::vector<double> hres(4 * (size_t)std::max(nred, 1));
+    if (e == hipSuccess && nred > 0) {
+        e = launch_reduce((const ProblemDesc *)dRed, nred, dRes, dd, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hres.data(), dRes, sizeof(double) * 4 * nred, hipMemcpyDeviceToHost, ctx->stream);
     }
     if (e == hipSuccess)
         e = hipStreamSynchronize(ctx->stream);
@@ -383,10 +413,81 @@ int run_recursive(tor_ctx *ctx, bool real, std::vector<Staged *> &mats, std::vec
         return hip_status(e);
     if (ms)
         (void)hipEventElapsedTime(ms, ctx->ev0, ctx->ev1);
+    if (results)
+        results->assign(hres.begin(), hres.begin() + 4 * nred);
+    return TOR_OK;
+}
+
+// Synchronous path: all roots of every matrix in one launch, matrices with
+// more modes first.  results: 4 doubles per matrix (input order).
+int run_recursive(tor_ctx *ctx, bool real, std::vector<Staged *> &mats, std::vector<int> &ks,
+                  std::vector<double> &results, float *ms, std::vector<double> *slots_out)
+{
+    const size_t esz = real ? sizeof(double) : sizeof(c64);
+    const int count = (int)mats.size();
+    std::vector<int> order(count);
+    for (int i = 0; i < count; i++)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return modes_of(*mats[a], real) > modes_of(*mats[b], real); });
+    // workspace: matrices, then slots, then what run_launch needs
+    std::vector<size_t> c_off(count), s_off(count);
+    size_t off = 0;
+    long long nslots = 0;
+    int Nmax = 0;
+    for (int s = 0; s < count; s++) {
+        const Staged *m = mats[order[s]];
+        c_off[s] = off;
+        off = align_up(off + esz * (size_t)NSZ(modes_of(*m, real)), 256);
+        Nmax = std::max(Nmax, modes_of(*m, real));
+    }
+    for (int s = 0; s < count; s++) {
+        s_off[s] = off + sizeof(double) * 4 * (size_t)nslots;
+        nslots += 1ll << ks[order[s]];
+    }
+    off = align_up(off + sizeof(double) * 4 * (size_t)nslots, 256);
+    const int grid = launch_grid(ctx, real, Nmax);
+    // size the workspace for everything before placing data in it
+    int rc = ensure_ws(ctx, off + launch_layout(real, count, count, Nmax).total(grid));
+    if (rc != TOR_OK)
+        return rc;
+    std::vector<char> hbuf(s_off.empty() ? 0 : s_off[0], 0);
+    std::vector<ProblemDesc> descs(count);
+    std::vector<int> red(count);
+    for (int s = 0; s < count; s++) {
+        const Staged *m = mats[order[s]];
+        if (real)
+            std::memcpy(hbuf.data() + c_off[s], m->packed_r.data(), esz * m->packed_r.size());
+        else
+            std::memcpy(hbuf.data() + c_off[s], m->packed.data(), esz * m->packed.size());
+        ProblemDesc &d = descs[s];
+        d.C = ctx->ws + c_off[s];
+        d.slots = (double *)(ctx->ws + s_off[s]);
+        d.N = modes_of(*m, real);
+        d.k = ks[order[s]];
+        d.root_begin = 0;
+        d.nroots = 1ll << d.k;
+        red[s] = s;
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess && !hbuf.empty())
+        e = hipMemcpyAsync(ctx->ws, hbuf.data(), hbuf.size(), hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    std::vector<double> res;
+    rc = run_launch(ctx, real, descs, red, off, grid, &res, ms);
+    if (rc != TOR_OK)
+        return rc;
     results.assign(4 * (size_t)count, 0.0);
     for (int s = 0; s < count; s++)
         for (int j = 0; j < 4; j++)
-            results[4 * (size_t)plan.order[s] + j] = hres[4 * (size_t)s + j];
+            results[4 * (size_t)order[s] + j] = res[4 * (size_t)s + j];
+    if (slots_out) {
+        slots_out->resize(4 * (size_t)nslots);
+        e = hipMemcpy(slots_out->data(), ctx->ws + s_off[0], sizeof(double) * 4 * nslots, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return hip_status(e);
+    }
     return TOR_OK;
 }
 
@@ -422,8 +523,7 @@ int copy_input_to_host(int n, const double *O, long ld, unsigned flags, std::vec
     return TOR_OK;
 }
 
-// Launch the staged matrices, one launch per arithmetic path.  done[j] and
-// out[idx[j]] are filled for every staged matrix.
+// Launch the staged matrices, one launch per arithmetic path.
 int run_staged(tor_ctx *ctx, std::vector<Staged *> &mats, const std::vector<int> &idx, int fixed_k,
                tor_result *out, std::vector<double> *slots_out, int *k_out)
 {
@@ -495,7 +595,249 @@ int eval_many(tor_ctx *ctx, int count, const int *n, const double *const *O, con
     return first_err;
 }
 
-void serve_loop(tor_ctx *ctx);
+// ---- serving: device pool ----------------------------------------------------
+
+bool pool_alloc(tor_ctx *ctx, size_t len, size_t &off)
+{
+    len = align_up(len, 256);
+    for (auto it = ctx->pool_free.begin(); it != ctx->pool_free.end(); ++it)
+        if (it->second >= len) {
+            off = it->first;
+            const size_t rest = it->second - len;
+            ctx->pool_free.erase(it);
+            if (rest)
+                ctx->pool_free[off + len] = rest;
+            return true;
+        }
+    return false;
+}
+
+void pool_release(tor_ctx *ctx, size_t off, size_t len)
+{
+    len = align_up(len, 256);
+    auto it = ctx->pool_free.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != ctx->pool_free.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        ctx->pool_free.erase(nx);
+    }
+    if (it != ctx->pool_free.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            ctx->pool_free.erase(it);
+        }
+    }
+}
+
+size_t request_bytes(const Request &r)
+{
+    const size_t esz = r.real ? sizeof(double) : sizeof(c64);
+    return align_up(esz * (size_t)NSZ(r.N), 256) + align_up(sizeof(double) * 4 * (size_t)r.nroots, 256);
+}
+
+// One scheduling round for one path: pick root ranges for a launch, run it,
+// retire the finished requests.  Called with ctx->mu held.
+int serve_round(tor_ctx *ctx, bool real, std::vector<Request *> &active, std::vector<Request *> &finished)
+{
+    std::vector<Request *> cand;
+    for (Request *r : active)
+        if (r->real == real && r->next_root < r->nroots)
+            cand.push_back(r);
+    if (cand.empty())
+        return TOR_OK;
+    // the oldest request always gets a quarter of the budget; the rest goes
+    // to the requests with the least remaining work
+    Request *oldest = *std::min_element(cand.begin(), cand.end(),
+                                        [](Request *a, Request *b) { return a->ticket < b->ticket; });
+    std::stable_sort(cand.begin(), cand.end(), [](Request *a, Request *b) {
+        return (a->nroots - a->next_root) * a->root_work < (b->nroots - b->next_root) * b->root_work;
+    });
+    long long budget = ctx->chunk_subsets;
+    std::vector<ProblemDesc> descs;
+    std::vector<Request *> used;
+    auto take = [&](Request *r, long long share) {
+        long long n = std::max(1ll, share / std::max(r->root_work, 1ll));
+        n = std::min(n, r->nroots - r->next_root);
+        ProblemDesc d{};
+        d.C = r->dC;
+        d.slots = r->dSlots;
+        d.N = r->N;
+        d.k = r->k;
+        d.root_begin = r->next_root;
+        d.nroots = n;
+        descs.push_back(d);
+        used.push_back(r);
+        r->next_root += n;
+        budget -= n * r->root_work;
+    };
+    take(oldest, budget / 4);
+    for (Request *r : cand) {
+        if (budget <= 0)
+            break;
+        if (r->next_root < r->nroots)
+            take(r, budget);
+    }
+    int Nmax = 0;
+    for (auto &d : descs)
+        Nmax = std::max(Nmax, d.N);
+    // reduce the requests that this launch completes
+    std::vector<int> red;
+    for (size_t i = 0; i < used.size(); i++)
+        if (used[i]->next_root == used[i]->nroots && std::find(used.begin(), used.begin() + i, used[i]) == used.begin() + i)
+            red.push_back((int)i);
+    std::vector<ProblemDesc> rdesc;
+    for (int i : red) {
+        ProblemDesc d = descs[i];
+        rdesc.push_back(d);
+    }
+    std::vector<double> res;
+    float ms = 0.f;
+    int rc = run_launch(ctx, real, descs, red, 0, launch_grid(ctx, real, Nmax), &res, &ms);
+    for (Request *r : used)
+        r->device_ms += ms / (float)used.size();
+    if (rc != TOR_OK) {
+        for (Request *r : used) {
+            r->res = tor_result{};
+            r->res.status = rc;
+            r->next_root = r->nroots;
+            if (std::find(finished.begin(), finished.end(), r) == finished.end())
+                finished.push_back(r);
+        }
+        return rc;
+    }
+    for (size_t j = 0; j < red.size(); j++) {
+        Request *r = used[red[j]];
+        fill_result(r->st, real, &res[4 * j], r->device_ms, &r->res);
+        finished.push_back(r);
+    }
+    return TOR_OK;
+}
+
+void serve_loop(tor_ctx *ctx)
+{
+    std::vector<Request *> active;
+    for (;;) {
+        std::vector<Request *> admit;
+        {
+            std::unique_lock<std::mutex> lk(ctx->smu);
+            ctx->scv.wait(lk, [&] { return ctx->stop || !ctx->pending.empty() || !active.empty(); });
+            if (ctx->stop)
+                return;
+            // admission by device footprint, in arrival order
+            while (!ctx->pending.empty()) {
+                Request *r = ctx->pending.front();
+                if (!ctx->pool) {
+                    if (hipSetDevice(ctx->device) != hipSuccess ||
+                        hipMalloc((void **)&ctx->pool, ctx->pool_bytes) != hipSuccess) {
+                        ctx->pool = nullptr;
+                        break;
+                    }
+                    ctx->pool_free.clear();
+                    ctx->pool_free[0] = ctx->pool_bytes;
+                }
+                size_t off;
+                const size_t len = request_bytes(*r);
+                if (!pool_alloc(ctx, len, off))
+                    break;
+                r->pool_off = off;
+                r->pool_len = len;
+                r->dC = ctx->pool + off;
+                r->dSlots = (double *)(ctx->pool + off + align_up((r->real ? sizeof(double) : sizeof(c64)) *
+                                                                       (size_t)NSZ(r->N), 256));
+                ctx->pending.pop_front();
+                admit.push_back(r);
+                ++ctx->admitted;
+            }
+        }
+        std::vector<Request *> finished;
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            hipError_t e = hipSetDevice(ctx->device);
+            for (Request *r : admit) {
+                const void *src = r->real ? (const void *)r->st.packed_r.data() : (const void *)r->st.packed.data();
+                const size_t bytes = (r->real ? sizeof(double) : sizeof(c64)) * (size_t)NSZ(r->N);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(r->dC, src, bytes, hipMemcpyHostToDevice, ctx->stream);
+                active.push_back(r);
+            }
+            if (e != hipSuccess) {
+                for (Request *r : admit) {
+                    r->res = tor_result{};
+                    r->res.status = hip_status(e);
+                    r->next_root = r->nroots;
+                    finished.push_back(r);
+                }
+            } else {
+                serve_round(ctx, true, active, finished);
+                serve_round(ctx, false, active, finished);
+            }
+        }
+        if (finished.empty() && admit.empty() && active.empty())
+            continue;
+        {
+            std::lock_guard<std::mutex> g(ctx->smu);
+            for (Request *r : finished) {
+                pool_release(ctx, r->pool_off, r->pool_len);
+                r->done = true;
+                --ctx->admitted;
+                active.erase(std::remove(active.begin(), active.end(), r), active.end());
+            }
+        }
+        ctx->scv.notify_all();
+    }
+}
+
+// ---- autotuning ------------------------------------------------------------
+
+int tune_one(tor_ctx *ctx, bool real, int n, TuneEntry &best)
+{
+    // timing does not depend on the values: I - O = I/2 has the Gaussian-state
+    // structure (real path) and is well inside the positive-definite cone
+    std::vector<double> O((size_t)2 * n * 2 * n * 2, 0.0);
+    for (int i = 0; i < 2 * n; i++)
+        O[2 * ((size_t)i * 2 * n + i)] = 0.5;
+    Staged st;
+    int rc = stage_matrix(n, O.data(), 2 * n, real ? 0u : (unsigned)TOR_FORCE_COMPLEX, CPLX_R, st);
+    if (rc != TOR_OK)
+        return rc;
+    if (st.real != real)
+        return TOR_E_INVAL;
+    const int N = modes_of(st, real);
+    const int LA = std::max(N - path_R(real), 0);
+    best = TuneEntry{};
+    const int wave_opts[4] = {2, 4, 6, 8};
+    for (int w : wave_opts) {
+        if (w > ctx->fit[real])
+            continue;
+        const int grid = ctx->num_cu * w;
+        int g = 1;
+        while ((1 << g) < grid)
+            ++g;
+        const int klo = std::min(LA, std::max(0, g - 1)), khi = std::min(LA, g + 3);
+        for (int k = klo; k <= khi; ++k) {
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 3; rep++) {
+                std::vector<Staged *> mats{&st};
+                std::vector<int> ks{k};
+                // run with this grid: temporarily pin the table entry
+                TuneEntry save = ctx->tune[real][std::min(N, MAX_N)];
+                ctx->tune[real][std::min(N, MAX_N)] = TuneEntry{true, k, w, 0.f};
+                std::vector<double> res;
+                float ms = 0.f;
+                rc = run_recursive(ctx, real, mats, ks, res, &ms, nullptr);
+                ctx->tune[real][std::min(N, MAX_N)] = save;
+                if (rc != TOR_OK)
+                    return rc;
+                if (rep > 0)
+                    tmin = std::min(tmin, ms);
+            }
+            if (!best.valid || tmin < best.ms)
+                best = TuneEntry{true, k, w, tmin};
+        }
+    }
+    return TOR_OK;
+}
 
 }  // namespace
 
@@ -534,11 +876,12 @@ size_t tor_workspace_size(int max_n, int split_k, int max_inflight)
         return 0;
     const int N = std::max(max_n, CPLX_R);
     const int k = split_k > 0 ? split_k : 14;
-    const long long items = (1ll << std::min(k, std::max(N - CPLX_R, 0))) * std::max(max_inflight, 1);
+    const int cnt = std::max(max_inflight, 1);
+    const long long items = (1ll << std::min(k, std::max(N - REAL_R, 0))) * cnt;
     const size_t grid = 256 * 8;
-    const size_t scr = align_up(sizeof(c64) * (size_t)std::max(Gsum(N - 1) - Gsum(CPLX_R - 1), 1ll), 256) * grid;
-    return align_up(sizeof(c64) * (size_t)NSZ(N), 256) * std::max(max_inflight, 1) + 4096 * (size_t)std::max(max_inflight, 1) +
-           256 + align_up(32 * (size_t)items, 256) + scr + (1 << 20);
+    const size_t scr = align_up(sizeof(c64) * (size_t)std::max(Gsum(N - 1) - Gsum(REAL_R - 1), 1ll), 256) * grid;
+    return align_up(sizeof(c64) * (size_t)NSZ(N), 256) * cnt + 2 * align_up(sizeof(ProblemDesc) * cnt, 256) + 256 +
+           align_up(32 * (size_t)items, 256) + align_up(32 * (size_t)cnt, 256) + scr + (1 << 20);
 }
 
 int tor_create(tor_ctx **out, const tor_options *opt)
@@ -552,7 +895,8 @@ int tor_create(tor_ctx **out, const tor_options *opt)
         o = *opt;
     if (o.max_n <= 0)
         o.max_n = 40;
-    if (o.max_n > MAX_N || o.split_k < 0 || o.split_k > 40 || o.waves_per_cu < 0 || o.waves_per_cu > 16)
+    if (o.max_n > MAX_N || o.split_k < 0 || o.split_k > 40 || o.waves_per_cu < 0 || o.waves_per_cu > 16 ||
+        (o.accum != TOR_ACCUM_DD && o.accum != TOR_ACCUM_FP64))
         return TOR_E_INVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0 || o.device < 0 || o.device >= ndev)
@@ -572,12 +916,14 @@ int tor_create(tor_ctx **out, const tor_options *opt)
         return TOR_E_DEVICE;
     }
     ctx->num_cu = prop.multiProcessorCount;
+    ctx->arch = prop.gcnArchName;
     // persistent grid: as many one-wave workgroups per CU as the LDS allows
     for (int real = 0; real < 2; real++) {
         const int lds = main_lds_bytes(real != 0);
         int fit = (int)(prop.maxSharedMemoryPerMultiProcessor / (size_t)std::max(lds, 1));
         fit = std::max(1, std::min(fit, 8));
-        const int w = o.waves_per_cu > 0 ? o.waves_per_cu : fit;
+        ctx->fit[real] = fit;
+        const int w = o.waves_per_cu > 0 ? std::min(o.waves_per_cu, fit) : fit;
         (real ? ctx->grid_r : ctx->grid) = ctx->num_cu * w;
         if (!real)
             ctx->waves_per_cu = w;
@@ -617,7 +963,7 @@ void tor_destroy(tor_ctx *ctx)
     }
     ctx->scv.notify_all();
     if (ctx->worker.joinable())
-        ctx->worker.join();
+        ctx->worker.join();  // the scheduler finishes its current launch first
     {
         std::lock_guard<std::mutex> g(ctx->mu);
         (void)hipSetDevice(ctx->device);
@@ -625,6 +971,8 @@ void tor_destroy(tor_ctx *ctx)
             (void)hipStreamSynchronize(ctx->stream);
         if (ctx->own_ws && ctx->ws)
             (void)hipFree(ctx->ws);
+        if (ctx->pool)
+            (void)hipFree(ctx->pool);
         if (ctx->ev0)
             (void)hipEventDestroy(ctx->ev0);
         if (ctx->ev1)
@@ -686,7 +1034,6 @@ int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max, 
             partials[3 * i + j] = slots[4 * i + j];
     return rc;
 }
-
 int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long mask_begin,
                    unsigned long long mask_end, tor_result *out)
 {
@@ -788,7 +1135,15 @@ int tor_submit(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long
         delete r;
         return rc;
     }
-    r->t_submit = std::chrono::steady_clock::now();
+    r->real = r->st.real;
+    r->N = modes_of(r->st, r->real);
+    r->k = choose_k(ctx, r->N, r->real);
+    r->nroots = 1ll << r->k;
+    r->root_work = 1ll << (r->N - r->k);
+    if (request_bytes(*r) > ctx->pool_bytes) {
+        delete r;
+        return TOR_E_NOMEM;
+    }
     {
         std::lock_guard<std::mutex> g(ctx->smu);
         if ((int)ctx->live.size() >= ctx->max_queue) {
@@ -825,7 +1180,7 @@ int tor_drain(tor_ctx *ctx, int timeout_ms)
     if (!ctx)
         return TOR_E_INVAL;
     std::unique_lock<std::mutex> lk(ctx->smu);
-    auto pred = [&] { return ctx->pending.empty() && ctx->inflight == 0; };
+    auto pred = [&] { return ctx->pending.empty() && ctx->admitted == 0; };
     if (timeout_ms < 0) {
         ctx->scv.wait(lk, pred);
         return TOR_OK;
@@ -833,56 +1188,91 @@ int tor_drain(tor_ctx *ctx, int timeout_ms)
     return ctx->scv.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred) ? TOR_OK : TOR_E_TIMEOUT;
 }
 
-}  // extern "C"
+// ---- autotuning ---------------------------------------------------------------
 
-namespace {
-
-// Continuous batching at launch granularity: whatever is pending when the
-// device becomes free goes into the next persistent launch; requests that
-// arrive meanwhile wait for the launch after it.
-void serve_loop(tor_ctx *ctx)
+int tor_autotune(tor_ctx *ctx, int n_min, int n_max, unsigned paths)
 {
-    for (;;) {
-        std::vector<Request *> batch;
-        {
-            std::unique_lock<std::mutex> lk(ctx->smu);
-            ctx->scv.wait(lk, [&] { return ctx->stop || !ctx->pending.empty(); });
-            if (ctx->pending.empty() && ctx->stop)
-                return;
-            while (!ctx->pending.empty()) {
-                batch.push_back(ctx->pending.front());
-                ctx->pending.pop_front();
-            }
-            ctx->inflight += (int)batch.size();
+    if (!ctx || n_min < 1 || n_max > ctx->opt.max_n || n_min > n_max || (paths & ~3u) || !paths)
+        return TOR_E_INVAL;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    for (int real = 1; real >= 0; real--) {
+        if (!(paths & (real ? TOR_TUNE_REAL : TOR_TUNE_COMPLEX)))
+            continue;
+        for (int n = n_min; n <= n_max; n++) {
+            TuneEntry best;
+            int rc = tune_one(ctx, real != 0, n, best);
+            if (rc != TOR_OK)
+                return rc;
+            const int N = std::max(n, path_R(real != 0));
+            ctx->tune[real][std::min(N, MAX_N)] = best;
         }
-        std::vector<Staged *> mats;
-        std::vector<int> idx;
-        std::vector<tor_result> res(batch.size());
-        for (size_t i = 0; i < batch.size(); i++) {
-            mats.push_back(&batch[i]->st);
-            idx.push_back((int)i);
-        }
-        int rc;
-        {
-            std::lock_guard<std::mutex> g(ctx->mu);
-            rc = run_staged(ctx, mats, idx, -1, res.data(), nullptr, nullptr);
-        }
-        {
-            std::lock_guard<std::mutex> g(ctx->smu);
-            for (size_t i = 0; i < batch.size(); i++) {
-                Request *r = batch[i];
-                if (rc == TOR_OK || rc == TOR_E_NUMERIC) {
-                    r->res = res[i];
-                } else {
-                    r->res = tor_result{};
-                    r->res.status = rc;
-                }
-                r->done = true;
-            }
-            ctx->inflight -= (int)batch.size();
-        }
-        ctx->scv.notify_all();
     }
+    return TOR_OK;
 }
 
-}  // namespace
+int tor_tune_save(tor_ctx *ctx, const char *path)
+{
+    if (!ctx || !path)
+        return TOR_E_INVAL;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    FILE *f = std::fopen(path, "w");
+    if (!f)
+        return TOR_E_INVAL;
+    std::fprintf(f, "{\"arch\": \"%s\", \"cus\": %d, \"entries\": [", ctx->arch.c_str(), ctx->num_cu);
+    bool first = true;
+    for (int real = 0; real < 2; real++)
+        for (int N = 0; N <= MAX_N; N++) {
+            const TuneEntry &t = ctx->tune[real][N];
+            if (!t.valid)
+                continue;
+            std::fprintf(f, "%s\n  {\"path\": \"%s\", \"modes\": %d, \"k\": %d, \"waves_per_cu\": %d, \"ms\": %.4f}",
+                         first ? "" : ",", real ? "real" : "complex", N, t.k, t.waves, (double)t.ms);
+            first = false;
+        }
+    std::fprintf(f, "\n]}\n");
+    std::fclose(f);
+    return TOR_OK;
+}
+
+int tor_tune_load(tor_ctx *ctx, const char *path)
+{
+    if (!ctx || !path)
+        return TOR_E_INVAL;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return TOR_E_INVAL;
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0)
+        txt.append(buf, got);
+    std::fclose(f);
+    // entries written by tor_tune_save; the cache is only taken for the same
+    // architecture and CU count
+    char arch[64] = {0};
+    int cus = 0;
+    const char *a = std::strstr(txt.c_str(), "\"arch\": \"");
+    const char *c = std::strstr(txt.c_str(), "\"cus\": ");
+    if (!a || !c || std::sscanf(a + 9, "%63[^\"]", arch) != 1 || std::sscanf(c + 7, "%d", &cus) != 1)
+        return TOR_E_INVAL;
+    if (ctx->arch != arch || cus != ctx->num_cu)
+        return TOR_E_INVAL;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const char *p = txt.c_str();
+    while ((p = std::strstr(p, "{\"path\": \"")) != nullptr) {
+        char kind[16] = {0};
+        int N = 0, k = 0, w = 0;
+        double ms = 0.0;
+        if (std::sscanf(p, "{\"path\": \"%15[^\"]\", \"modes\": %d, \"k\": %d, \"waves_per_cu\": %d, \"ms\": %lf}",
+                        kind, &N, &k, &w, &ms) != 5)
+            return TOR_E_INVAL;
+        if (N < 0 || N > MAX_N || k < 0 || w < 1 || w > 16)
+            return TOR_E_INVAL;
+        const int real = std::strcmp(kind, "real") == 0 ? 1 : 0;
+        ctx->tune[real][N] = TuneEntry{true, k, w, (float)ms};
+        ++p;
+    }
+    return TOR_OK;
+}
+
+}  // extern "C"

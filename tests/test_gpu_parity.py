@@ -262,3 +262,82 @@ def test_click_submatrices_of_a_40_mode_state(ctx):
         O = gen.click_submatrix(big, S)
         r, q = check(ctx, O, label=f"click pattern n={n}")
         assert r.path == 1
+
+
+def test_autotune_and_cache_roundtrip(tmp_path):
+    from paper_2109_04528_amd import Context, TOR_TUNE_REAL, TorError
+    say("case autotune n=12..16")
+    with Context(device=0) as c:
+        c.autotune(12, 16, TOR_TUNE_REAL)
+        p = str(tmp_path / "tune.json")
+        c.save_tuning(p)
+        import json
+        d = json.load(open(p))
+        assert d["arch"].startswith("gfx") and len(d["entries"]) == 5
+        O = gen.random_O(15, 1, 0.5, 1.0, 0.6)
+        a = c.eval(O)
+    with Context(device=0) as c2:
+        c2.load_tuning(p)
+        b = c2.eval(O)
+        bad = tmp_path / "bad.json"
+        bad.write_text('{"arch": "gfx000", "cus": 1, "entries": []}')
+        with pytest.raises(TorError):
+            c2.load_tuning(str(bad))
+    q = orc.tor(O, mode=orc.QUAD)
+    assert abs(a.value - q.value) <= term_bound(O, q.sum_abs)
+    assert (a.tor, a.tor_lo) == (b.tor, b.tor_lo)
+
+
+def test_batch_of_64_mixed_sizes_bitwise(ctx):
+    ns, Os = gen.batch_mix(64, 12, 20, seed=4)
+    say("case batch of 64, n in [12, 20]")
+    batch = ctx.eval_batch(Os)
+    for O, b in zip(Os[::7], batch[::7]):
+        s = ctx.eval(O)
+        assert (b.tor, b.tor_lo) == (s.tor, s.tor_lo)
+    O = Os[3]
+    q = orc.tor(O, mode=orc.F64)
+    assert abs(batch[3].value - q.value) <= term_bound(O, q.sum_abs)
+
+
+def test_serving_alone_equals_in_mix(ctx):
+    big = gen.random_O(40, 5001, 0.5, 1.0, 0.8)
+    rng = np.random.default_rng(3)
+    reqs = []
+    for i in range(40):
+        n = int(rng.integers(8, 23))
+        S = sorted(rng.choice(40, size=n, replace=False).tolist())
+        reqs.append(gen.click_submatrix(big, S))
+    say("case serving: 40 mixed requests in one stream")
+    tickets = [ctx.submit(O) for O in reqs]
+    got = {}
+    import time
+    t0 = time.time()
+    while len(got) < len(tickets) and time.time() - t0 < 120:
+        for t in tickets:
+            if t not in got:
+                r = ctx.poll(t)
+                if r is not None:
+                    got[t] = r
+        time.sleep(0.001)
+    assert len(got) == len(tickets)
+    for O, t in zip(reqs, tickets):
+        alone = ctx.eval(O)
+        assert got[t].status == 0
+        assert (got[t].tor, got[t].tor_lo) == (alone.tor, alone.tor_lo)
+
+
+def test_serving_errors(ctx):
+    from paper_2109_04528_amd import TorError, TOR_E_UNKNOWN, TOR_E_INVAL
+    say("case serving errors")
+    with pytest.raises(TorError) as ei:
+        ctx.poll(10 ** 12)
+    assert ei.value.code == TOR_E_UNKNOWN
+    with pytest.raises(TorError) as ei:
+        ctx.submit(gen.vacuum_O(41))
+    assert ei.value.code == TOR_E_INVAL
+    t = ctx.submit(gen.random_O(9, 1))
+    ctx.drain(60000)
+    assert ctx.poll(t) is not None
+    with pytest.raises(TorError):
+        ctx.poll(t)  # released after the first successful poll
