@@ -148,6 +148,14 @@ int tor_drain(tor_ctx *ctx, int timeout_ms);
  * third-order correction), then the two raw hardware seeds. */
 int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out);
 
+/* Serving policy.  Each serving launch runs at most chunk_subsets subsets
+ * (default 2^29, about 2.5 ms at n = 30 rates) taken from the admitted
+ * requests: oldest_share of it (default 0.5) goes to the oldest request, the
+ * rest to the requests with the least remaining work.  max_queue bounds the
+ * requests held (admitted or waiting); tor_submit beyond it returns
+ * TOR_E_BUSY.  Applies from the next launch on. */
+int tor_serve_config(tor_ctx *ctx, long long chunk_subsets, double oldest_share, int max_queue);
+
 /* Autotuner.  For every n in [n_min, n_max] and each selected path
  * (TOR_TUNE_REAL: Gaussian-state matrices, TOR_TUNE_COMPLEX: general ones)
  * time the recursive kernel over split depths k and persistent waves per CU

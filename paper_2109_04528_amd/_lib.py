@@ -39,6 +39,7 @@ EXPORTS = [
     "tor_default_options", "tor_create", "tor_destroy", "tor_workspace_size", "tor_eval",
     "tor_eval_batch", "tor_eval_plain", "tor_eval_partials", "tor_submit", "tor_poll",
     "tor_drain", "tor_debug_math", "tor_strerror", "tor_autotune", "tor_tune_save", "tor_tune_load",
+    "tor_serve_config",
 ]
 
 TOR_TUNE_REAL = 0x1
@@ -113,6 +114,8 @@ def load(path: str = LIB_PATH):
     lib.tor_drain.restype = ctypes.c_int
     lib.tor_debug_math.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]
     lib.tor_debug_math.restype = ctypes.c_int
+    lib.tor_serve_config.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_double, ctypes.c_int]
+    lib.tor_serve_config.restype = ctypes.c_int
     lib.tor_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint]
     lib.tor_autotune.restype = ctypes.c_int
     lib.tor_tune_save.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
@@ -286,6 +289,12 @@ class Context:
         rc = self._lib.tor_drain(self._h, timeout_ms)
         if rc != TOR_OK:
             raise TorError(rc, "tor_drain")
+
+    def serve_config(self, chunk_subsets: int = 1 << 29, oldest_share: float = 0.5,
+                     max_queue: int = 1 << 16) -> None:
+        rc = self._lib.tor_serve_config(self._h, chunk_subsets, oldest_share, max_queue)
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_serve_config")
 
     def autotune(self, n_min: int, n_max: int, paths: int = TOR_TUNE_REAL | TOR_TUNE_COMPLEX) -> None:
         rc = self._lib.tor_autotune(self._h, n_min, n_max, paths)

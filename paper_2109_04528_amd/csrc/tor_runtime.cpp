@@ -107,6 +107,7 @@ struct tor_ctx {
     int admitted = 0;
     int max_queue = 1 << 16;
     long long chunk_subsets = 1ll << 29;  // work per serving launch
+    double oldest_share = 0.5;            // of it, guaranteed to the oldest request
     char *pool = nullptr;
     size_t pool_bytes = 256ull << 20;
     std::map<size_t, size_t> pool_free;  // offset -> length
@@ -523,6 +524,30 @@ int copy_input_to_host(int n, const double *O, long ld, unsigned flags, std::vec
     return TOR_OK;
 }
 
+// Split depths for a launch of several matrices: roots of about equal work,
+// about four per persistent wave over the whole launch (a lone matrix keeps
+// its own tuned or default depth).
+void batch_ks(const tor_ctx *ctx, bool real, const std::vector<Staged *> &grp, std::vector<int> &ks)
+{
+    if (grp.size() == 1 || ctx->opt.split_k > 0) {
+        for (size_t j = 0; j < grp.size(); j++)
+            ks[j] = choose_k(ctx, modes_of(*grp[j], real), real);
+        return;
+    }
+    double work = 0.0;
+    int Nmax = 0;
+    for (Staged *m : grp) {
+        work += std::ldexp(1.0, modes_of(*m, real));
+        Nmax = std::max(Nmax, modes_of(*m, real));
+    }
+    const double per_root = std::max(work / (4.0 * launch_grid(ctx, real, Nmax)), 1.0);
+    const int lg = (int)std::floor(std::log2(per_root) + 0.5);
+    for (size_t j = 0; j < grp.size(); j++) {
+        const int N = modes_of(*grp[j], real);
+        ks[j] = std::max(0, std::min(N - lg, N - path_R(real)));
+    }
+}
+
 // Launch the staged matrices, one launch per arithmetic path.
 int run_staged(tor_ctx *ctx, std::vector<Staged *> &mats, const std::vector<int> &idx, int fixed_k,
                tor_result *out, std::vector<double> *slots_out, int *k_out)
@@ -537,10 +562,12 @@ int run_staged(tor_ctx *ctx, std::vector<Staged *> &mats, const std::vector<int>
                 grp.push_back(mats[j]);
                 gidx.push_back(idx[j]);
                 const int N = modes_of(*mats[j], real);
-                ks.push_back(fixed_k >= 0 ? std::min(fixed_k, std::max(N - path_R(real), 0)) : choose_k(ctx, N, real));
+                ks.push_back(std::min(std::max(fixed_k, 0), std::max(N - path_R(real), 0)));
             }
         if (grp.empty())
             continue;
+        if (fixed_k < 0)
+            batch_ks(ctx, real, grp, ks);
         std::vector<double> res;
         float ms = 0.f;
         int rc = run_recursive(ctx, real, grp, ks, res, &ms, slots_out);
@@ -561,27 +588,45 @@ int eval_many(tor_ctx *ctx, int count, const int *n, const double *const *O, con
               int fixed_k, std::vector<double> *slots_out, int *k_out)
 {
     std::vector<Staged> st(count);
-    std::vector<Staged *> ok;
-    std::vector<int> idx;
-    int first_err = TOR_OK;
-    for (int i = 0; i < count; i++) {
+    std::vector<int> rcs(count, TOR_OK);
+    // host staging (validation, HPD check, packing) of a batch on a few threads
+    auto stage_one = [&](int i) {
         if (n[i] > ctx->opt.max_n) {
-            out[i] = tor_result{};
-            out[i].status = TOR_E_INVAL;
-            if (first_err == TOR_OK)
-                first_err = TOR_E_INVAL;
-            continue;
+            rcs[i] = TOR_E_INVAL;
+            return;
         }
         std::vector<double> tmp;
         const double *host;
         int rc = copy_input_to_host(n[i], O ? O[i] : nullptr, ld ? ld[i] : 0, ctx->opt.flags, tmp, host);
         if (rc == TOR_OK)
             rc = stage_matrix(n[i], host, ld ? ld[i] : 0, ctx->opt.flags, CPLX_R, st[i]);
-        if (rc != TOR_OK) {
+        rcs[i] = rc;
+    };
+    const int nthr = (count >= 8 && !(ctx->opt.flags & TOR_INPUT_DEVICE))
+                         ? (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()))
+                         : 1;
+    if (nthr <= 1) {
+        for (int i = 0; i < count; i++)
+            stage_one(i);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthr; t++)
+            pool.emplace_back([&, t] {
+                for (int i = t; i < count; i += nthr)
+                    stage_one(i);
+            });
+        for (auto &th : pool)
+            th.join();
+    }
+    std::vector<Staged *> ok;
+    std::vector<int> idx;
+    int first_err = TOR_OK;
+    for (int i = 0; i < count; i++) {
+        if (rcs[i] != TOR_OK) {
             out[i] = tor_result{};
-            out[i].status = rc;
+            out[i].status = rcs[i];
             if (first_err == TOR_OK)
-                first_err = rc;
+                first_err = rcs[i];
             continue;
         }
         ok.push_back(&st[i]);
@@ -630,6 +675,17 @@ void pool_release(tor_ctx *ctx, size_t off, size_t len)
     }
 }
 
+// Split depth of a served request: roots of at most a quarter-wave share of
+// one launch's budget, so that no single root outlasts the launch it is in.
+int serve_k(const tor_ctx *ctx, const Request &r)
+{
+    const int LA = std::max(r.N - path_R(r.real), 0);
+    const double per_root = std::max((double)ctx->chunk_subsets / (4.0 * launch_grid(ctx, r.real, r.N)), 1.0);
+    const int lg = (int)std::floor(std::log2(per_root));
+    const int k = std::max(choose_k(ctx, r.N, r.real), r.N - lg);
+    return std::max(0, std::min(k, std::min(LA, 20)));
+}
+
 size_t request_bytes(const Request &r)
 {
     const size_t esz = r.real ? sizeof(double) : sizeof(c64);
@@ -671,7 +727,7 @@ int serve_round(tor_ctx *ctx, bool real, std::vector<Request *> &active, std::ve
         r->next_root += n;
         budget -= n * r->root_work;
     };
-    take(oldest, budget / 4);
+    take(oldest, (long long)(ctx->oldest_share * (double)budget));
     for (Request *r : cand) {
         if (budget <= 0)
             break;
@@ -727,6 +783,9 @@ void serve_loop(tor_ctx *ctx)
             // admission by device footprint, in arrival order
             while (!ctx->pending.empty()) {
                 Request *r = ctx->pending.front();
+                r->k = serve_k(ctx, *r);
+                r->nroots = 1ll << r->k;
+                r->root_work = 1ll << (r->N - r->k);
                 if (!ctx->pool) {
                     if (hipSetDevice(ctx->device) != hipSuccess ||
                         hipMalloc((void **)&ctx->pool, ctx->pool_bytes) != hipSuccess) {
@@ -1137,9 +1196,8 @@ int tor_submit(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long
     }
     r->real = r->st.real;
     r->N = modes_of(r->st, r->real);
-    r->k = choose_k(ctx, r->N, r->real);
+    r->k = std::min(std::max(r->N - path_R(r->real), 0), 20);  // largest split admission may choose
     r->nroots = 1ll << r->k;
-    r->root_work = 1ll << (r->N - r->k);
     if (request_bytes(*r) > ctx->pool_bytes) {
         delete r;
         return TOR_E_NOMEM;
@@ -1186,6 +1244,17 @@ int tor_drain(tor_ctx *ctx, int timeout_ms)
         return TOR_OK;
     }
     return ctx->scv.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred) ? TOR_OK : TOR_E_TIMEOUT;
+}
+
+int tor_serve_config(tor_ctx *ctx, long long chunk_subsets, double oldest_share, int max_queue)
+{
+    if (!ctx || chunk_subsets < 1024 || !(oldest_share >= 0.0 && oldest_share <= 1.0) || max_queue < 1)
+        return TOR_E_INVAL;
+    std::lock_guard<std::mutex> g(ctx->smu);
+    ctx->chunk_subsets = chunk_subsets;
+    ctx->oldest_share = oldest_share;
+    ctx->max_queue = max_queue;
+    return TOR_OK;
 }
 
 // ---- autotuning ---------------------------------------------------------------
