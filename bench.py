@@ -27,6 +27,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Tor evals/s + subset dets/s at n=30 FP64; p50/p99 latency, mixed-n stream"
+KERNEL_SOURCES = ["paper_2109_04528_amd/csrc/tor_kernels.hip", "paper_2109_04528_amd/csrc/tor_device.hpp",
+                  "paper_2109_04528_amd/csrc/tor_internal.hpp"]
+TRAFFIC_FILE = "profiles/tor_main_real_n30_traffic.md"
+COPY_BYTES = 256 << 20  # calibration copy for the HBM counters
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per launch of the recursive kernel measured with rocprofv3
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size), valid only
+    while the kernel sources are the ones that were profiled."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
 
 
@@ -127,6 +159,8 @@ def main():
     ap.add_argument("--serve", type=int, default=4096, help="requests in the mixed-n stream (0: skip)")
     ap.add_argument("--batch", type=int, default=512, help="matrices in the batched launch (0: skip)")
     ap.add_argument("--n34", type=int, default=1, help="also time one n=34 Torontonian")
+    ap.add_argument("--profile-traffic", action="store_true",
+                    help="one n=30 Torontonian and one 256 MiB device copy, for the HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -143,6 +177,16 @@ def main():
     O = inputs.random_O(n, 0, 0.3, 1.2, 0.9)
     print(f"bench: n={n} workload staged", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
+    if args.profile_traffic:
+        with Context(device=0) as c:
+            c.eval(O)
+        src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_traffic": True, "copy_bytes": COPY_BYTES,
+                          "kernel_source_sha256": kernel_source_hash()}), flush=True)
+        return
     stream = torch.cuda.Stream(device=dev)
     ws = torch.empty(workspace_size(max(n, 32), 0, 4), dtype=torch.uint8, device=dev)
     ctx = Context(device=0, stream=stream, workspace=ws)
@@ -237,7 +281,7 @@ def main():
         "tor": r.value,
         "cancellation_R": r.cancellation,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": stored_traffic() if real_path else None,
                      "flop_per_launch": flops,
                      "kernel": "tor_main<double, T=4, B=6>" if real_path else "tor_main<c64, T=3, B=6>"},
         "plain": plain,
