@@ -62,7 +62,7 @@ def stored_traffic():
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
 
 
-def cpu_baseline(O, n, budget_s=15.0):
+def cpu_baseline(O, n, budget_s=12.0):
     """The CPU oracle (as it stands) on a subtree of the workload: modes
     0..k-1 fixed to an alternating include pattern, the rest enumerated."""
     from oracle import oracle as orc
@@ -76,9 +76,11 @@ def cpu_baseline(O, n, budget_s=15.0):
         r = orc.tor(O, mode=orc.F64, threads=cores, fix_mask=fix_mask, fix_val=fix_val)
         return time.perf_counter() - t0, r.count, k
 
-    dt, cnt, _ = run(12)
+    # a calibration run long enough that thread start-up does not dominate,
+    # then the subtree whose size is nearest the budget (0.7x..1.4x of it)
+    dt, cnt, _ = run(min(18, n - 2))
     rate = cnt / max(dt, 1e-9)
-    m = int(math.floor(math.log2(max(rate * budget_s, 1 << 12))))
+    m = int(round(math.log2(max(rate * budget_s, 1 << 12))))
     m = max(12, min(m, n - 2))
     dt, cnt, k = run(m)
     dets = cnt / dt
@@ -151,11 +153,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--plain-masks", type=int, default=1 << 18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--serve", type=int, default=4096, help="requests in the mixed-n stream (0: skip)")
     ap.add_argument("--batch", type=int, default=512, help="matrices in the batched launch (0: skip)")
     ap.add_argument("--n34", type=int, default=1, help="also time one n=34 Torontonian")
@@ -283,7 +285,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": stored_traffic() if real_path else None,
                      "flop_per_launch": flops,
-                     "kernel": "tor_main<double, T=4, B=6>" if real_path else "tor_main<c64, T=3, B=6>"},
+                     "kernel": "tor_main<double, T=5, B=6, L=2>" if real_path else "tor_main<c64, T=3, B=6, L=2>"},
         "plain": plain,
         "batch": batch,
         "n34": big,

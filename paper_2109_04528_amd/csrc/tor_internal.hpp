@@ -65,13 +65,14 @@ __host__ __device__ constexpr long long slot_off(int N, int l) { return Gsum(N -
 // registers (the first B - L are expanded in LDS).
 constexpr int CPLX_T = 3;
 constexpr int CPLX_B = 6;
-constexpr int CPLX_L = 1;
+constexpr int CPLX_L = 2;
 constexpr int CPLX_R = CPLX_T + CPLX_B;
-constexpr int REAL_T = 4;
+constexpr int REAL_T = 5;
 constexpr int REAL_B = 6;
 constexpr int REAL_L = 2;
 constexpr int REAL_R = REAL_T + REAL_B;
 constexpr int MAX_N = 48;
+constexpr int MAX_FIT = 8;  // persistent one-wave workgroups per CU, at most
 
 // host-side launchers (defined in tor_kernels.hip)
 hipError_t launch_main(bool real_path, bool dd, const MainParams &p, int grid, hipStream_t s);
@@ -80,6 +81,7 @@ hipError_t launch_zero(unsigned long long *p, int count, hipStream_t s);
 hipError_t launch_plain(const PlainParams &p, int grid, hipStream_t s);
 hipError_t launch_plain_reduce(const double *partials, int nwaves, double *result, hipStream_t s);
 hipError_t launch_math_probe(const double *x, double *out, int count, hipStream_t s);
-int main_lds_bytes(bool real_path);
+// resident one-wave workgroups of the main kernel per CU (0 on error)
+int main_occupancy(bool real_path);
 
 }  // namespace tor

@@ -23,11 +23,13 @@
 //    changes the path is one wave-parallel rank-2 update, stacked per level
 //    in a private global scratch area (L2-resident);
 //  * tier B: from each tier-A leaf (R = T + B modes left) the wave expands
-//    B-1 levels breadth first in LDS, every include node of a level updated
+//    B-L levels breadth first in LDS, every include node of a level updated
 //    together (all lanes busy);
-//  * tier C: lane l takes node l of level B (its parent is an LDS node of
-//    level B-1; odd lanes include, even lanes exclude that mode) and finishes
-//    the last T modes alone in registers: 2^T subsets per lane.
+//  * tier C: lane l takes node l of level B.  Its ancestor of level B-L is
+//    an LDS node; the lane makes the last L decisions itself (an exclude is
+//    a zero update, so all lanes run the same code), fused into one pass over
+//    that node, and finishes the last T modes alone in registers: 2^T
+//    subsets per lane.
 // Terms are summed per lane in double-double, reduced over the wave, and
 // written to the root's partial slot; a second kernel sums the slots of each
 // matrix in index order.
@@ -280,17 +282,20 @@ __device__ __forceinline__ void tail(const S *h, double det, double sgn, Acc &ac
     }
 }
 
-// one lane-level decision on a register node of M modes: include its highest
-// mode (the rank-2 update) or exclude it (the same code with a zero update,
-// which copies the prefix exactly), so that both kinds of lanes run the same
-// instructions.
-template <class S, int M>
-__device__ __forceinline__ double lane_step(const S *h, bool inc, S *hn, int &bad)
+// element (x, y), y <= x, of an LDS node in block layout
+template <class S>
+__device__ __forceinline__ S node_el(const S *node, int x, int y)
 {
-    constexpr int p = 2 * M - 2;
-    const double a = re(h[pidx(p, p)]);
-    const S b = h[pidx(p + 1, p)];
-    const double g = re(h[pidx(p + 1, p + 1)]);
+    return node[4 * bidx(x >> 1, y >> 1) + ((x & 1) << 1) + (y & 1)];
+}
+
+// pivot of one lane-level decision: an include lane takes the 2x2 pivot, an
+// exclude lane a zero update (inverses and beta/alpha zero, determinant 1),
+// which leaves the prefix exactly as it is, so that both kinds of lanes run
+// the same instructions.
+template <class S>
+__device__ __forceinline__ Piv<S> lane_pivot(double a, S b, double g, bool inc, int &bad)
+{
     Piv<S> pq = pivot(a, b, g);
     if (inc && (!(a > 0.0) || !(pq.pdet > 0.0)))
         bad = 1;
@@ -300,43 +305,87 @@ __device__ __forceinline__ double lane_step(const S *h, bool inc, S *hn, int &ba
         pq.ba = zero_of(b);
         pq.pdet = 1.0;
     }
-    elim_regs<S, M>(h, pq, hn);
-    return pq.pdet;
+    return pq;
 }
 
 // tier C: lane l finishes node l of level B.  Its ancestor of level B-L is an
-// LDS node; the lane takes the last L decisions itself (bit L-1-j of l is the
-// decision at level B-L+1+j) and then the last T modes.
+// LDS node of T+L modes; the lane takes the last L decisions itself (bit
+// L-1-j of l is the decision at level B-L+1+j) and then the last T modes.
+// The L lane levels are fused into one pass over the LDS node: the pivot
+// rows of every level are formed first, then each remaining entry is read
+// once and receives the L rank-2 updates in turn, so only the pivot rows and
+// the T-mode result are held in registers.
 template <class S, int T, int B, int L, class Acc>
 __device__ __forceinline__ void tierC(const S *bufB, const double *ndet, const uint16_t *srcOff,
                                       const uint8_t *srcDet, double leafDet, int leafInc, int N, int lane, Acc &acc,
                                       int &bad)
 {
+    static_assert(L == 1 || L == 2, "one or two lane levels");
     constexpr int NP = (1 << (B - L)) - 1;  // table base of level B-L
+    constexpr int pT = 2 * T;               // rows of the T-mode result
+    constexpr int p1 = 2 * (T + L) - 2;     // pivot rows of the first lane level
     const int ip = lane >> L;
     const S *src = bufB + srcOff[NP + ip];
     const int di = srcDet[NP + ip];
     double det = di == 0xff ? leafDet : ndet[di];
-    // block layout -> packed lower triangle in registers (T+L modes)
-    S h[E(T + L)];
+    const bool inc1 = (lane >> (L - 1)) & 1;  // first lane level
+    const bool inc0 = lane & 1;               // second (L == 2)
+
+    // first level: pivot of mode T+L-1 and its rows, r2 in LDL form
+    const Piv<S> q1 = lane_pivot(re(node_el(src, p1, p1)), node_el(src, p1 + 1, p1), re(node_el(src, p1 + 1, p1 + 1)),
+                                 inc1, bad);
+    S r1[p1], r2[p1];
 #pragma unroll
-    for (int x = 0; x < 2 * (T + L); ++x)
+    for (int y = 0; y < p1; ++y) {
+        r1[y] = node_el(src, p1, y);
+        r2[y] = sub_mul(node_el(src, p1 + 1, y), r1[y], q1.ba);
+    }
+    det *= q1.pdet;
+    int includes = leafInc + __popc(ip) + inc1;
+
+    // second level (L == 2): its pivot rows are rows pT, pT+1 of the first
+    // child, formed here from the node and the first level's rows
+    Piv<S> q2;
+    S s1[pT], s2[pT];
+    if constexpr (L == 2) {
+        S c[2][pT + 2];
 #pragma unroll
-        for (int y = 0; y <= x; ++y)
-            h[pidx(x, y)] = src[4 * bidx(x >> 1, y >> 1) + ((x & 1) << 1) + (y & 1)];
-    int includes = leafInc + __popc(ip);
+        for (int x = pT; x < pT + 2; ++x) {
+            const S u1 = scale(r1[x], q1.inv_a), u2 = scale(r2[x], q1.inv_g);
+#pragma unroll
+            for (int y = 0; y <= x; ++y) {
+                const S v = node_el(src, x, y);
+                c[x - pT][y] = (x == y) ? upd_diag(v, u1, r1[y], u2, r2[y]) : upd(v, u1, r1[y], u2, r2[y]);
+            }
+        }
+        q2 = lane_pivot(re(c[0][pT]), c[1][pT], re(c[1][pT + 1]), inc0, bad);
+#pragma unroll
+        for (int y = 0; y < pT; ++y) {
+            s1[y] = c[0][y];
+            s2[y] = sub_mul(c[1][y], s1[y], q2.ba);
+        }
+        det *= q2.pdet;
+        includes += inc0;
+    }
+
+    // the T-mode result: every entry read once, updated level by level
     S hT[E(T)];
-    if constexpr (L == 1) {
-        const bool inc = lane & 1;
-        det *= lane_step<S, T + 1>(h, inc, hT, bad);
-        includes += inc;
-    } else {
-        static_assert(L == 2, "one or two lane levels");
-        S h1[E(T + 1)];
-        const bool inc1 = (lane >> 1) & 1, inc0 = lane & 1;
-        det *= lane_step<S, T + 2>(h, inc1, h1, bad);
-        det *= lane_step<S, T + 1>(h1, inc0, hT, bad);
-        includes += inc1 + inc0;
+#pragma unroll
+    for (int x = 0; x < pT; ++x) {
+        const S u1 = scale(r1[x], q1.inv_a), u2 = scale(r2[x], q1.inv_g);
+        S w1, w2;
+        if constexpr (L == 2) {
+            w1 = scale(s1[x], q2.inv_a);
+            w2 = scale(s2[x], q2.inv_g);
+        }
+#pragma unroll
+        for (int y = 0; y <= x; ++y) {
+            const S v = node_el(src, x, y);
+            S o = (x == y) ? upd_diag(v, u1, r1[y], u2, r2[y]) : upd(v, u1, r1[y], u2, r2[y]);
+            if constexpr (L == 2)
+                o = (x == y) ? upd_diag(o, w1, s1[y], w2, s2[y]) : upd(o, w1, s1[y], w2, s2[y]);
+            hT[pidx(x, y)] = o;
+        }
     }
     const int excluded = (N - T) - includes;
     const double sgn = (excluded & 1) ? -1.0 : 1.0;
@@ -680,18 +729,14 @@ hipError_t launch_main(bool real_path, bool dd, const MainParams &p, int grid, h
     return hipGetLastError();
 }
 
-template <class S, int T, int B, int L>
-constexpr int lds_bytes()
+int main_occupancy(bool real_path)
 {
-    constexpr int R = T + B, BL = B - L;
-    return (int)(sizeof(S) * (offB<R>(BL + 1) + (1 << (BL - 1))) +
-                 sizeof(double) * (2 * (1 << (BL - 1)) + (1 << BL)) + 3 * ((1 << (BL + 1)) - 1) + 2 * NB(R - 1) +
-                 (sizeof(double) + sizeof(int)) * (MAX_N + 1));
-}
-
-int main_lds_bytes(bool real_path)
-{
-    return real_path ? lds_bytes<double, REAL_T, REAL_B, REAL_L>() : lds_bytes<c64, CPLX_T, CPLX_B, CPLX_L>();
+    int n = 0;
+    hipError_t e = real_path ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                   &n, tor_main<double, REAL_T, REAL_B, REAL_L, AccDD>, 64, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                   &n, tor_main<c64, CPLX_T, CPLX_B, CPLX_L, AccDD>, 64, 0);
+    return e == hipSuccess ? n : 0;
 }
 
 hipError_t launch_reduce(const ProblemDesc *probs, int nprob, double *results, bool dd, hipStream_t s)

@@ -497,11 +497,15 @@ void fill_result(const Staged &st, bool real, const double *r, float ms, tor_res
     std::memset(out, 0, sizeof(*out));
     out->tor = r[0];
     out->tor_lo = r[1];
-    out->sum_abs = r[2];
+    // a padding mode (its block of I - O is I/2) turns each term t into the
+    // pair -t, +2t: Tor is unchanged and the padded sum of |t| is 3 times the
+    // input's, so it is scaled back (3^pad is exact for pad < 34)
+    const int pad = (real ? st.Nr : st.N) - st.n;
+    out->sum_abs = pad > 0 ? r[2] / std::pow(3.0, pad) : r[2];
     const double v = std::fabs(r[0] + r[1]);
     // each term carries a relative rounding error of a few units of roundoff
     // per factorisation step; independent errors add in quadrature
-    const double R = v > 0.0 ? r[2] / v : INFINITY;
+    const double R = v > 0.0 ? out->sum_abs / v : INFINITY;
     out->err_est = kU * (double)std::max(st.n, 1) * R / std::sqrt(std::ldexp(1.0, st.n));
     out->subsets = 1ull << st.n;
     out->status = (r[3] != 0.0 || !std::isfinite(r[0])) ? TOR_E_NUMERIC : TOR_OK;
@@ -933,12 +937,15 @@ size_t tor_workspace_size(int max_n, int split_k, int max_inflight)
 {
     if (max_n < 0 || max_n > MAX_N)
         return 0;
-    const int N = std::max(max_n, CPLX_R);
+    // bounds over both paths: the smaller R has more roots and a deeper
+    // tier-A stack; complex scalars; at most MAX_FIT waves on each of 256 CUs
+    const int Rmin = std::min(REAL_R, CPLX_R);
+    const int N = std::max(max_n, std::max(REAL_R, CPLX_R));
     const int k = split_k > 0 ? split_k : 14;
     const int cnt = std::max(max_inflight, 1);
-    const long long items = (1ll << std::min(k, std::max(N - REAL_R, 0))) * cnt;
-    const size_t grid = 256 * 8;
-    const size_t scr = align_up(sizeof(c64) * (size_t)std::max(Gsum(N - 1) - Gsum(REAL_R - 1), 1ll), 256) * grid;
+    const long long items = (1ll << std::min(k, std::max(N - Rmin, 0))) * cnt;
+    const size_t grid = 256 * MAX_FIT;
+    const size_t scr = align_up(sizeof(c64) * (size_t)std::max(Gsum(N - 1) - Gsum(Rmin - 1), 1ll), 256) * grid;
     return align_up(sizeof(c64) * (size_t)NSZ(N), 256) * cnt + 2 * align_up(sizeof(ProblemDesc) * cnt, 256) + 256 +
            align_up(32 * (size_t)items, 256) + align_up(32 * (size_t)cnt, 256) + scr + (1 << 20);
 }
@@ -976,11 +983,15 @@ int tor_create(tor_ctx **out, const tor_options *opt)
     }
     ctx->num_cu = prop.multiProcessorCount;
     ctx->arch = prop.gcnArchName;
-    // persistent grid: as many one-wave workgroups per CU as the LDS allows
+    // persistent grid: as many one-wave workgroups per CU as the kernel's
+    // registers and LDS allow
     for (int real = 0; real < 2; real++) {
-        const int lds = main_lds_bytes(real != 0);
-        int fit = (int)(prop.maxSharedMemoryPerMultiProcessor / (size_t)std::max(lds, 1));
-        fit = std::max(1, std::min(fit, 8));
+        int fit = main_occupancy(real != 0);
+        if (fit <= 0) {
+            delete ctx;
+            return TOR_E_DEVICE;
+        }
+        fit = std::min(fit, MAX_FIT);
         ctx->fit[real] = fit;
         const int w = o.waves_per_cu > 0 ? std::min(o.waves_per_cu, fit) : fit;
         (real ? ctx->grid_r : ctx->grid) = ctx->num_cu * w;
@@ -1088,9 +1099,14 @@ int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max, 
         return rc;
     *out = r;
     *k_out = k;
-    for (long long i = 0; i < (1ll << k); i++)
-        for (int j = 0; j < 3; j++)
-            partials[3 * i + j] = slots[4 * i + j];
+    // padding modes scale each partial's sum of |t| by 3 (see fill_result)
+    const int pad = std::max(n, path_R(r.path == 1)) - n;
+    const double p3 = std::pow(3.0, pad);
+    for (long long i = 0; i < (1ll << k); i++) {
+        partials[3 * i] = slots[4 * i];
+        partials[3 * i + 1] = slots[4 * i + 1];
+        partials[3 * i + 2] = pad > 0 ? slots[4 * i + 2] / p3 : slots[4 * i + 2];
+    }
     return rc;
 }
 int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long mask_begin,

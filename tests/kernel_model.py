@@ -168,4 +168,4 @@ def model_tor(O: np.ndarray, T: int = 3, B: int = 6, k: int = 0, real: bool = Fa
                     includes += inc
                 excluded = (N - T) - includes
                 tail(h, T, det, -1.0 if excluded & 1 else 1.0, terms)
-    return math.fsum(terms), len(terms)
+    return math.fsum(terms), len(terms), math.fsum(abs(t) for t in terms)

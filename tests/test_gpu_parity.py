@@ -61,6 +61,10 @@ def check(ctx, O, mode=orc.QUAD, label=""):
         f"bound_rel={bound / max(abs(q.value), 1e-300):.3e} ms={r.device_ms:.3f}")
     assert r.status == 0
     assert err <= bound, (label, r.value, q.value, err, bound)
+    # sum of |t| over the input's own subsets (padding modes scale it by 3
+    # each on the device; the library divides that back out)
+    n = O.shape[0] // 2
+    assert abs(r.sum_abs - q.sum_abs) <= max(1e-9, 8.0 * max(n, 9) * kappa(O) * U) * q.sum_abs
     return r, q
 
 

@@ -8,30 +8,37 @@ from oracle import oracle as orc
 from paper_2109_04528_amd import inputs as gen
 
 
+# the complex path: T = 3 register modes, B = 6 (64 lanes), L = 2 lane levels
 @pytest.mark.parametrize("n,k", [(0, 0), (1, 0), (5, 0), (9, 0), (10, 1), (11, 2), (12, 3)])
 def test_model_matches_oracle(n, k):
     O = gen.random_O(n, 3 + n, 0.5, 1.0, 0.7) if n else gen.vacuum_O(0)
-    v, cnt = model_tor(O, 3, 6, k)
+    v, cnt, sabs = model_tor(O, 3, 6, k, L=2)
     q = orc.tor(O, mode=orc.QUAD)
     assert cnt == 1 << max(n, 9)
     tol = 64 * 1.1e-16 * max(n, 9) * q.sum_abs
     assert abs(v - q.value) <= tol, (v, q.value, tol)
+    # each padding mode (block I/2) turns a term t into -t and +2t
+    pad = max(n, 9) - n
+    assert abs(sabs - 3.0 ** pad * q.sum_abs) <= 1e-12 * sabs
 
 
 def test_model_product_state_closed_form():
     r = np.array([0.6, 0.8, 1.0, 0.7, 0.9, 0.55, 0.65, 0.75, 0.85, 0.95, 0.5])
     O = gen.product_state_O(r, 0.6, np.arange(11.0))
-    v, _ = model_tor(O, 3, 6, 1)
+    v, _, _ = model_tor(O, 3, 6, 1, L=1)
     single = np.sqrt(1 + 0.6 * 1.4 * np.sinh(r) ** 2)
     want = float(np.prod(single - 1))
     sum_abs = float(np.prod(single + 1))  # sum of |terms| of a product state
     assert abs(v - want) <= 64 * 1.1e-16 * 11 * sum_abs
 
 
-@pytest.mark.parametrize("n,k", [(4, 0), (10, 0), (11, 1), (12, 2)])
+# the real path: T = 5, B = 6, L = 2
+@pytest.mark.parametrize("n,k", [(4, 0), (11, 0), (12, 1), (13, 2)])
 def test_real_form_model_matches_oracle(n, k):
     O = gen.random_O(n, 50 + n, 0.3, 1.2, 0.9)
-    v, cnt = model_tor(O, 4, 6, k, real=True, L=2)
+    v, cnt, sabs = model_tor(O, 5, 6, k, real=True, L=2)
     q = orc.tor(O, mode=orc.QUAD)
-    assert cnt == 1 << max(n, 10)
-    assert abs(v - q.value) <= 64 * 1.1e-16 * max(n, 10) * q.sum_abs, (v, q.value)
+    assert cnt == 1 << max(n, 11)
+    assert abs(v - q.value) <= 64 * 1.1e-16 * max(n, 11) * q.sum_abs, (v, q.value)
+    pad = max(n, 11) - n
+    assert abs(sabs - 3.0 ** pad * q.sum_abs) <= 1e-12 * sabs
