@@ -13,14 +13,27 @@ struct __align__(16) c64 {
 
 // Device layout of a node of s modes: the Hermitian (or real symmetric)
 // 2s x 2s matrix in mode-interleaved rows, REVERSED (the next mode to decide
-// owns the two highest rows), stored as its lower-triangular 2x2 mode blocks
-// (a, b), a >= b, at block index a(a+1)/2 + b; each block holds its 4 entries
-// [(2a,2b), (2a,2b+1), (2a+1,2b), (2a+1,2b+1)] (a diagonal block keeps its
-// upper entry as the conjugate of the lower one).  Dropping the highest mode
-// leaves a prefix of the array.
+// owns the two highest rows), cut into its lower-triangular 2x2 mode blocks
+// (a, b), a >= b, numbered a(a+1)/2 + b.  Each block has 4 entries
+// e = 0..3: (2a,2b), (2a,2b+1), (2a+1,2b), (2a+1,2b+1) (a diagonal block keeps
+// its upper entry as the conjugate of the lower one).  The entries of a block
+// form 16-byte granules (two real entries, or one complex entry), and the
+// node stores granule g of every block as one array, then granule g+1:
+// neighbouring lanes that work on neighbouring blocks touch neighbouring
+// 16-byte words.  Dropping the highest mode leaves the first blocks of every
+// granule array, so an exclude child is a view of its parent that keeps the
+// parent's block count nb as the array stride.
 __host__ __device__ constexpr int NB(int s) { return s * (s + 1) / 2; }        // blocks
 __host__ __device__ constexpr int NSZ(int s) { return 2 * s * (s + 1); }       // scalars
 __host__ __device__ constexpr int bidx(int a, int b) { return a * (a + 1) / 2 + b; }
+// entries per 16-byte granule for scalars of sz bytes
+__host__ __device__ constexpr int EPG(int sz) { return 16 / sz; }
+// scalar index of entry e of block bi in a node whose granule arrays have nb
+// blocks
+__host__ __device__ constexpr int gpos(int sz, int nb, int bi, int e)
+{
+    return EPG(sz) * ((e / EPG(sz)) * nb + bi) + e % EPG(sz);
+}
 // packed lower triangle (registers of the per-lane tail): entry (x, y), y <= x
 __host__ __device__ constexpr int E(int s) { return s * (2 * s + 1); }
 __host__ __device__ constexpr int pidx(int x, int y) { return x * (x + 1) / 2 + y; }

@@ -41,15 +41,44 @@
 namespace tor {
 
 // ---------------------------------------------------------------------------
-// LDS layout of tier B: node 0 (the tier-A leaf, R modes), then for each level
-// j = 1..B-1 the 2^(j-1) include nodes of R-j modes (block layout).
-template <int R>
-__host__ __device__ constexpr int offB(int j)
+// LDS placement of the nodes tier B stores: node 0 is the tier-A leaf (R
+// modes), node 2^(j-1) + i the include node i of level j (R - j modes), for
+// j = 1..BL.  Nodes follow one another in that order, each on a 16-byte
+// boundary.  Tier C reads the same entry of 16 different nodes in one
+// instruction, so each node is moved forward (by at most 15 granules) to the
+// first place where the starts of its granule arrays, taken as 16-byte slots
+// modulo 16 (a bank group in a 256-byte row of banks), clash with as few
+// earlier nodes' starts of the same array as possible.  Returns the byte
+// offset of node `stop`, or the total size for stop = 2^BL.
+__host__ __device__ constexpr int node_place(int R, int BL, int esz, int stop)
 {
-    int o = NSZ(R);
-    for (int jj = 1; jj < j; ++jj)
-        o += (1 << (jj - 1)) * NSZ(R - jj);
-    return o;
+    const int gpb = 4 / EPG(esz);  // granule arrays per node
+    unsigned used[4] = {0u, 0u, 0u, 0u};
+    int off = 0;
+    for (int t = 0; t < (1 << BL); ++t) {
+        int lev = 0;
+        while ((1 << lev) <= t)
+            ++lev;
+        const int nb = NB(R - lev);
+        const int b0 = (off + 15) & ~15;
+        int best = b0, bestc = 5;
+        for (int k = 0; k < 16 && bestc > 0; ++k) {
+            const int b = b0 + 16 * k;
+            int c = 0;
+            for (int g = 0; g < gpb; ++g)
+                c += (int)((used[g] >> (((b >> 4) + g * nb) & 15)) & 1u);
+            if (c < bestc) {
+                bestc = c;
+                best = b;
+            }
+        }
+        if (t == stop)
+            return best;
+        for (int g = 0; g < gpb; ++g)
+            used[g] |= 1u << (((best >> 4) + g * nb) & 15);
+        off = best + esz * NSZ(R - lev);
+    }
+    return off;
 }
 
 // 2x2 pivot of the highest mode m of a node, and the update of one output
@@ -57,29 +86,46 @@ __host__ __device__ constexpr int offB(int j)
 //   H'[x][y] = H[x][y] - conj(r1[x]) r1[y] / alpha - conj(r2'[x]) r2'[y] / gamma1
 // with r1 = row 2m, r2' = row 2m+1 - r1 beta/alpha (the LDL form of the 2x2
 // pivot); rows 2a, 2a+1 read r1, r2 from block (m, a), columns from (m, b).
+// entry e of block bi of a node whose granule arrays hold nb blocks
 template <class S>
-__device__ __forceinline__ Piv<S> node_pivot(const S *node, int m)
+__device__ __forceinline__ S &blk(S *node, int nb, int bi, int e)
 {
-    const S *P = node + 4 * bidx(m, m);
-    return pivot(re(P[0]), P[2], re(P[3]));
+    return node[gpos((int)sizeof(S), nb, bi, e)];
+}
+template <class S>
+__device__ __forceinline__ const S &blk(const S *node, int nb, int bi, int e)
+{
+    return node[gpos((int)sizeof(S), nb, bi, e)];
+}
+template <class S>
+__device__ __forceinline__ void put_block(S *node, int nb, int bi, const S *o)
+{
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        blk(node, nb, bi, e) = o[e];
 }
 
 template <class S>
-__device__ __forceinline__ void elim_block(const S *node, int m, int a, int b, const Piv<S> &pv, S *o)
+__device__ __forceinline__ Piv<S> node_pivot(const S *node, int nb, int m)
 {
-    const S *pa = node + 4 * bidx(m, a);
-    const S *pb = node + 4 * bidx(m, b);
-    const S *hb = node + 4 * bidx(a, b);
-    const S ra0 = pa[0], ra1 = pa[1];
-    const S qa0 = sub_mul(pa[2], ra0, pv.ba), qa1 = sub_mul(pa[3], ra1, pv.ba);
-    const S rb0 = pb[0], rb1 = pb[1];
-    const S qb0 = sub_mul(pb[2], rb0, pv.ba), qb1 = sub_mul(pb[3], rb1, pv.ba);
+    const int bi = bidx(m, m);
+    return pivot(re(blk(node, nb, bi, 0)), blk(node, nb, bi, 2), re(blk(node, nb, bi, 3)));
+}
+
+template <class S>
+__device__ __forceinline__ void elim_block(const S *node, int nb, int m, int a, int b, const Piv<S> &pv, S *o)
+{
+    const int ia = bidx(m, a), ib = bidx(m, b), ih = bidx(a, b);
+    const S ra0 = blk(node, nb, ia, 0), ra1 = blk(node, nb, ia, 1);
+    const S qa0 = sub_mul(blk(node, nb, ia, 2), ra0, pv.ba), qa1 = sub_mul(blk(node, nb, ia, 3), ra1, pv.ba);
+    const S rb0 = blk(node, nb, ib, 0), rb1 = blk(node, nb, ib, 1);
+    const S qb0 = sub_mul(blk(node, nb, ib, 2), rb0, pv.ba), qb1 = sub_mul(blk(node, nb, ib, 3), rb1, pv.ba);
     const S ua0 = scale(ra0, pv.inv_a), ua1 = scale(ra1, pv.inv_a);
     const S va0 = scale(qa0, pv.inv_g), va1 = scale(qa1, pv.inv_g);
-    o[0] = upd(hb[0], ua0, rb0, va0, qb0);
-    o[1] = upd(hb[1], ua0, rb1, va0, qb1);
-    o[2] = upd(hb[2], ua1, rb0, va1, qb0);
-    o[3] = upd(hb[3], ua1, rb1, va1, qb1);
+    o[0] = upd(blk(node, nb, ih, 0), ua0, rb0, va0, qb0);
+    o[1] = upd(blk(node, nb, ih, 1), ua0, rb1, va0, qb1);
+    o[2] = upd(blk(node, nb, ih, 2), ua1, rb0, va1, qb0);
+    o[3] = upd(blk(node, nb, ih, 3), ua1, rb1, va1, qb1);
     if (a == b) {  // diagonal block: real diagonal, conjugate upper entry
         o[0] = fix_diag(o[0]);
         o[3] = fix_diag(o[3]);
@@ -100,16 +146,17 @@ __device__ __forceinline__ void block_ab(int bi, int &a, int &b)
 
 // ---------------------------------------------------------------------------
 // one include step on global memory (tier A and the root path): src is a view
-// of s modes, dst receives the Schur complement of s-1 modes.  Every lane
-// forms the pivot itself; lane l updates blocks l, l+64, ...
-// dst (global, may be null) receives the whole child; lds (may be null)
-// receives its first nlds blocks (the prefix that is the tier-A leaf).
+// of s modes of a node with snb blocks per granule array, dst receives the
+// Schur complement of s-1 modes as a node of its own (NB(s-1) blocks per
+// array).  Every lane forms the pivot itself; lane l updates blocks l, l+64,
+// ...  dst (global, may be null) receives the whole child; lds (may be null)
+// receives its first nlds blocks (the tier-A leaf) as a node of nlds blocks.
 template <class S>
-__device__ void elim_global(const S *__restrict__ src, S *__restrict__ dst, S *lds, int nlds, int s, int lane,
-                            double &pdet, int &bad)
+__device__ void elim_global(const S *__restrict__ src, int snb, S *__restrict__ dst, S *lds, int nlds, int s,
+                            int lane, double &pdet, int &bad)
 {
     const int m = s - 1;
-    const Piv<S> pv = node_pivot(src, m);
+    const Piv<S> pv = node_pivot(src, snb, m);
     pdet = pv.pdet;
     if (!(pv.pdet > 0.0) || !(pv.inv_a > 0.0))
         bad = 1;
@@ -118,21 +165,11 @@ __device__ void elim_global(const S *__restrict__ src, S *__restrict__ dst, S *l
         int a, b;
         block_ab(bi, a, b);
         S o[4];
-        elim_block(src, m, a, b, pv, o);
-        if (dst) {
-            S *d = dst + 4 * bi;
-            d[0] = o[0];
-            d[1] = o[1];
-            d[2] = o[2];
-            d[3] = o[3];
-        }
-        if (lds && bi < nlds) {
-            S *d = lds + 4 * bi;
-            d[0] = o[0];
-            d[1] = o[1];
-            d[2] = o[2];
-            d[3] = o[3];
-        }
+        elim_block(src, snb, m, a, b, pv, o);
+        if (dst)
+            put_block(dst, NB(m), bi, o);
+        if (lds && bi < nlds)
+            put_block(lds, nlds, bi, o);
     }
     __syncthreads();
 }
@@ -140,27 +177,28 @@ __device__ void elim_global(const S *__restrict__ src, S *__restrict__ dst, S *l
 // ---------------------------------------------------------------------------
 // tier B tables, built once per wave: for the node of level jl with id i
 // (bit jl-1-m of i = decision on the m-th mode below the tier-A leaf, 1 =
-// include; stored at (2^jl - 1) + i) the LDS offset of the include node it
-// is a prefix view of, and the slot of that node's determinant (0xff: the
-// tier-A leaf).  The include node (lev, idx) keeps its determinant at
-// (2^(lev-1) - 1) + idx.
-template <int R, int B>
-__device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcDet, uint16_t *blkAB, int lane)
+// include; stored at (2^jl - 1) + i) the LDS offset of the stored node it
+// is a view of, that node's blocks per granule array, and the slot of its
+// determinant (0xff: the tier-A leaf).  The include node (lev, idx) keeps its
+// determinant at (2^(lev-1) - 1) + idx.
+template <class S, int R, int B>
+__device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcNB, uint8_t *srcDet, uint16_t *blkAB,
+                                             int lane)
 {
+    constexpr int esz = (int)sizeof(S);
     for (int t = lane; t < (1 << B) - 1; t += 64) {
         int jl = 31 - __clz(t + 1);
         int i = t + 1 - (1 << jl);
         if (i == 0) {
             srcOff[t] = 0;
+            srcNB[t] = (uint8_t)NB(R);
             srcDet[t] = 0xff;
         } else {
             int tz = __builtin_ctz(i);
             int lev = jl - tz;
             int idx = (i >> tz) >> 1;
-            int off = NSZ(R);
-            for (int jj = 1; jj < lev; ++jj)
-                off += (1 << (jj - 1)) * NSZ(R - jj);
-            srcOff[t] = (uint16_t)(off + idx * NSZ(R - lev));
+            srcOff[t] = (uint16_t)(node_place(R, B - 1, esz, (1 << (lev - 1)) + idx) / esz);
+            srcNB[t] = (uint8_t)NB(R - lev);
             srcDet[t] = (uint8_t)((1 << (lev - 1)) - 1 + idx);
         }
     }
@@ -171,25 +209,35 @@ __device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcDet, 
     }
 }
 
+// LDS tables of tier B (see build_tables) and its per-node pivot scalars
+template <class S>
+struct TierB {
+    S *buf;                 // stored nodes (node_place)
+    const uint16_t *srcOff; // per view: offset of its stored node
+    const uint8_t *srcNB;   // per view: blocks per granule array of that node
+    const uint8_t *srcDet;  // per view: determinant slot (0xff: tier-A leaf)
+    const uint16_t *blkAB;  // block index -> a | b << 8
+    double *nInv;           // per include node of a level: 1/alpha, 1/gamma1
+    S *nBa;                 // per include node of a level: beta/alpha
+    double *ndet;           // per include node: running determinant
+};
+
 // tier B, level J: every include node of level J from its parent of level J-1
 template <class S, int R, int J>
-__device__ __forceinline__ void tierB_level(S *bufB, double *nInv, S *nBa, double *ndet, const uint16_t *srcOff,
-                                            const uint8_t *srcDet, const uint16_t *blkAB, double leafDet, int lane,
-                                            int &bad)
+__device__ __forceinline__ void tierB_level(const TierB<S> &tb, double leafDet, int lane, int &bad)
 {
     constexpr int m = R - J;          // pivot mode of the parent (it has m+1 modes)
     constexpr int NN = 1 << (J - 1);  // include nodes at level J
     constexpr int NBO = NB(m);        // blocks of a child
-    constexpr int OUT = offB<R>(J);
     if (lane < NN) {
-        const S *par = bufB + srcOff[NN - 1 + lane];
-        const int di = srcDet[NN - 1 + lane];
-        const double pdp = di == 0xff ? leafDet : ndet[di];
-        const Piv<S> pq = node_pivot(par, m);
-        nInv[2 * lane] = pq.inv_a;
-        nInv[2 * lane + 1] = pq.inv_g;
-        nBa[lane] = pq.ba;
-        ndet[NN - 1 + lane] = pdp * pq.pdet;
+        const S *par = tb.buf + tb.srcOff[NN - 1 + lane];
+        const int di = tb.srcDet[NN - 1 + lane];
+        const double pdp = di == 0xff ? leafDet : tb.ndet[di];
+        const Piv<S> pq = node_pivot(par, (int)tb.srcNB[NN - 1 + lane], m);
+        tb.nInv[2 * lane] = pq.inv_a;
+        tb.nInv[2 * lane + 1] = pq.inv_g;
+        tb.nBa[lane] = pq.ba;
+        tb.ndet[NN - 1 + lane] = pdp * pq.pdet;
         if (!(pq.pdet > 0.0) || !(pq.inv_a > 0.0))
             bad = 1;
     }
@@ -199,31 +247,28 @@ __device__ __forceinline__ void tierB_level(S *bufB, double *nInv, S *nBa, doubl
         const int it = it0 + lane;
         if (it < NN * NBO) {
             const int i = it / NBO, bi = it - i * NBO;
-            const int ab = blkAB[bi];
-            const S *par = bufB + srcOff[NN - 1 + i];
+            const int ab = tb.blkAB[bi];
+            const S *par = tb.buf + tb.srcOff[NN - 1 + i];
+            const int pnb = tb.srcNB[NN - 1 + i];
             Piv<S> pq;
-            pq.inv_a = nInv[2 * i];
-            pq.inv_g = nInv[2 * i + 1];
-            pq.ba = nBa[i];
+            pq.inv_a = tb.nInv[2 * i];
+            pq.inv_g = tb.nInv[2 * i + 1];
+            pq.ba = tb.nBa[i];
             S o[4];
-            elim_block(par, m, ab & 0xff, ab >> 8, pq, o);
-            S *d = bufB + OUT + i * NSZ(m) + 4 * bi;
-            d[0] = o[0];
-            d[1] = o[1];
-            d[2] = o[2];
-            d[3] = o[3];
+            elim_block(par, pnb, m, ab & 0xff, ab >> 8, pq, o);
+            // the include child i of level J is view 2i+1 of that level
+            put_block(tb.buf + tb.srcOff[(1 << J) + 2 * i], NBO, bi, o);
         }
     }
     __syncthreads();
 }
 
 template <class S, int R, int J, int B>
-__device__ __forceinline__ void tierB(S *bufB, double *nInv, S *nBa, double *ndet, const uint16_t *srcOff,
-                                      const uint8_t *srcDet, const uint16_t *blkAB, double leafDet, int lane, int &bad)
+__device__ __forceinline__ void tierB(const TierB<S> &tb, double leafDet, int lane, int &bad)
 {
     if constexpr (J < B) {
-        tierB_level<S, R, J>(bufB, nInv, nBa, ndet, srcOff, srcDet, blkAB, leafDet, lane, bad);
-        tierB<S, R, J + 1, B>(bufB, nInv, nBa, ndet, srcOff, srcDet, blkAB, leafDet, lane, bad);
+        tierB_level<S, R, J>(tb, leafDet, lane, bad);
+        tierB<S, R, J + 1, B>(tb, leafDet, lane, bad);
     }
 }
 
@@ -282,11 +327,11 @@ __device__ __forceinline__ void tail(const S *h, double det, double sgn, Acc &ac
     }
 }
 
-// element (x, y), y <= x, of an LDS node in block layout
+// element (x, y), y <= x, of a node with nb blocks per granule array
 template <class S>
-__device__ __forceinline__ S node_el(const S *node, int x, int y)
+__device__ __forceinline__ S node_el(const S *node, int nb, int x, int y)
 {
-    return node[4 * bidx(x >> 1, y >> 1) + ((x & 1) << 1) + (y & 1)];
+    return blk(node, nb, bidx(x >> 1, y >> 1), ((x & 1) << 1) + (y & 1));
 }
 
 // pivot of one lane-level decision: an include lane takes the 2x2 pivot, an
@@ -316,8 +361,7 @@ __device__ __forceinline__ Piv<S> lane_pivot(double a, S b, double g, bool inc, 
 // once and receives the L rank-2 updates in turn, so only the pivot rows and
 // the T-mode result are held in registers.
 template <class S, int T, int B, int L, class Acc>
-__device__ __forceinline__ void tierC(const S *bufB, const double *ndet, const uint16_t *srcOff,
-                                      const uint8_t *srcDet, double leafDet, int leafInc, int N, int lane, Acc &acc,
+__device__ __forceinline__ void tierC(const TierB<S> &tb, double leafDet, int leafInc, int N, int lane, Acc &acc,
                                       int &bad)
 {
     static_assert(L == 1 || L == 2, "one or two lane levels");
@@ -325,20 +369,22 @@ __device__ __forceinline__ void tierC(const S *bufB, const double *ndet, const u
     constexpr int pT = 2 * T;               // rows of the T-mode result
     constexpr int p1 = 2 * (T + L) - 2;     // pivot rows of the first lane level
     const int ip = lane >> L;
-    const S *src = bufB + srcOff[NP + ip];
-    const int di = srcDet[NP + ip];
-    double det = di == 0xff ? leafDet : ndet[di];
+    const S *src = tb.buf + tb.srcOff[NP + ip];
+    const int snb = tb.srcNB[NP + ip];
+    const int di = tb.srcDet[NP + ip];
+    double det = di == 0xff ? leafDet : tb.ndet[di];
     const bool inc1 = (lane >> (L - 1)) & 1;  // first lane level
     const bool inc0 = lane & 1;               // second (L == 2)
 
     // first level: pivot of mode T+L-1 and its rows, r2 in LDL form
-    const Piv<S> q1 = lane_pivot(re(node_el(src, p1, p1)), node_el(src, p1 + 1, p1), re(node_el(src, p1 + 1, p1 + 1)),
+    const Piv<S> q1 = lane_pivot(re(node_el(src, snb, p1, p1)), node_el(src, snb, p1 + 1, p1),
+                                 re(node_el(src, snb, p1 + 1, p1 + 1)),
                                  inc1, bad);
     S r1[p1], r2[p1];
 #pragma unroll
     for (int y = 0; y < p1; ++y) {
-        r1[y] = node_el(src, p1, y);
-        r2[y] = sub_mul(node_el(src, p1 + 1, y), r1[y], q1.ba);
+        r1[y] = node_el(src, snb, p1, y);
+        r2[y] = sub_mul(node_el(src, snb, p1 + 1, y), r1[y], q1.ba);
     }
     det *= q1.pdet;
     int includes = leafInc + __popc(ip) + inc1;
@@ -354,7 +400,7 @@ __device__ __forceinline__ void tierC(const S *bufB, const double *ndet, const u
             const S u1 = scale(r1[x], q1.inv_a), u2 = scale(r2[x], q1.inv_g);
 #pragma unroll
             for (int y = 0; y <= x; ++y) {
-                const S v = node_el(src, x, y);
+                const S v = node_el(src, snb, x, y);
                 c[x - pT][y] = (x == y) ? upd_diag(v, u1, r1[y], u2, r2[y]) : upd(v, u1, r1[y], u2, r2[y]);
             }
         }
@@ -380,7 +426,7 @@ __device__ __forceinline__ void tierC(const S *bufB, const double *ndet, const u
         }
 #pragma unroll
         for (int y = 0; y <= x; ++y) {
-            const S v = node_el(src, x, y);
+            const S v = node_el(src, snb, x, y);
             S o = (x == y) ? upd_diag(v, u1, r1[y], u2, r2[y]) : upd(v, u1, r1[y], u2, r2[y]);
             if constexpr (L == 2)
                 o = (x == y) ? upd_diag(o, w1, s1[y], w2, s2[y]) : upd(o, w1, s1[y], w2, s2[y]);
@@ -399,19 +445,21 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
     constexpr int R = T + B;
     constexpr int BL = B - L;                // levels expanded in LDS
     constexpr int NN_MAX = 1 << (BL - 1);    // include nodes of the last LDS level
-    __shared__ S bufB[offB<R>(BL + 1)];
+    __shared__ S bufB[node_place(R, BL, (int)sizeof(S), 1 << BL) / (int)sizeof(S)];
     __shared__ S nBa[NN_MAX];
     __shared__ double nInv[2 * NN_MAX];
     __shared__ double ndet[1 << BL];
     __shared__ uint16_t srcOff[(1 << (BL + 1)) - 1];
+    __shared__ uint8_t srcNB[(1 << (BL + 1)) - 1];
     __shared__ uint8_t srcDet[(1 << (BL + 1)) - 1];
     __shared__ uint16_t blkAB[NB(R - 1)];
     __shared__ double sdet[MAX_N + 1];
     __shared__ int sinc[MAX_N + 1];
 
     const int lane = threadIdx.x;
-    build_tables<R, BL + 1>(srcOff, srcDet, blkAB, lane);
+    build_tables<S, R, BL + 1>(srcOff, srcNB, srcDet, blkAB, lane);
     __syncthreads();
+    const TierB<S> tb{bufB, srcOff, srcNB, srcDet, blkAB, nInv, nBa, ndet};
     S *wscr = reinterpret_cast<S *>(prm.scratch + (long long)blockIdx.x * prm.scratch_stride);
 
     for (;;) {
@@ -436,17 +484,21 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
         int bad = 0;
 
         // root: decisions on modes 0..k-1 given by the bits of root
+        // (every stored node keeps its own block count as the array stride:
+        // the matrix NB(N), stack slot l a node of N-l modes, NB(N-l))
         const S *rsrc = C;
+        int rnb = NB(N);
         double rdet = 1.0;
         int rinc = 0;
         for (int l = 0; l < k; ++l) {
             if ((root >> l) & 1) {
                 S *dst = wscr + slot_off(N, l + 1);
                 double pd;
-                elim_global<S>(rsrc, dst, nullptr, 0, N - l, lane, pd, bad);
+                elim_global<S>(rsrc, rnb, dst, nullptr, 0, N - l, lane, pd, bad);
                 rdet *= pd;
                 ++rinc;
                 rsrc = dst;
+                rnb = NB(N - l - 1);
             }
         }
 
@@ -456,8 +508,12 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
             double ldet;
             int linc;
             if (x == 0) {
-                for (int e = lane; e < NSZ(R); e += 64)
-                    bufB[e] = rsrc[e];
+                // the first R modes of the root node, restrided to NB(R)
+                constexpr int GA = EPG((int)sizeof(S)) * NB(R);  // scalars per granule array
+                for (int e = lane; e < NSZ(R); e += 64) {
+                    const int g = e / GA;
+                    bufB[e] = rsrc[g * EPG((int)sizeof(S)) * rnb + (e - g * GA)];
+                }
                 ldet = rdet;
                 linc = rinc;
             } else {
@@ -467,15 +523,18 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                 const int lvl = LA - 1 - t;
                 const long long xr = x >> (t + 1);
                 const S *s;
+                int snb;
                 double sd;
                 int si;
                 if (xr == 0) {
                     s = rsrc;
+                    snb = rnb;
                     sd = rdet;
                     si = rinc;
                 } else {
                     const int sl = LA - (__builtin_ctzll(xr) + t + 1);
                     s = wscr + slot_off(N, sl);
+                    snb = NB(N - sl);
                     sd = sdet[sl];
                     si = sinc[sl];
                 }
@@ -484,7 +543,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                 // their stack slot
                 S *dst = (lvl + 1 < LA) ? wscr + slot_off(N, lvl + 1) : nullptr;
                 double pd;
-                elim_global<S>(s, dst, bufB, NB(R), N - lvl, lane, pd, bad);
+                elim_global<S>(s, snb, dst, bufB, NB(R), N - lvl, lane, pd, bad);
                 ldet = sd * pd;
                 linc = si + 1;
                 if (lane == 0) {
@@ -493,8 +552,8 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                 }
             }
             __syncthreads();
-            tierB<S, R, 1, BL + 1>(bufB, nInv, nBa, ndet, srcOff, srcDet, blkAB, ldet, lane, bad);
-            tierC<S, T, B, L, Acc>(bufB, ndet, srcOff, srcDet, ldet, linc, N, lane, acc, bad);
+            tierB<S, R, 1, BL + 1>(tb, ldet, lane, bad);
+            tierC<S, T, B, L, Acc>(tb, ldet, linc, N, lane, acc, bad);
             __syncthreads();
         }
 
@@ -612,7 +671,7 @@ __global__ void __launch_bounds__(64) tor_plain(PlainParams prm)
                 }
                 for (int e = lane; e < ed; e += 64) {
                     const int gx = rows[x], gy = rows[y];  // gx >= gy
-                    A[e] = C[4 * bidx(gx >> 1, gy >> 1) + ((gx & 1) << 1) + (gy & 1)];
+                    A[e] = blk(C, NB(n), bidx(gx >> 1, gy >> 1), ((gx & 1) << 1) + (gy & 1));
                     y += 64;
                     while (y > x) {
                         y -= x + 1;

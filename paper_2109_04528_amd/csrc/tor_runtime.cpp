@@ -195,7 +195,8 @@ void stage_real(int n, const std::vector<double> &C, Staged &st)
         for (int b = 0; b <= a; b++)
             for (int e = 0; e < 4; e++) {
                 const int qi = 2 * N - 1 - (2 * a + (e >> 1)), qj = 2 * N - 1 - (2 * b + (e & 1));
-                st.packed_r[(size_t)4 * bidx(a, b) + e] = rblk(qi / 2, qj / 2, qi % 2, qj % 2);
+                st.packed_r[(size_t)gpos((int)sizeof(double), NB(N), bidx(a, b), e)] =
+                    rblk(qi / 2, qj / 2, qi % 2, qj % 2);
             }
     st.real = true;
 }
@@ -258,7 +259,7 @@ int stage_matrix(int n, const double *O, long ld, unsigned flags, int min_modes,
                 c64 v = elem(2 * N - 1 - x, 2 * N - 1 - y);
                 if (x == y)
                     v.y = 0.0;
-                st.packed[(size_t)4 * bidx(a, b) + e] = v;
+                st.packed[(size_t)gpos((int)sizeof(c64), NB(N), bidx(a, b), e)] = v;
             }
     st.real = false;
     if (!(flags & TOR_FORCE_COMPLEX) && n > 0)
