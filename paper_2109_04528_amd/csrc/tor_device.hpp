@@ -131,27 +131,72 @@ __device__ __forceinline__ Piv<S> pivot(double a, S b, double g)
 }
 
 // ---- accumulators ----------------------------------------------------------
+// Terms are added with a sign known at compile time (SG = +1 or -1) relative
+// to a lane's running sign `frame`; when the lane's sign changes between
+// leaves the sums are negated (exact), and the final sum is hi * frame.
+// r, r0, r1 are reciprocal square roots of determinants (positive).
+//
 // Double-double sum by Knuth's TwoSum (TAOCP vol. 2, 4.2.2): hi + lo carries
 // the running sum, lo collects the exact rounding error of every addition.
+// The pair of the last mode, SG (r1 - r0), is formed first by Dekker's
+// Fast2Sum, r1 - r0 = s + err, which is exact when r1 >= r0 / 2 (then
+// exponent(r1) >= exponent(r0), or the difference is exact by Sterbenz's
+// lemma), i.e. whenever that mode's pivot determinant is at most 4.
 struct AccDD {
-    double hi = 0.0, lo = 0.0, abs_sum = 0.0;
-    __device__ __forceinline__ void add(double t)
+    double hi = 0.0, lo = 0.0, abs_sum = 0.0, frame = 1.0;
+    __device__ __forceinline__ void two_sum(double t)
     {
         double s = hi + t;
         double bb = s - hi;
         double e = (hi - (s - bb)) + (t - bb);
         hi = s;
         lo += e;
-        abs_sum += fabs(t);
+    }
+    template <int SG>
+    __device__ __forceinline__ void add(double r)
+    {
+        two_sum(SG * r);
+        abs_sum += r;
+    }
+    template <int SG>
+    __device__ __forceinline__ void add_pair(double r0, double r1)
+    {
+        const double s = r1 - r0;
+        const double z = s - r1;
+        const double err = -r0 - z;
+        two_sum(SG * s);
+        lo += SG * err;
+        abs_sum += r0 + r1;
+    }
+    __device__ __forceinline__ void set_frame(double f)
+    {
+        const double m = f * frame;
+        hi *= m;
+        lo *= m;
+        frame = f;
     }
 };
-// plain FP64 sum, kept only for the dd-vs-FP64 comparison
+// plain FP64 sum of the same terms, one by one, kept only for the dd-vs-FP64
+// comparison
 struct AccF64 {
-    double hi = 0.0, lo = 0.0, abs_sum = 0.0;
-    __device__ __forceinline__ void add(double t)
+    double hi = 0.0, lo = 0.0, abs_sum = 0.0, frame = 1.0;
+    template <int SG>
+    __device__ __forceinline__ void add(double r)
     {
-        hi += t;
-        abs_sum += fabs(t);
+        hi += SG * r;
+        abs_sum += r;
+    }
+    template <int SG>
+    __device__ __forceinline__ void add_pair(double r0, double r1)
+    {
+        hi += -SG * r0;
+        hi += SG * r1;
+        abs_sum += r0 + r1;
+    }
+    __device__ __forceinline__ void set_frame(double f)
+    {
+        hi *= f * frame;
+        frame = f;
     }
 };
 

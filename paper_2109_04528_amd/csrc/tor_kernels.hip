@@ -298,32 +298,35 @@ __device__ __forceinline__ void elim_regs(const S *h, const Piv<S> &pq, S *hn)
         }
 }
 
-// all 2^M subsets below a register-resident node of M modes.
-// sgn = (-1)^(#excluded so far); det = running determinant.
-template <class S, int M, class Acc>
-__device__ __forceinline__ void tail(const S *h, double det, double sgn, Acc &acc, int &bad)
+// all 2^M subsets below a register-resident node of M modes.  SG is the sign
+// (-1)^(#excluded) of its subsets relative to the lane's frame (see the
+// accumulators); det is the running determinant.
+template <class S, int M, int SG, class Acc>
+__device__ __forceinline__ void tail(const S *h, double det, Acc &acc, int &bad)
 {
     if constexpr (M == 0) {
-        acc.add(sgn * rsqrt_nr(det));
+        acc.template add<SG>(rsqrt_nr(det));
+    } else if constexpr (M == 1) {
+        // exclude (sign -SG) and include (sign SG) of the last mode
+        const double a = re(h[0]);
+        const S b = h[1];
+        const double g = re(h[2]);
+        const double pd = fma(a, g, -abs2(b));  // det of the last 2x2 block
+        if (!(a > 0.0) || !(pd > 0.0))
+            bad = 1;
+        acc.template add_pair<SG>(rsqrt_nr(det), rsqrt_nr(det * pd));
     } else {
-        tail<S, M - 1, Acc>(h, det, -sgn, acc, bad);  // exclude the next mode
+        tail<S, M - 1, -SG, Acc>(h, det, acc, bad);  // exclude the next mode
         constexpr int p = 2 * M - 2;
         const double a = re(h[pidx(p, p)]);
         const S b = h[pidx(p + 1, p)];
         const double g = re(h[pidx(p + 1, p + 1)]);
-        if constexpr (M == 1) {
-            const double pd = fma(a, g, -abs2(b));  // det of the last 2x2 block
-            if (!(a > 0.0) || !(pd > 0.0))
-                bad = 1;
-            acc.add(sgn * rsqrt_nr(det * pd));
-        } else {
-            const Piv<S> pq = pivot(a, b, g);
-            if (!(a > 0.0) || !(pq.pdet > 0.0))
-                bad = 1;
-            S hn[E(M - 1)];
-            elim_regs<S, M>(h, pq, hn);
-            tail<S, M - 1, Acc>(hn, det * pq.pdet, sgn, acc, bad);
-        }
+        const Piv<S> pq = pivot(a, b, g);
+        if (!(a > 0.0) || !(pq.pdet > 0.0))
+            bad = 1;
+        S hn[E(M - 1)];
+        elim_regs<S, M>(h, pq, hn);
+        tail<S, M - 1, SG, Acc>(hn, det * pq.pdet, acc, bad);
     }
 }
 
@@ -434,8 +437,8 @@ __device__ __forceinline__ void tierC(const TierB<S> &tb, double leafDet, int le
         }
     }
     const int excluded = (N - T) - includes;
-    const double sgn = (excluded & 1) ? -1.0 : 1.0;
-    tail<S, T, Acc>(hT, det, sgn, acc, bad);
+    acc.set_frame((excluded & 1) ? -1.0 : 1.0);
+    tail<S, T, 1, Acc>(hT, det, acc, bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -557,7 +560,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
             __syncthreads();
         }
 
-        double h = acc.hi, l = acc.lo, ab = acc.abs_sum;
+        double h = acc.hi * acc.frame, l = acc.lo * acc.frame, ab = acc.abs_sum;
         constexpr bool is_dd = std::is_same<Acc, AccDD>::value;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
@@ -720,7 +723,10 @@ __global__ void __launch_bounds__(64) tor_plain(PlainParams prm)
             }
             if (lane == 0) {
                 const double t = rsqrt_nr(det);
-                acc.add(((n - d) & 1) ? -t : t);
+                if ((n - d) & 1)
+                    acc.template add<-1>(t);
+                else
+                    acc.template add<1>(t);
             }
             __syncthreads();
         }
