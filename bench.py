@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--serve", type=int, default=4096, help="requests in the mixed-n stream (0: skip)")
     ap.add_argument("--batch", type=int, default=512, help="matrices in the batched launch (0: skip)")
     ap.add_argument("--n34", type=int, default=1, help="also time one n=34 Torontonian")
+    ap.add_argument("--quad", type=int, default=1,
+                    help="also time the same n=30 Torontonian with the double-double factor")
     ap.add_argument("--profile-traffic", action="store_true",
                     help="one n=30 Torontonian and one 256 MiB device copy, for the HBM counters")
     args = ap.parse_args()
@@ -243,6 +245,21 @@ def main():
                "tor": r34.value, "cancellation_R": r34.cancellation}
         print("bench: n=34 done", file=sys.stderr, flush=True)
 
+    quad = None
+    if args.quad:
+        from paper_2109_04528_amd import TOR_FACTOR_DD
+        with Context(device=0, stream=stream, workspace=ws, flags=TOR_FACTOR_DD) as qc:
+            qc.eval(O)
+            qms = [qc.eval(O).device_ms for _ in range(3)]
+            rq = qc.eval(O)
+        # the FP64 result's actual error, measured against the double-double one
+        quad = {"n": n, "kernel_ms": float(np.median(qms)),
+                "subset_dets_per_s": (1 << n) / (float(np.median(qms)) * 1e-3),
+                "tor_hi": rq.tor, "tor_lo": rq.tor_lo, "err_est": rq.err_est,
+                "fp64_path_rel_error": abs(r.value - rq.value) / abs(rq.value),
+                "factor": "double-double (TOR_FACTOR_DD), real quadrature form"}
+        print("bench: double-double factor done", file=sys.stderr, flush=True)
+
     serve = None
     if args.serve > 0:
         reqs = serve_requests(args.serve, 5)
@@ -289,6 +306,7 @@ def main():
         "plain": plain,
         "batch": batch,
         "n34": big,
+        "quad": quad,
         "serving": serve,
         "cpu_baseline": cpu,
     }

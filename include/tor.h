@@ -64,6 +64,17 @@ extern "C" {
 #define TOR_CHECK_HERMITIAN 0x2u /* reject O whose upper triangle is not the conjugate
                                     transpose of its lower triangle (rel. tol 1e-12)   */
 #define TOR_FORCE_COMPLEX 0x4u   /* never take the real quadrature path               */
+/* Factorise in double-double (about 104-bit significands) instead of FP64:
+ * the higher-precision factor that the FP64 floor u R / sqrt(2^n) calls for
+ * when the cancellation R = sum|t| / |Tor| is large (Sec. 5 keeps the
+ * determinants in extended precision for the same reason).  Each term then
+ * carries a relative error of a few units of 2^-104 per factorisation step,
+ * and the terms are summed in double-double.  Runs on the real quadrature
+ * form only: a matrix without the Gaussian-state block structure is rejected
+ * with TOR_E_INVAL; tor_create rejects it together with TOR_FORCE_COMPLEX.
+ * The input itself is FP64; I - O and the real form are formed from it in
+ * double-double (exactly, or rounded to 2^-106).  About 20x the FP64 time. */
+#define TOR_FACTOR_DD 0x8u
 
 typedef struct tor_ctx tor_ctx;
 
@@ -83,10 +94,12 @@ typedef struct {
     double tor;                /* Torontonian, high part                                */
     double tor_lo;             /* low part of the double-double value                   */
     double sum_abs;            /* sum of |term|; R = sum_abs / |tor| is the cancellation */
-    double err_est;            /* estimated relative error from FP64 term rounding       */
+    double err_est;            /* estimated relative error from term rounding (FP64, or
+                                  2^-104 with TOR_FACTOR_DD)                            */
     unsigned long long subsets;/* 2^n                                                   */
     int status;                /* TOR_OK or an error for this matrix                    */
-    int path;                  /* 1 = real quadrature path, 2 = complex path            */
+    int path;                  /* 1 = real quadrature path, 2 = complex path,
+                                  3 = real quadrature path with a double-double factor  */
     float device_ms;           /* device time of the launch that produced it            */
 } tor_result;
 
@@ -157,7 +170,8 @@ int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out);
 int tor_serve_config(tor_ctx *ctx, long long chunk_subsets, double oldest_share, int max_queue);
 
 /* Autotuner.  For every n in [n_min, n_max] and each selected path
- * (TOR_TUNE_REAL: Gaussian-state matrices, TOR_TUNE_COMPLEX: general ones)
+ * (TOR_TUNE_REAL: Gaussian-state matrices, TOR_TUNE_COMPLEX: general ones,
+ * TOR_TUNE_QUAD: the double-double factor)
  * time the recursive kernel over split depths k and persistent waves per CU
  * and keep the fastest pair for that size in the context; later evaluations
  * (single, batched and served) use it.  Timing does not depend on the matrix
@@ -165,6 +179,7 @@ int tor_serve_config(tor_ctx *ctx, long long chunk_subsets, double oldest_share,
  * duration of the timing runs. */
 #define TOR_TUNE_REAL 0x1u
 #define TOR_TUNE_COMPLEX 0x2u
+#define TOR_TUNE_QUAD 0x4u
 int tor_autotune(tor_ctx *ctx, int n_min, int n_max, unsigned paths);
 
 /* Write the context's tuning table as JSON (arch, CU count, entries). */

@@ -5,6 +5,8 @@ Kaposi et al. (arXiv 2109.04528) as HIP kernels for gfx950 behind a C ABI.
     with Context() as ctx:
         r = ctx.eval(O)            # O: 2n x 2n complex128 (numpy or torch)
         r.value, r.cancellation   # Tor(O) and R = sum|t| / |Tor|
+    with Context(flags=TOR_FACTOR_DD) as ctx:
+        ctx.eval(O)                # the same with a double-double factor
 
 The binding only marshals arguments; the library must be built (see build.py)
 and there is no CPU fallback.
@@ -14,7 +16,7 @@ from ._lib import (  # noqa: F401
     TOR_OK, TOR_PENDING, TOR_E_INVAL, TOR_E_NOT_PD, TOR_E_NUMERIC, TOR_E_BUSY,
     TOR_E_NOMEM, TOR_E_DEVICE, TOR_E_TIMEOUT, TOR_E_UNKNOWN,
     TOR_ACCUM_DD, TOR_ACCUM_FP64, TOR_INPUT_DEVICE, TOR_CHECK_HERMITIAN, TOR_FORCE_COMPLEX,
-    TOR_TUNE_REAL, TOR_TUNE_COMPLEX,
+    TOR_FACTOR_DD, TOR_TUNE_REAL, TOR_TUNE_COMPLEX, TOR_TUNE_QUAD,
 )
 
 

@@ -33,6 +33,7 @@ TOR_ACCUM_FP64 = 1
 TOR_INPUT_DEVICE = 0x1
 TOR_CHECK_HERMITIAN = 0x2
 TOR_FORCE_COMPLEX = 0x4
+TOR_FACTOR_DD = 0x8
 
 # every symbol include/tor.h declares
 EXPORTS = [
@@ -44,6 +45,7 @@ EXPORTS = [
 
 TOR_TUNE_REAL = 0x1
 TOR_TUNE_COMPLEX = 0x2
+TOR_TUNE_QUAD = 0x4
 
 
 class tor_options(ctypes.Structure):

@@ -76,6 +76,101 @@ __device__ __forceinline__ c64 upd_diag(c64 h, c64 u1, c64 r1, c64 u2, c64 r2)
     return c64{xr, 0.0};
 }
 
+// ---- double-double arithmetic (the factor of the higher-precision mode) -----
+// Error-free transformations: Knuth's TwoSum, Dekker's Fast2Sum, and the
+// exact product by FMA; the double-double operations built from them follow
+// Dekker (1971) and Hida, Li and Bailey's double-double library: results are
+// renormalised so that |lo| <= ulp(hi) / 2, with relative errors of a few
+// units of 2^-104 (the "sloppy" addition: absolute error a few 2^-104 times
+// |a| + |b|, which is the error model the Cholesky backward-error analysis
+// needs).  Contraction of a product and a sum into one FMA is switched off
+// inside these routines: it would round the product away from the value its
+// separately computed rounding error belongs to, and the transformation
+// would no longer be exact.
+__device__ __forceinline__ ddr fast2sum(double a, double b)
+{
+#pragma clang fp contract(off)
+    const double s = a + b;
+    return ddr{s, b - (s - a)};
+}
+__device__ __forceinline__ ddr dd_add(ddr a, ddr b)
+{
+#pragma clang fp contract(off)
+    const double s = a.hi + b.hi;
+    const double bb = s - a.hi;
+    double e = (a.hi - (s - bb)) + (b.hi - bb);
+    e += a.lo + b.lo;
+    return fast2sum(s, e);
+}
+__device__ __forceinline__ ddr dd_neg(ddr a) { return ddr{-a.hi, -a.lo}; }
+__device__ __forceinline__ ddr dd_mul(ddr a, ddr b)
+{
+#pragma clang fp contract(off)
+    const double p = a.hi * b.hi;
+    double e = fma(a.hi, b.hi, -p);
+    e = fma(a.hi, b.lo, e);
+    e = fma(a.lo, b.hi, e);
+    return fast2sum(p, e);
+}
+// h - u1 r1 - u2 r2 with one renormalisation: the two leading products and
+// their sum with h.hi are error-free, every lower-order part is summed in
+// double
+__device__ __forceinline__ ddr dd_upd(ddr h, ddr u1, ddr r1, ddr u2, ddr r2)
+{
+#pragma clang fp contract(off)
+    const double p1 = u1.hi * r1.hi, p2 = u2.hi * r2.hi;
+    const double e1 = fma(u1.hi, r1.hi, -p1), e2 = fma(u2.hi, r2.hi, -p2);
+    double s = h.hi - p1;
+    double bb = s - h.hi;
+    double t = (h.hi - (s - bb)) + (-p1 - bb);
+    const double s2 = s - p2;
+    bb = s2 - s;
+    t += (s - (s2 - bb)) + (-p2 - bb);
+    double lo = h.lo - e1 - e2;
+    lo = fma(-u1.hi, r1.lo, lo);
+    lo = fma(-u1.lo, r1.hi, lo);
+    lo = fma(-u2.hi, r2.lo, lo);
+    lo = fma(-u2.lo, r2.hi, lo);
+    return fast2sum(s2, t + lo);
+}
+
+__device__ __forceinline__ ddr re(ddr a) { return a; }
+__device__ __forceinline__ ddr abs2(ddr a) { return dd_mul(a, a); }
+__device__ __forceinline__ ddr scale(ddr a, ddr s) { return dd_mul(a, s); }
+__device__ __forceinline__ ddr zero_of(ddr) { return ddr{0.0, 0.0}; }
+__device__ __forceinline__ ddr sub_mul(ddr a, ddr b, ddr c) { return dd_add(a, dd_neg(dd_mul(b, c))); }
+__device__ __forceinline__ ddr conj_of(ddr a) { return a; }
+__device__ __forceinline__ ddr fix_diag(ddr a) { return a; }
+__device__ __forceinline__ ddr upd(ddr h, ddr u1, ddr r1, ddr u2, ddr r2) { return dd_upd(h, u1, r1, u2, r2); }
+__device__ __forceinline__ ddr upd_diag(ddr h, ddr u1, ddr r1, ddr u2, ddr r2) { return dd_upd(h, u1, r1, u2, r2); }
+
+// real type of a scalar: double for double and c64, ddr for ddr
+template <class S>
+struct RealOf {
+    using type = double;
+};
+template <>
+struct RealOf<ddr> {
+    using type = ddr;
+};
+template <class S>
+using RT = typename RealOf<S>::type;
+
+template <class R>
+__device__ __forceinline__ R rconst(double x);
+template <>
+__device__ __forceinline__ double rconst<double>(double x) { return x; }
+template <>
+__device__ __forceinline__ ddr rconst<ddr>(double x) { return ddr{x, 0.0}; }
+__device__ __forceinline__ double rmul(double a, double b) { return a * b; }
+__device__ __forceinline__ ddr rmul(ddr a, ddr b) { return dd_mul(a, b); }
+__device__ __forceinline__ bool is_pos(double a) { return a > 0.0; }
+__device__ __forceinline__ bool is_pos(ddr a) { return a.hi > 0.0; }
+// determinant of the last 2x2 block [[a, conj b], [b, g]]
+__device__ __forceinline__ double det_last(double a, double b, double g) { return fma(a, g, -abs2(b)); }
+__device__ __forceinline__ double det_last(double a, c64 b, double g) { return fma(a, g, -abs2(b)); }
+__device__ __forceinline__ ddr det_last(ddr a, ddr b, ddr g) { return dd_add(dd_mul(a, g), dd_neg(dd_mul(b, b))); }
+
 // ---- reciprocal and reciprocal square root ---------------------------------
 // The hardware seeds (v_rcp_f64, v_rsq_f64) are good to about 2^-24; one
 // correction of third order brings them to within one unit in the last place:
@@ -98,6 +193,35 @@ __device__ __forceinline__ double rsqrt_nr(double x)
     return fma(y * d, fma(d, 0.375, 0.5), y);
 }
 
+// double-double versions: the double result y0 (about one ulp) and one
+// Newton correction with the residual formed to double-double accuracy,
+//   1/x:        r = 1 - x y0,      y = y0 + y0 r
+//   1/sqrt(x):  r = 1 - x y0^2,    y = y0 + y0 r / 2
+// (r is about 2^-52, so the neglected r^2 terms are below 2^-104)
+__device__ __forceinline__ ddr rcp_nr(ddr x)
+{
+#pragma clang fp contract(off)
+    const double y0 = rcp_nr(x.hi);
+    const double p = x.hi * y0;
+    const double pe = fma(x.hi, y0, -p);
+    const double r = fma(-x.lo, y0, (1.0 - p) - pe);
+    return fast2sum(y0, y0 * r);
+}
+
+__device__ __forceinline__ ddr rsqrt_nr(ddr x)
+{
+#pragma clang fp contract(off)
+    const double y0 = rsqrt_nr(x.hi);
+    const double q = y0 * y0;
+    const double qe = fma(y0, y0, -q);
+    const double p = x.hi * q;
+    const double pe = fma(x.hi, q, -p);
+    double r = (1.0 - p) - pe;
+    r = fma(-x.hi, qe, r);
+    r = fma(-x.lo, q, r);
+    return fast2sum(y0, 0.5 * y0 * r);
+}
+
 // ---- wave-uniform broadcast ------------------------------------------------
 // The value of the first active lane, in scalar registers.  Loop bounds and
 // exits built from it are provably uniform, so the compiler emits scalar
@@ -114,7 +238,7 @@ __device__ __forceinline__ unsigned long long bcast_first(unsigned long long v)
 // ---- 2x2 pivot of one include step
 template <class S>
 struct Piv {
-    double inv_a, inv_g, pdet;
+    RT<S> inv_a, inv_g, pdet;
     S ba;  // beta / alpha
 };
 
@@ -127,6 +251,18 @@ __device__ __forceinline__ Piv<S> pivot(double a, S b, double g)
     double g1 = g - p.inv_a * abs2(b);  // gamma - |beta|^2 / alpha
     p.inv_g = rcp_nr(g1);
     p.pdet = a * g1;  // |L_pp|^2 |L_p+1,p+1|^2
+    return p;
+}
+
+__device__ __forceinline__ Piv<ddr> pivot(ddr a, ddr b, ddr g)
+{
+#pragma clang fp contract(off)
+    Piv<ddr> p;
+    p.inv_a = rcp_nr(a);
+    p.ba = dd_mul(b, p.inv_a);
+    const ddr g1 = sub_mul(g, b, p.ba);  // gamma - beta^2 / alpha
+    p.inv_g = rcp_nr(g1);
+    p.pdet = dd_mul(a, g1);
     return p;
 }
 
@@ -143,6 +279,7 @@ __device__ __forceinline__ Piv<S> pivot(double a, S b, double g)
 // exponent(r1) >= exponent(r0), or the difference is exact by Sterbenz's
 // lemma), i.e. whenever that mode's pivot determinant is at most 4.
 struct AccDD {
+    static constexpr bool kDD = true;  // reduce as double-double
     double hi = 0.0, lo = 0.0, abs_sum = 0.0, frame = 1.0;
     __device__ __forceinline__ void two_sum(double t)
     {
@@ -179,6 +316,7 @@ struct AccDD {
 // plain FP64 sum of the same terms, one by one, kept only for the dd-vs-FP64
 // comparison
 struct AccF64 {
+    static constexpr bool kDD = false;
     double hi = 0.0, lo = 0.0, abs_sum = 0.0, frame = 1.0;
     template <int SG>
     __device__ __forceinline__ void add(double r)
@@ -196,6 +334,39 @@ struct AccF64 {
     __device__ __forceinline__ void set_frame(double f)
     {
         hi *= f * frame;
+        frame = f;
+    }
+};
+
+// double-double sum of double-double terms (the higher-precision mode); the
+// pair of the last mode is formed as a double-double difference first
+struct AccQ {
+    static constexpr bool kDD = true;
+    double hi = 0.0, lo = 0.0, abs_sum = 0.0, frame = 1.0;
+    __device__ __forceinline__ void acc(double th, double tl)
+    {
+        const ddr s = dd_add(ddr{hi, lo}, ddr{th, tl});
+        hi = s.hi;
+        lo = s.lo;
+    }
+    template <int SG>
+    __device__ __forceinline__ void add(ddr r)
+    {
+        acc(SG * r.hi, SG * r.lo);
+        abs_sum += r.hi;
+    }
+    template <int SG>
+    __device__ __forceinline__ void add_pair(ddr r0, ddr r1)
+    {
+        const ddr d = dd_add(r1, dd_neg(r0));
+        acc(SG * d.hi, SG * d.lo);
+        abs_sum += r0.hi + r1.hi;
+    }
+    __device__ __forceinline__ void set_frame(double f)
+    {
+        const double m = f * frame;
+        hi *= m;
+        lo *= m;
         frame = f;
     }
 };

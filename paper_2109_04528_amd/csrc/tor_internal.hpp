@@ -11,6 +11,11 @@ struct __align__(16) c64 {
     double x, y;  // re, im
 };
 
+// real double-double: the unevaluated sum hi + lo, |lo| <= ulp(hi) / 2
+struct __align__(16) ddr {
+    double hi, lo;
+};
+
 // Device layout of a node of s modes: the Hermitian (or real symmetric)
 // 2s x 2s matrix in mode-interleaved rows, REVERSED (the next mode to decide
 // owns the two highest rows), cut into its lower-triangular 2x2 mode blocks
@@ -84,17 +89,26 @@ constexpr int REAL_T = 5;
 constexpr int REAL_B = 6;
 constexpr int REAL_L = 2;
 constexpr int REAL_R = REAL_T + REAL_B;
+// double-double factor (real quadrature form only)
+constexpr int QUAD_T = 3;
+constexpr int QUAD_B = 6;
+constexpr int QUAD_L = 2;
+constexpr int QUAD_R = QUAD_T + QUAD_B;
+
+// kernel paths: general Hermitian input, the real quadrature form of a
+// Gaussian-state matrix, and that form with a double-double factor
+enum { PATH_CPLX = 0, PATH_REAL = 1, PATH_QUAD = 2, NPATH = 3 };
 constexpr int MAX_N = 48;
 constexpr int MAX_FIT = 8;  // persistent one-wave workgroups per CU, at most
 
 // host-side launchers (defined in tor_kernels.hip)
-hipError_t launch_main(bool real_path, bool dd, const MainParams &p, int grid, hipStream_t s);
+hipError_t launch_main(int path, bool dd, const MainParams &p, int grid, hipStream_t s);
 hipError_t launch_reduce(const ProblemDesc *probs, int nprob, double *results, bool dd, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, int count, hipStream_t s);
 hipError_t launch_plain(const PlainParams &p, int grid, hipStream_t s);
 hipError_t launch_plain_reduce(const double *partials, int nwaves, double *result, hipStream_t s);
 hipError_t launch_math_probe(const double *x, double *out, int count, hipStream_t s);
 // resident one-wave workgroups of the main kernel per CU (0 on error)
-int main_occupancy(bool real_path);
+int main_occupancy(int path);
 
 }  // namespace tor

@@ -153,12 +153,12 @@ __device__ __forceinline__ void block_ab(int bi, int &a, int &b)
 // receives its first nlds blocks (the tier-A leaf) as a node of nlds blocks.
 template <class S>
 __device__ void elim_global(const S *__restrict__ src, int snb, S *__restrict__ dst, S *lds, int nlds, int s,
-                            int lane, double &pdet, int &bad)
+                            int lane, RT<S> &pdet, int &bad)
 {
     const int m = s - 1;
     const Piv<S> pv = node_pivot(src, snb, m);
     pdet = pv.pdet;
-    if (!(pv.pdet > 0.0) || !(pv.inv_a > 0.0))
+    if (!is_pos(pv.pdet) || !is_pos(pv.inv_a))
         bad = 1;
     const int nbo = dst ? NB(m) : nlds;
     for (int bi = lane; bi < nbo; bi += 64) {
@@ -217,14 +217,14 @@ struct TierB {
     const uint8_t *srcNB;   // per view: blocks per granule array of that node
     const uint8_t *srcDet;  // per view: determinant slot (0xff: tier-A leaf)
     const uint16_t *blkAB;  // block index -> a | b << 8
-    double *nInv;           // per include node of a level: 1/alpha, 1/gamma1
+    RT<S> *nInv;            // per include node of a level: 1/alpha, 1/gamma1
     S *nBa;                 // per include node of a level: beta/alpha
-    double *ndet;           // per include node: running determinant
+    RT<S> *ndet;            // per include node: running determinant
 };
 
 // tier B, level J: every include node of level J from its parent of level J-1
 template <class S, int R, int J>
-__device__ __forceinline__ void tierB_level(const TierB<S> &tb, double leafDet, int lane, int &bad)
+__device__ __forceinline__ void tierB_level(const TierB<S> &tb, RT<S> leafDet, int lane, int &bad)
 {
     constexpr int m = R - J;          // pivot mode of the parent (it has m+1 modes)
     constexpr int NN = 1 << (J - 1);  // include nodes at level J
@@ -232,13 +232,13 @@ __device__ __forceinline__ void tierB_level(const TierB<S> &tb, double leafDet, 
     if (lane < NN) {
         const S *par = tb.buf + tb.srcOff[NN - 1 + lane];
         const int di = tb.srcDet[NN - 1 + lane];
-        const double pdp = di == 0xff ? leafDet : tb.ndet[di];
+        const RT<S> pdp = di == 0xff ? leafDet : tb.ndet[di];
         const Piv<S> pq = node_pivot(par, (int)tb.srcNB[NN - 1 + lane], m);
         tb.nInv[2 * lane] = pq.inv_a;
         tb.nInv[2 * lane + 1] = pq.inv_g;
         tb.nBa[lane] = pq.ba;
-        tb.ndet[NN - 1 + lane] = pdp * pq.pdet;
-        if (!(pq.pdet > 0.0) || !(pq.inv_a > 0.0))
+        tb.ndet[NN - 1 + lane] = rmul(pdp, pq.pdet);
+        if (!is_pos(pq.pdet) || !is_pos(pq.inv_a))
             bad = 1;
     }
     __syncthreads();
@@ -264,7 +264,7 @@ __device__ __forceinline__ void tierB_level(const TierB<S> &tb, double leafDet, 
 }
 
 template <class S, int R, int J, int B>
-__device__ __forceinline__ void tierB(const TierB<S> &tb, double leafDet, int lane, int &bad)
+__device__ __forceinline__ void tierB(const TierB<S> &tb, RT<S> leafDet, int lane, int &bad)
 {
     if constexpr (J < B) {
         tierB_level<S, R, J>(tb, leafDet, lane, bad);
@@ -302,31 +302,31 @@ __device__ __forceinline__ void elim_regs(const S *h, const Piv<S> &pq, S *hn)
 // (-1)^(#excluded) of its subsets relative to the lane's frame (see the
 // accumulators); det is the running determinant.
 template <class S, int M, int SG, class Acc>
-__device__ __forceinline__ void tail(const S *h, double det, Acc &acc, int &bad)
+__device__ __forceinline__ void tail(const S *h, RT<S> det, Acc &acc, int &bad)
 {
     if constexpr (M == 0) {
         acc.template add<SG>(rsqrt_nr(det));
     } else if constexpr (M == 1) {
         // exclude (sign -SG) and include (sign SG) of the last mode
-        const double a = re(h[0]);
+        const RT<S> a = re(h[0]);
         const S b = h[1];
-        const double g = re(h[2]);
-        const double pd = fma(a, g, -abs2(b));  // det of the last 2x2 block
-        if (!(a > 0.0) || !(pd > 0.0))
+        const RT<S> g = re(h[2]);
+        const RT<S> pd = det_last(a, b, g);  // det of the last 2x2 block
+        if (!is_pos(a) || !is_pos(pd))
             bad = 1;
-        acc.template add_pair<SG>(rsqrt_nr(det), rsqrt_nr(det * pd));
+        acc.template add_pair<SG>(rsqrt_nr(det), rsqrt_nr(rmul(det, pd)));
     } else {
         tail<S, M - 1, -SG, Acc>(h, det, acc, bad);  // exclude the next mode
         constexpr int p = 2 * M - 2;
-        const double a = re(h[pidx(p, p)]);
+        const RT<S> a = re(h[pidx(p, p)]);
         const S b = h[pidx(p + 1, p)];
-        const double g = re(h[pidx(p + 1, p + 1)]);
+        const RT<S> g = re(h[pidx(p + 1, p + 1)]);
         const Piv<S> pq = pivot(a, b, g);
-        if (!(a > 0.0) || !(pq.pdet > 0.0))
+        if (!is_pos(a) || !is_pos(pq.pdet))
             bad = 1;
         S hn[E(M - 1)];
         elim_regs<S, M>(h, pq, hn);
-        tail<S, M - 1, SG, Acc>(hn, det * pq.pdet, acc, bad);
+        tail<S, M - 1, SG, Acc>(hn, rmul(det, pq.pdet), acc, bad);
     }
 }
 
@@ -342,16 +342,16 @@ __device__ __forceinline__ S node_el(const S *node, int nb, int x, int y)
 // which leaves the prefix exactly as it is, so that both kinds of lanes run
 // the same instructions.
 template <class S>
-__device__ __forceinline__ Piv<S> lane_pivot(double a, S b, double g, bool inc, int &bad)
+__device__ __forceinline__ Piv<S> lane_pivot(RT<S> a, S b, RT<S> g, bool inc, int &bad)
 {
     Piv<S> pq = pivot(a, b, g);
-    if (inc && (!(a > 0.0) || !(pq.pdet > 0.0)))
+    if (inc && (!is_pos(a) || !is_pos(pq.pdet)))
         bad = 1;
     if (!inc) {
-        pq.inv_a = 0.0;
-        pq.inv_g = 0.0;
+        pq.inv_a = rconst<RT<S>>(0.0);
+        pq.inv_g = rconst<RT<S>>(0.0);
         pq.ba = zero_of(b);
-        pq.pdet = 1.0;
+        pq.pdet = rconst<RT<S>>(1.0);
     }
     return pq;
 }
@@ -364,7 +364,7 @@ __device__ __forceinline__ Piv<S> lane_pivot(double a, S b, double g, bool inc, 
 // once and receives the L rank-2 updates in turn, so only the pivot rows and
 // the T-mode result are held in registers.
 template <class S, int T, int B, int L, class Acc>
-__device__ __forceinline__ void tierC(const TierB<S> &tb, double leafDet, int leafInc, int N, int lane, Acc &acc,
+__device__ __forceinline__ void tierC(const TierB<S> &tb, RT<S> leafDet, int leafInc, int N, int lane, Acc &acc,
                                       int &bad)
 {
     static_assert(L == 1 || L == 2, "one or two lane levels");
@@ -375,7 +375,7 @@ __device__ __forceinline__ void tierC(const TierB<S> &tb, double leafDet, int le
     const S *src = tb.buf + tb.srcOff[NP + ip];
     const int snb = tb.srcNB[NP + ip];
     const int di = tb.srcDet[NP + ip];
-    double det = di == 0xff ? leafDet : tb.ndet[di];
+    RT<S> det = di == 0xff ? leafDet : tb.ndet[di];
     const bool inc1 = (lane >> (L - 1)) & 1;  // first lane level
     const bool inc0 = lane & 1;               // second (L == 2)
 
@@ -389,7 +389,7 @@ __device__ __forceinline__ void tierC(const TierB<S> &tb, double leafDet, int le
         r1[y] = node_el(src, snb, p1, y);
         r2[y] = sub_mul(node_el(src, snb, p1 + 1, y), r1[y], q1.ba);
     }
-    det *= q1.pdet;
+    det = rmul(det, q1.pdet);
     int includes = leafInc + __popc(ip) + inc1;
 
     // second level (L == 2): its pivot rows are rows pT, pT+1 of the first
@@ -413,7 +413,7 @@ __device__ __forceinline__ void tierC(const TierB<S> &tb, double leafDet, int le
             s1[y] = c[0][y];
             s2[y] = sub_mul(c[1][y], s1[y], q2.ba);
         }
-        det *= q2.pdet;
+        det = rmul(det, q2.pdet);
         includes += inc0;
     }
 
@@ -450,13 +450,13 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
     constexpr int NN_MAX = 1 << (BL - 1);    // include nodes of the last LDS level
     __shared__ S bufB[node_place(R, BL, (int)sizeof(S), 1 << BL) / (int)sizeof(S)];
     __shared__ S nBa[NN_MAX];
-    __shared__ double nInv[2 * NN_MAX];
-    __shared__ double ndet[1 << BL];
+    __shared__ RT<S> nInv[2 * NN_MAX];
+    __shared__ RT<S> ndet[1 << BL];
     __shared__ uint16_t srcOff[(1 << (BL + 1)) - 1];
     __shared__ uint8_t srcNB[(1 << (BL + 1)) - 1];
     __shared__ uint8_t srcDet[(1 << (BL + 1)) - 1];
     __shared__ uint16_t blkAB[NB(R - 1)];
-    __shared__ double sdet[MAX_N + 1];
+    __shared__ RT<S> sdet[MAX_N + 1];
     __shared__ int sinc[MAX_N + 1];
 
     const int lane = threadIdx.x;
@@ -491,14 +491,14 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
         // the matrix NB(N), stack slot l a node of N-l modes, NB(N-l))
         const S *rsrc = C;
         int rnb = NB(N);
-        double rdet = 1.0;
+        RT<S> rdet = rconst<RT<S>>(1.0);
         int rinc = 0;
         for (int l = 0; l < k; ++l) {
             if ((root >> l) & 1) {
                 S *dst = wscr + slot_off(N, l + 1);
-                double pd;
+                RT<S> pd;
                 elim_global<S>(rsrc, rnb, dst, nullptr, 0, N - l, lane, pd, bad);
-                rdet *= pd;
+                rdet = rmul(rdet, pd);
                 ++rinc;
                 rsrc = dst;
                 rnb = NB(N - l - 1);
@@ -508,7 +508,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
         Acc acc;
         const long long nleaf = 1ll << D;
         for (long long x = 0; x < nleaf; ++x) {
-            double ldet;
+            RT<S> ldet;
             int linc;
             if (x == 0) {
                 // the first R modes of the root node, restrided to NB(R)
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                 const long long xr = x >> (t + 1);
                 const S *s;
                 int snb;
-                double sd;
+                RT<S> sd;
                 int si;
                 if (xr == 0) {
                     s = rsrc;
@@ -545,9 +545,9 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                 // step: that child goes to LDS only; shallower ones also go to
                 // their stack slot
                 S *dst = (lvl + 1 < LA) ? wscr + slot_off(N, lvl + 1) : nullptr;
-                double pd;
+                RT<S> pd;
                 elim_global<S>(s, snb, dst, bufB, NB(R), N - lvl, lane, pd, bad);
-                ldet = sd * pd;
+                ldet = rmul(sd, pd);
                 linc = si + 1;
                 if (lane == 0) {
                     sdet[lvl + 1] = ldet;
@@ -561,7 +561,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
         }
 
         double h = acc.hi * acc.frame, l = acc.lo * acc.frame, ab = acc.abs_sum;
-        constexpr bool is_dd = std::is_same<Acc, AccDD>::value;
+        constexpr bool is_dd = Acc::kDD;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             double oh = __shfl_xor(h, off), ol = __shfl_xor(l, off), oa = __shfl_xor(ab, off);
@@ -778,29 +778,34 @@ __global__ void tor_math_probe(const double *x, double *out, int count)
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_main(bool real_path, bool dd, const MainParams &p, int grid, hipStream_t s)
+hipError_t launch_main(int path, bool dd, const MainParams &p, int grid, hipStream_t s)
 {
-    if (real_path) {
+    if (path == PATH_QUAD) {
+        hipLaunchKernelGGL((tor_main<ddr, QUAD_T, QUAD_B, QUAD_L, AccQ>), dim3(grid), dim3(64), 0, s, p);
+    } else if (path == PATH_REAL) {
         if (dd)
             hipLaunchKernelGGL((tor_main<double, REAL_T, REAL_B, REAL_L, AccDD>), dim3(grid), dim3(64), 0, s, p);
         else
             hipLaunchKernelGGL((tor_main<double, REAL_T, REAL_B, REAL_L, AccF64>), dim3(grid), dim3(64), 0, s, p);
-        return hipGetLastError();
+    } else {
+        if (dd)
+            hipLaunchKernelGGL((tor_main<c64, CPLX_T, CPLX_B, CPLX_L, AccDD>), dim3(grid), dim3(64), 0, s, p);
+        else
+            hipLaunchKernelGGL((tor_main<c64, CPLX_T, CPLX_B, CPLX_L, AccF64>), dim3(grid), dim3(64), 0, s, p);
     }
-    if (dd)
-        hipLaunchKernelGGL((tor_main<c64, CPLX_T, CPLX_B, CPLX_L, AccDD>), dim3(grid), dim3(64), 0, s, p);
-    else
-        hipLaunchKernelGGL((tor_main<c64, CPLX_T, CPLX_B, CPLX_L, AccF64>), dim3(grid), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 
-int main_occupancy(bool real_path)
+int main_occupancy(int path)
 {
     int n = 0;
-    hipError_t e = real_path ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                   &n, tor_main<double, REAL_T, REAL_B, REAL_L, AccDD>, 64, 0)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                   &n, tor_main<c64, CPLX_T, CPLX_B, CPLX_L, AccDD>, 64, 0);
+    hipError_t e;
+    if (path == PATH_QUAD)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tor_main<ddr, QUAD_T, QUAD_B, QUAD_L, AccQ>, 64, 0);
+    else if (path == PATH_REAL)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tor_main<double, REAL_T, REAL_B, REAL_L, AccDD>, 64, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tor_main<c64, CPLX_T, CPLX_B, CPLX_L, AccDD>, 64, 0);
     return e == hipSuccess ? n : 0;
 }
 

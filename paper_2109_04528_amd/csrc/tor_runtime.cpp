@@ -44,14 +44,16 @@ using namespace tor;
 namespace {
 
 constexpr double kU = 1.1102230246251565e-16;  // FP64 unit roundoff
+constexpr double kUdd = 4.930380657631324e-32; // 2^-104, double-double roundoff
 
 struct Staged {
     int n = 0;                    // modes of the input
     int N = 0;                    // modes after padding (complex path)
     std::vector<c64> packed;      // complex device layout
-    bool real = false;            // Gaussian-state structure found: real path
-    int Nr = 0;                   // modes after padding (real path)
+    int path = PATH_CPLX;         // PATH_REAL when the Gaussian-state structure is found
+    int Nr = 0;                   // modes after padding (real and double-double paths)
     std::vector<double> packed_r; // real symmetric form, same layout
+    std::vector<ddr> packed_q;    // the same form in double-double
 };
 
 struct Request {
@@ -60,7 +62,7 @@ struct Request {
     tor_result res{};
     bool done = false;
     // device state once admitted
-    bool real = false;
+    int path = PATH_CPLX;
     int N = 0, k = 0;
     long long nroots = 0, next_root = 0;
     long long root_work = 0;  // subsets per root
@@ -87,13 +89,11 @@ struct tor_ctx {
     bool own_ws = false;
     tor_options opt{};
     int num_cu = 0;
-    int fit[2] = {1, 1};  // one-wave workgroups per CU the LDS allows (complex, real)
-    int waves_per_cu = 4;
-    int grid = 0;         // complex-path persistent grid
-    int grid_r = 0;       // real-path persistent grid
+    int fit[NPATH] = {1, 1, 1};  // resident one-wave workgroups per CU, per path
+    int grid[NPATH] = {0, 0, 0}; // persistent grid per path
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::mutex mu;        // serialises device work on this context
-    TuneEntry tune[2][MAX_N + 1];
+    TuneEntry tune[NPATH][MAX_N + 1];
     std::string arch;
 
     // serving
@@ -156,8 +156,30 @@ bool hpd_check(int n2, const std::vector<double> &C)
 // (w is unitary and acts inside each mode), so the Torontonian is unchanged.
 // C is taken as structured when both defining relations hold to 64 units of
 // roundoff of max |C|; it is then symmetrised exactly (P <- (P + conj P')/2,
-// Q <- (Q + Q^T)/2) before the transform.
-void stage_real(int n, const std::vector<double> &C, Staged &st)
+// Q <- (Q + Q^T)/2) before the transform.  With quad set the form is built in
+// double-double from O itself (1 - O_ii and every sum of the transform are
+// exact or rounded to 2^-106), for the double-double factor.
+// Host double-double helpers: exact sum by TwoSum, renormalised sum.
+struct hdd {
+    double hi, lo;
+};
+hdd h_two_sum(double a, double b)
+{
+    const double s = a + b, bb = s - a;
+    return hdd{s, (a - (s - bb)) + (b - bb)};
+}
+hdd h_add(hdd a, hdd b)
+{
+    hdd s = h_two_sum(a.hi, b.hi);
+    const hdd t = h_two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = h_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return h_two_sum(s.hi, s.lo);
+}
+hdd h_neg(hdd a) { return hdd{-a.hi, -a.lo}; }
+
+bool stage_real(int n, const std::vector<double> &C, const double *O, long ld, bool quad, Staged &st)
 {
     const int n2 = 2 * n;
     auto cre = [&](int a, int b) { return C[2 * ((size_t)a * n2 + b)]; };
@@ -173,9 +195,45 @@ void stage_real(int n, const std::vector<double> &C, Staged &st)
             dev = std::max(dev, std::hypot(cre(i + n, j) - cre(j + n, i), cim(i + n, j) - cim(j + n, i)));
         }
     if (!(dev <= 64.0 * kU * std::max(cmax, 1.0)))
-        return;
-    const int N = std::max(n, REAL_R);
+        return false;
+    const int N = std::max(n, quad ? QUAD_R : REAL_R);
     st.Nr = N;
+    if (quad) {
+        // entry (a, b) of I - O from the lower triangle of O, in double-double
+        auto cdd = [&](int a, int b, hdd &re_, hdd &im_) {
+            const bool up = a < b;
+            const int i = up ? b : a, j = up ? a : b;
+            const double orr = O[2 * ((size_t)i * ld + j)], oi = O[2 * ((size_t)i * ld + j) + 1];
+            re_ = h_two_sum(i == j ? 1.0 : 0.0, -orr);
+            im_ = hdd{i == j ? 0.0 : (up ? oi : -oi), 0.0};
+        };
+        auto qblk = [&](int mi, int mj, int ci, int cj) -> hdd {
+            if (mi >= n || mj >= n)
+                return hdd{(mi == mj && ci == cj) ? 0.5 : 0.0, 0.0};
+            hdd p1r, p1i, p2r, p2i, q1r, q1i, q2r, q2i;
+            cdd(mi, mj, p1r, p1i);
+            cdd(mi + n, mj + n, p2r, p2i);
+            cdd(mi, mj + n, q1r, q1i);
+            cdd(mj, mi + n, q2r, q2i);
+            auto half = [](hdd v) { return hdd{0.5 * v.hi, 0.5 * v.lo}; };
+            const hdd pr = half(h_add(p1r, p2r)), pi = half(h_add(p1i, h_neg(p2i)));
+            const hdd qr = half(h_add(q1r, q2r)), qi = half(h_add(q1i, q2i));
+            if (ci == 0 && cj == 0) return h_add(pr, qr);
+            if (ci == 0 && cj == 1) return h_add(qi, h_neg(pi));
+            if (ci == 1 && cj == 0) return h_add(pi, qi);
+            return h_add(pr, h_neg(qr));
+        };
+        st.packed_q.assign((size_t)NSZ(N), ddr{0.0, 0.0});
+        for (int a = 0; a < N; a++)
+            for (int b = 0; b <= a; b++)
+                for (int e = 0; e < 4; e++) {
+                    const int qi = 2 * N - 1 - (2 * a + (e >> 1)), qj = 2 * N - 1 - (2 * b + (e & 1));
+                    const hdd v = qblk(qi / 2, qj / 2, qi % 2, qj % 2);
+                    st.packed_q[(size_t)gpos((int)sizeof(ddr), NB(N), bidx(a, b), e)] = ddr{v.hi, v.lo};
+                }
+        st.path = PATH_QUAD;
+        return true;
+    }
     st.packed_r.assign((size_t)NSZ(N), 0.0);
     // real 2x2 block of modes (mi, mj), row component ci, column component cj
     auto rblk = [&](int mi, int mj, int ci, int cj) -> double {
@@ -198,7 +256,8 @@ void stage_real(int n, const std::vector<double> &C, Staged &st)
                 st.packed_r[(size_t)gpos((int)sizeof(double), NB(N), bidx(a, b), e)] =
                     rblk(qi / 2, qj / 2, qi % 2, qj % 2);
             }
-    st.real = true;
+    st.path = PATH_REAL;
+    return true;
 }
 
 // Validate, check, pack one matrix.  O is host memory.
@@ -261,43 +320,58 @@ int stage_matrix(int n, const double *O, long ld, unsigned flags, int min_modes,
                     v.y = 0.0;
                 st.packed[(size_t)gpos((int)sizeof(c64), NB(N), bidx(a, b), e)] = v;
             }
-    st.real = false;
-    if (!(flags & TOR_FORCE_COMPLEX) && n > 0)
-        stage_real(n, C, st);
+    st.path = PATH_CPLX;
+    if (flags & TOR_FACTOR_DD) {
+        // the double-double factor runs on the real form only
+        if (!stage_real(n, C, O, ld, true, st))
+            return TOR_E_INVAL;
+    } else if (!(flags & TOR_FORCE_COMPLEX) && n > 0) {
+        stage_real(n, C, O, ld, false, st);
+    }
     return TOR_OK;
 }
 
 
-int path_R(bool real) { return real ? REAL_R : CPLX_R; }
-int modes_of(const Staged &m, bool real) { return real ? m.Nr : m.N; }
+int path_R(int path) { return path == PATH_QUAD ? QUAD_R : path == PATH_REAL ? REAL_R : CPLX_R; }
+int modes_of(const Staged &m, int path) { return path == PATH_CPLX ? m.N : m.Nr; }
+// bytes per scalar of the device layout (c64 and ddr are both 16)
+size_t path_esz(int path) { return path == PATH_REAL ? sizeof(double) : sizeof(c64); }
+const void *packed_of(const Staged &m, int path)
+{
+    return path == PATH_QUAD ? (const void *)m.packed_q.data()
+                             : path == PATH_REAL ? (const void *)m.packed_r.data() : (const void *)m.packed.data();
+}
+// tor_result.path: 1 real, 2 complex, 3 real with a double-double factor
+int api_path(int path) { return path == PATH_REAL ? 1 : path == PATH_QUAD ? 3 : 2; }
+const char *path_name(int path) { return path == PATH_REAL ? "real" : path == PATH_QUAD ? "quad" : "complex"; }
 
-int default_grid(const tor_ctx *ctx, bool real) { return real ? ctx->grid_r : ctx->grid; }
+int default_grid(const tor_ctx *ctx, int path) { return ctx->grid[path]; }
 
 // launch grid for a set of matrices: the tuned waves/CU of the largest one,
 // else as many one-wave workgroups as the LDS allows (at most 8 per CU)
-int launch_grid(const tor_ctx *ctx, bool real, int Nmax)
+int launch_grid(const tor_ctx *ctx, int path, int Nmax)
 {
     const int n = std::min(Nmax, MAX_N);
-    const TuneEntry &t = ctx->tune[real][n];
+    const TuneEntry &t = ctx->tune[path][n];
     if (ctx->opt.waves_per_cu <= 0 && t.valid)
-        return ctx->num_cu * std::min(t.waves, ctx->fit[real]);
-    return default_grid(ctx, real);
+        return ctx->num_cu * std::min(t.waves, ctx->fit[path]);
+    return default_grid(ctx, path);
 }
 
 // split depth: the tuned value for this size, else about four subtree roots
 // per persistent wave, never deeper than the levels above the last R modes
-int choose_k(const tor_ctx *ctx, int N, bool real)
+int choose_k(const tor_ctx *ctx, int N, int path)
 {
-    const int LA = N - path_R(real);
+    const int LA = N - path_R(path);
     if (LA <= 0)
         return 0;
     if (ctx->opt.split_k > 0)
         return std::min(ctx->opt.split_k, LA);
-    const TuneEntry &t = ctx->tune[real][std::min(N, MAX_N)];
+    const TuneEntry &t = ctx->tune[path][std::min(N, MAX_N)];
     if (t.valid)
         return std::min(t.k, LA);
     int g = 1;
-    while ((1 << g) < default_grid(ctx, real))
+    while ((1 << g) < default_grid(ctx, path))
         ++g;
     return std::min(LA, g + 2);
 }
@@ -331,15 +405,15 @@ struct LaunchLayout {
     size_t total(int grid) const { return b_probs + b_red + b_counter + b_res + (size_t)stride * grid; }
 };
 
-LaunchLayout launch_layout(bool real, int count, int nred, int Nmax)
+LaunchLayout launch_layout(int path, int count, int nred, int Nmax)
 {
-    const size_t esz = real ? sizeof(double) : sizeof(c64);
+    const size_t esz = path_esz(path);
     LaunchLayout L;
     L.b_probs = align_up(sizeof(ProblemDesc) * std::max(count, 1), 256);
     L.b_red = align_up(sizeof(ProblemDesc) * std::max(nred, 1), 256);
     L.b_counter = 256;
     L.b_res = align_up(sizeof(double) * 4 * std::max(nred, 1), 256);
-    L.stride = (long long)align_up(esz * (size_t)std::max(Gsum(Nmax - 1) - Gsum(path_R(real) - 1), 1ll), 256);
+    L.stride = (long long)align_up(esz * (size_t)std::max(Gsum(Nmax - 1) - Gsum(path_R(path) - 1), 1ll), 256);
     return L;
 }
 
@@ -350,7 +424,7 @@ LaunchLayout launch_layout(bool real, int count, int nred, int Nmax)
 // results and the per-wave tier-A stacks.  When ws_off > 0 the bytes below it
 // hold data the descriptors point to, and the caller has already sized the
 // workspace (a reallocation here would move that data).
-int run_launch(tor_ctx *ctx, bool real, std::vector<ProblemDesc> &descs, const std::vector<int> &reduce,
+int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const std::vector<int> &reduce,
                size_t ws_off, int grid, std::vector<double> *results, float *ms)
 {
     const int count = (int)descs.size();
@@ -365,7 +439,7 @@ int run_launch(tor_ctx *ctx, bool real, std::vector<ProblemDesc> &descs, const s
     for (int i : reduce)
         red.push_back(descs[i]);
     const int nred = (int)red.size();
-    const LaunchLayout Lo = launch_layout(real, count, nred, Nmax);
+    const LaunchLayout Lo = launch_layout(path, count, nred, Nmax);
     const size_t need = ws_off + Lo.total(grid);
     if (ws_off > 0 && need > ctx->ws_bytes)
         return TOR_E_NOMEM;  // the caller sizes the workspace first
@@ -396,11 +470,12 @@ int run_launch(tor_ctx *ctx, bool real, std::vector<ProblemDesc> &descs, const s
     mp.counter = dCounter;
     mp.scratch = dScr;
     mp.scratch_stride = stride;
-    const bool dd = ctx->opt.accum != TOR_ACCUM_FP64;
+    // the double-double factor always sums in double-double
+    const bool dd = ctx->opt.accum != TOR_ACCUM_FP64 || path == PATH_QUAD;
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev0, ctx->stream);
     if (e == hipSuccess && total > 0)
-        e = launch_main(real, dd, mp, grid, ctx->stream);
+        e = launch_main(path, dd, mp, grid, ctx->stream);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev1, ctx->stream);  // device_ms: the main kernel alone
     std::vector<double> hres(4 * (size_t)std::max(nred, 1));
@@ -422,16 +497,16 @@ int run_launch(tor_ctx *ctx, bool real, std::vector<ProblemDesc> &descs, const s
 
 // Synchronous path: all roots of every matrix in one launch, matrices with
 // more modes first.  results: 4 doubles per matrix (input order).
-int run_recursive(tor_ctx *ctx, bool real, std::vector<Staged *> &mats, std::vector<int> &ks,
+int run_recursive(tor_ctx *ctx, int path, std::vector<Staged *> &mats, std::vector<int> &ks,
                   std::vector<double> &results, float *ms, std::vector<double> *slots_out)
 {
-    const size_t esz = real ? sizeof(double) : sizeof(c64);
+    const size_t esz = path_esz(path);
     const int count = (int)mats.size();
     std::vector<int> order(count);
     for (int i = 0; i < count; i++)
         order[i] = i;
     std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return modes_of(*mats[a], real) > modes_of(*mats[b], real); });
+                     [&](int a, int b) { return modes_of(*mats[a], path) > modes_of(*mats[b], path); });
     // workspace: matrices, then slots, then what run_launch needs
     std::vector<size_t> c_off(count), s_off(count);
     size_t off = 0;
@@ -440,17 +515,17 @@ int run_recursive(tor_ctx *ctx, bool real, std::vector<Staged *> &mats, std::vec
     for (int s = 0; s < count; s++) {
         const Staged *m = mats[order[s]];
         c_off[s] = off;
-        off = align_up(off + esz * (size_t)NSZ(modes_of(*m, real)), 256);
-        Nmax = std::max(Nmax, modes_of(*m, real));
+        off = align_up(off + esz * (size_t)NSZ(modes_of(*m, path)), 256);
+        Nmax = std::max(Nmax, modes_of(*m, path));
     }
     for (int s = 0; s < count; s++) {
         s_off[s] = off + sizeof(double) * 4 * (size_t)nslots;
         nslots += 1ll << ks[order[s]];
     }
     off = align_up(off + sizeof(double) * 4 * (size_t)nslots, 256);
-    const int grid = launch_grid(ctx, real, Nmax);
+    const int grid = launch_grid(ctx, path, Nmax);
     // size the workspace for everything before placing data in it
-    int rc = ensure_ws(ctx, off + launch_layout(real, count, count, Nmax).total(grid));
+    int rc = ensure_ws(ctx, off + launch_layout(path, count, count, Nmax).total(grid));
     if (rc != TOR_OK)
         return rc;
     std::vector<char> hbuf(s_off.empty() ? 0 : s_off[0], 0);
@@ -458,14 +533,11 @@ int run_recursive(tor_ctx *ctx, bool real, std::vector<Staged *> &mats, std::vec
     std::vector<int> red(count);
     for (int s = 0; s < count; s++) {
         const Staged *m = mats[order[s]];
-        if (real)
-            std::memcpy(hbuf.data() + c_off[s], m->packed_r.data(), esz * m->packed_r.size());
-        else
-            std::memcpy(hbuf.data() + c_off[s], m->packed.data(), esz * m->packed.size());
+        std::memcpy(hbuf.data() + c_off[s], packed_of(*m, path), esz * (size_t)NSZ(modes_of(*m, path)));
         ProblemDesc &d = descs[s];
         d.C = ctx->ws + c_off[s];
         d.slots = (double *)(ctx->ws + s_off[s]);
-        d.N = modes_of(*m, real);
+        d.N = modes_of(*m, path);
         d.k = ks[order[s]];
         d.root_begin = 0;
         d.nroots = 1ll << d.k;
@@ -477,7 +549,7 @@ int run_recursive(tor_ctx *ctx, bool real, std::vector<Staged *> &mats, std::vec
     if (e != hipSuccess)
         return hip_status(e);
     std::vector<double> res;
-    rc = run_launch(ctx, real, descs, red, off, grid, &res, ms);
+    rc = run_launch(ctx, path, descs, red, off, grid, &res, ms);
     if (rc != TOR_OK)
         return rc;
     results.assign(4 * (size_t)count, 0.0);
@@ -493,7 +565,7 @@ int run_recursive(tor_ctx *ctx, bool real, std::vector<Staged *> &mats, std::vec
     return TOR_OK;
 }
 
-void fill_result(const Staged &st, bool real, const double *r, float ms, tor_result *out)
+void fill_result(const Staged &st, int path, const double *r, float ms, tor_result *out)
 {
     std::memset(out, 0, sizeof(*out));
     out->tor = r[0];
@@ -501,16 +573,18 @@ void fill_result(const Staged &st, bool real, const double *r, float ms, tor_res
     // a padding mode (its block of I - O is I/2) turns each term t into the
     // pair -t, +2t: Tor is unchanged and the padded sum of |t| is 3 times the
     // input's, so it is scaled back (3^pad is exact for pad < 34)
-    const int pad = (real ? st.Nr : st.N) - st.n;
+    const int pad = modes_of(st, path) - st.n;
     out->sum_abs = pad > 0 ? r[2] / std::pow(3.0, pad) : r[2];
     const double v = std::fabs(r[0] + r[1]);
     // each term carries a relative rounding error of a few units of roundoff
-    // per factorisation step; independent errors add in quadrature
+    // (FP64, or 2^-104 for the double-double factor) per factorisation step;
+    // independent errors add in quadrature
     const double R = v > 0.0 ? out->sum_abs / v : INFINITY;
-    out->err_est = kU * (double)std::max(st.n, 1) * R / std::sqrt(std::ldexp(1.0, st.n));
+    const double u = path == PATH_QUAD ? kUdd : kU;
+    out->err_est = u * (double)std::max(st.n, 1) * R / std::sqrt(std::ldexp(1.0, st.n));
     out->subsets = 1ull << st.n;
     out->status = (r[3] != 0.0 || !std::isfinite(r[0])) ? TOR_E_NUMERIC : TOR_OK;
-    out->path = real ? 1 : 2;
+    out->path = api_path(path);
     out->device_ms = ms;
 }
 
@@ -532,24 +606,24 @@ int copy_input_to_host(int n, const double *O, long ld, unsigned flags, std::vec
 // Split depths for a launch of several matrices: roots of about equal work,
 // about four per persistent wave over the whole launch (a lone matrix keeps
 // its own tuned or default depth).
-void batch_ks(const tor_ctx *ctx, bool real, const std::vector<Staged *> &grp, std::vector<int> &ks)
+void batch_ks(const tor_ctx *ctx, int path, const std::vector<Staged *> &grp, std::vector<int> &ks)
 {
     if (grp.size() == 1 || ctx->opt.split_k > 0) {
         for (size_t j = 0; j < grp.size(); j++)
-            ks[j] = choose_k(ctx, modes_of(*grp[j], real), real);
+            ks[j] = choose_k(ctx, modes_of(*grp[j], path), path);
         return;
     }
     double work = 0.0;
     int Nmax = 0;
     for (Staged *m : grp) {
-        work += std::ldexp(1.0, modes_of(*m, real));
-        Nmax = std::max(Nmax, modes_of(*m, real));
+        work += std::ldexp(1.0, modes_of(*m, path));
+        Nmax = std::max(Nmax, modes_of(*m, path));
     }
-    const double per_root = std::max(work / (4.0 * launch_grid(ctx, real, Nmax)), 1.0);
+    const double per_root = std::max(work / (4.0 * launch_grid(ctx, path, Nmax)), 1.0);
     const int lg = (int)std::floor(std::log2(per_root) + 0.5);
     for (size_t j = 0; j < grp.size(); j++) {
-        const int N = modes_of(*grp[j], real);
-        ks[j] = std::max(0, std::min(N - lg, N - path_R(real)));
+        const int N = modes_of(*grp[j], path);
+        ks[j] = std::max(0, std::min(N - lg, N - path_R(path)));
     }
 }
 
@@ -558,28 +632,28 @@ int run_staged(tor_ctx *ctx, std::vector<Staged *> &mats, const std::vector<int>
                tor_result *out, std::vector<double> *slots_out, int *k_out)
 {
     int first_err = TOR_OK;
-    for (int pass = 0; pass < 2; pass++) {
-        const bool real = pass == 0;
+    const int order[NPATH] = {PATH_REAL, PATH_CPLX, PATH_QUAD};
+    for (int path : order) {
         std::vector<Staged *> grp;
         std::vector<int> gidx, ks;
         for (size_t j = 0; j < mats.size(); j++)
-            if (mats[j]->real == real) {
+            if (mats[j]->path == path) {
                 grp.push_back(mats[j]);
                 gidx.push_back(idx[j]);
-                const int N = modes_of(*mats[j], real);
-                ks.push_back(std::min(std::max(fixed_k, 0), std::max(N - path_R(real), 0)));
+                const int N = modes_of(*mats[j], path);
+                ks.push_back(std::min(std::max(fixed_k, 0), std::max(N - path_R(path), 0)));
             }
         if (grp.empty())
             continue;
         if (fixed_k < 0)
-            batch_ks(ctx, real, grp, ks);
+            batch_ks(ctx, path, grp, ks);
         std::vector<double> res;
         float ms = 0.f;
-        int rc = run_recursive(ctx, real, grp, ks, res, &ms, slots_out);
+        int rc = run_recursive(ctx, path, grp, ks, res, &ms, slots_out);
         if (rc != TOR_OK)
             return rc;
         for (size_t j = 0; j < grp.size(); j++) {
-            fill_result(*grp[j], real, &res[4 * j], ms, &out[gidx[j]]);
+            fill_result(*grp[j], path, &res[4 * j], ms, &out[gidx[j]]);
             if (out[gidx[j]].status != TOR_OK && first_err == TOR_OK)
                 first_err = out[gidx[j]].status;
         }
@@ -684,31 +758,31 @@ void pool_release(tor_ctx *ctx, size_t off, size_t len)
 // one launch's budget, so that no single root outlasts the launch it is in.
 int serve_k(const tor_ctx *ctx, const Request &r)
 {
-    const int LA = std::max(r.N - path_R(r.real), 0);
-    const double per_root = std::max((double)ctx->chunk_subsets / (4.0 * launch_grid(ctx, r.real, r.N)), 1.0);
+    const int LA = std::max(r.N - path_R(r.path), 0);
+    const double per_root = std::max((double)ctx->chunk_subsets / (4.0 * launch_grid(ctx, r.path, r.N)), 1.0);
     const int lg = (int)std::floor(std::log2(per_root));
-    const int k = std::max(choose_k(ctx, r.N, r.real), r.N - lg);
+    const int k = std::max(choose_k(ctx, r.N, r.path), r.N - lg);
     return std::max(0, std::min(k, std::min(LA, 20)));
 }
 
 size_t request_bytes(const Request &r)
 {
-    const size_t esz = r.real ? sizeof(double) : sizeof(c64);
+    const size_t esz = path_esz(r.path);
     return align_up(esz * (size_t)NSZ(r.N), 256) + align_up(sizeof(double) * 4 * (size_t)r.nroots, 256);
 }
 
 // One scheduling round for one path: pick root ranges for a launch, run it,
 // retire the finished requests.  Called with ctx->mu held.
-int serve_round(tor_ctx *ctx, bool real, std::vector<Request *> &active, std::vector<Request *> &finished)
+int serve_round(tor_ctx *ctx, int path, std::vector<Request *> &active, std::vector<Request *> &finished)
 {
     std::vector<Request *> cand;
     for (Request *r : active)
-        if (r->real == real && r->next_root < r->nroots)
+        if (r->path == path && r->next_root < r->nroots)
             cand.push_back(r);
     if (cand.empty())
         return TOR_OK;
-    // the oldest request always gets a quarter of the budget; the rest goes
-    // to the requests with the least remaining work
+    // the oldest request always gets its share of the budget (oldest_share);
+    // the rest goes to the requests with the least remaining work
     Request *oldest = *std::min_element(cand.begin(), cand.end(),
                                         [](Request *a, Request *b) { return a->ticket < b->ticket; });
     std::stable_sort(cand.begin(), cand.end(), [](Request *a, Request *b) {
@@ -754,7 +828,7 @@ int serve_round(tor_ctx *ctx, bool real, std::vector<Request *> &active, std::ve
     }
     std::vector<double> res;
     float ms = 0.f;
-    int rc = run_launch(ctx, real, descs, red, 0, launch_grid(ctx, real, Nmax), &res, &ms);
+    int rc = run_launch(ctx, path, descs, red, 0, launch_grid(ctx, path, Nmax), &res, &ms);
     for (Request *r : used)
         r->device_ms += ms / (float)used.size();
     if (rc != TOR_OK) {
@@ -769,7 +843,7 @@ int serve_round(tor_ctx *ctx, bool real, std::vector<Request *> &active, std::ve
     }
     for (size_t j = 0; j < red.size(); j++) {
         Request *r = used[red[j]];
-        fill_result(r->st, real, &res[4 * j], r->device_ms, &r->res);
+        fill_result(r->st, path, &res[4 * j], r->device_ms, &r->res);
         finished.push_back(r);
     }
     return TOR_OK;
@@ -807,8 +881,7 @@ void serve_loop(tor_ctx *ctx)
                 r->pool_off = off;
                 r->pool_len = len;
                 r->dC = ctx->pool + off;
-                r->dSlots = (double *)(ctx->pool + off + align_up((r->real ? sizeof(double) : sizeof(c64)) *
-                                                                       (size_t)NSZ(r->N), 256));
+                r->dSlots = (double *)(ctx->pool + off + align_up(path_esz(r->path) * (size_t)NSZ(r->N), 256));
                 ctx->pending.pop_front();
                 admit.push_back(r);
                 ++ctx->admitted;
@@ -819,8 +892,8 @@ void serve_loop(tor_ctx *ctx)
             std::lock_guard<std::mutex> g(ctx->mu);
             hipError_t e = hipSetDevice(ctx->device);
             for (Request *r : admit) {
-                const void *src = r->real ? (const void *)r->st.packed_r.data() : (const void *)r->st.packed.data();
-                const size_t bytes = (r->real ? sizeof(double) : sizeof(c64)) * (size_t)NSZ(r->N);
+                const void *src = packed_of(r->st, r->path);
+                const size_t bytes = path_esz(r->path) * (size_t)NSZ(r->N);
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(r->dC, src, bytes, hipMemcpyHostToDevice, ctx->stream);
                 active.push_back(r);
@@ -833,8 +906,8 @@ void serve_loop(tor_ctx *ctx)
                     finished.push_back(r);
                 }
             } else {
-                serve_round(ctx, true, active, finished);
-                serve_round(ctx, false, active, finished);
+                for (int path : {PATH_REAL, PATH_CPLX, PATH_QUAD})
+                    serve_round(ctx, path, active, finished);
             }
         }
         if (finished.empty() && admit.empty() && active.empty())
@@ -854,7 +927,7 @@ void serve_loop(tor_ctx *ctx)
 
 // ---- autotuning ------------------------------------------------------------
 
-int tune_one(tor_ctx *ctx, bool real, int n, TuneEntry &best)
+int tune_one(tor_ctx *ctx, int path, int n, TuneEntry &best)
 {
     // timing does not depend on the values: I - O = I/2 has the Gaussian-state
     // structure (real path) and is well inside the positive-definite cone
@@ -862,17 +935,19 @@ int tune_one(tor_ctx *ctx, bool real, int n, TuneEntry &best)
     for (int i = 0; i < 2 * n; i++)
         O[2 * ((size_t)i * 2 * n + i)] = 0.5;
     Staged st;
-    int rc = stage_matrix(n, O.data(), 2 * n, real ? 0u : (unsigned)TOR_FORCE_COMPLEX, CPLX_R, st);
+    const unsigned fl = path == PATH_CPLX ? (unsigned)TOR_FORCE_COMPLEX : path == PATH_QUAD ? (unsigned)TOR_FACTOR_DD : 0u;
+    int rc = stage_matrix(n, O.data(), 2 * n, fl, CPLX_R, st);
     if (rc != TOR_OK)
         return rc;
-    if (st.real != real)
+    if (st.path != path)
         return TOR_E_INVAL;
-    const int N = modes_of(st, real);
-    const int LA = std::max(N - path_R(real), 0);
+    const int N = modes_of(st, path);
+    const int LA = std::max(N - path_R(path), 0);
     best = TuneEntry{};
-    const int wave_opts[4] = {2, 4, 6, 8};
-    for (int w : wave_opts) {
-        if (w > ctx->fit[real])
+    const int wave_opts[5] = {2, 4, 6, 8, ctx->fit[path]};
+    for (int wi = 0; wi < 5; wi++) {
+        const int w = wave_opts[wi];
+        if (w > ctx->fit[path] || (wi == 4 && (w == 2 || w == 4 || w == 6 || w == 8)))
             continue;
         const int grid = ctx->num_cu * w;
         int g = 1;
@@ -885,12 +960,12 @@ int tune_one(tor_ctx *ctx, bool real, int n, TuneEntry &best)
                 std::vector<Staged *> mats{&st};
                 std::vector<int> ks{k};
                 // run with this grid: temporarily pin the table entry
-                TuneEntry save = ctx->tune[real][std::min(N, MAX_N)];
-                ctx->tune[real][std::min(N, MAX_N)] = TuneEntry{true, k, w, 0.f};
+                TuneEntry save = ctx->tune[path][std::min(N, MAX_N)];
+                ctx->tune[path][std::min(N, MAX_N)] = TuneEntry{true, k, w, 0.f};
                 std::vector<double> res;
                 float ms = 0.f;
-                rc = run_recursive(ctx, real, mats, ks, res, &ms, nullptr);
-                ctx->tune[real][std::min(N, MAX_N)] = save;
+                rc = run_recursive(ctx, path, mats, ks, res, &ms, nullptr);
+                ctx->tune[path][std::min(N, MAX_N)] = save;
                 if (rc != TOR_OK)
                     return rc;
                 if (rep > 0)
@@ -938,10 +1013,10 @@ size_t tor_workspace_size(int max_n, int split_k, int max_inflight)
 {
     if (max_n < 0 || max_n > MAX_N)
         return 0;
-    // bounds over both paths: the smaller R has more roots and a deeper
-    // tier-A stack; complex scalars; at most MAX_FIT waves on each of 256 CUs
-    const int Rmin = std::min(REAL_R, CPLX_R);
-    const int N = std::max(max_n, std::max(REAL_R, CPLX_R));
+    // bounds over all paths: the smaller R has more roots and a deeper
+    // tier-A stack; 16-byte scalars; at most MAX_FIT waves on each of 256 CUs
+    const int Rmin = std::min(std::min(REAL_R, CPLX_R), QUAD_R);
+    const int N = std::max(max_n, std::max(std::max(REAL_R, CPLX_R), QUAD_R));
     const int k = split_k > 0 ? split_k : 14;
     const int cnt = std::max(max_inflight, 1);
     const long long items = (1ll << std::min(k, std::max(N - Rmin, 0))) * cnt;
@@ -963,7 +1038,8 @@ int tor_create(tor_ctx **out, const tor_options *opt)
     if (o.max_n <= 0)
         o.max_n = 40;
     if (o.max_n > MAX_N || o.split_k < 0 || o.split_k > 40 || o.waves_per_cu < 0 || o.waves_per_cu > 16 ||
-        (o.accum != TOR_ACCUM_DD && o.accum != TOR_ACCUM_FP64))
+        (o.accum != TOR_ACCUM_DD && o.accum != TOR_ACCUM_FP64) ||
+        ((o.flags & TOR_FACTOR_DD) && (o.flags & TOR_FORCE_COMPLEX)))
         return TOR_E_INVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0 || o.device < 0 || o.device >= ndev)
@@ -986,18 +1062,16 @@ int tor_create(tor_ctx **out, const tor_options *opt)
     ctx->arch = prop.gcnArchName;
     // persistent grid: as many one-wave workgroups per CU as the kernel's
     // registers and LDS allow
-    for (int real = 0; real < 2; real++) {
-        int fit = main_occupancy(real != 0);
+    for (int path = 0; path < NPATH; path++) {
+        int fit = main_occupancy(path);
         if (fit <= 0) {
             delete ctx;
             return TOR_E_DEVICE;
         }
         fit = std::min(fit, MAX_FIT);
-        ctx->fit[real] = fit;
+        ctx->fit[path] = fit;
         const int w = o.waves_per_cu > 0 ? std::min(o.waves_per_cu, fit) : fit;
-        (real ? ctx->grid_r : ctx->grid) = ctx->num_cu * w;
-        if (!real)
-            ctx->waves_per_cu = w;
+        ctx->grid[path] = ctx->num_cu * w;
     }
     if (o.stream) {
         ctx->stream = (hipStream_t)o.stream;
@@ -1126,7 +1200,8 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long 
         return rc;
     const int chunk = 16;
     const size_t bC = align_up(sizeof(c64) * st.packed.size(), 256);
-    const size_t bParts = align_up(sizeof(double) * 4 * ctx->grid, 256);
+    const int pgrid = ctx->grid[PATH_CPLX];
+    const size_t bParts = align_up(sizeof(double) * 4 * pgrid, 256);
     rc = ensure_ws(ctx, bC + 256 + bParts + 256);
     if (rc != TOR_OK)
         return rc;
@@ -1150,11 +1225,11 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long 
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev0, ctx->stream);
     if (e == hipSuccess)
-        e = launch_plain(pp, ctx->grid, ctx->stream);
+        e = launch_plain(pp, pgrid, ctx->stream);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev1, ctx->stream);
     if (e == hipSuccess)
-        e = launch_plain_reduce(dParts, ctx->grid, dRes, ctx->stream);
+        e = launch_plain_reduce(dParts, pgrid, dRes, ctx->stream);
     double h[4] = {0, 0, 0, 0};
     if (e == hipSuccess)
         e = hipMemcpyAsync(h, dRes, sizeof(h), hipMemcpyDeviceToHost, ctx->stream);
@@ -1211,9 +1286,9 @@ int tor_submit(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long
         delete r;
         return rc;
     }
-    r->real = r->st.real;
-    r->N = modes_of(r->st, r->real);
-    r->k = std::min(std::max(r->N - path_R(r->real), 0), 20);  // largest split admission may choose
+    r->path = r->st.path;
+    r->N = modes_of(r->st, r->path);
+    r->k = std::min(std::max(r->N - path_R(r->path), 0), 20);  // largest split admission may choose
     r->nroots = 1ll << r->k;
     if (request_bytes(*r) > ctx->pool_bytes) {
         delete r;
@@ -1278,19 +1353,20 @@ int tor_serve_config(tor_ctx *ctx, long long chunk_subsets, double oldest_share,
 
 int tor_autotune(tor_ctx *ctx, int n_min, int n_max, unsigned paths)
 {
-    if (!ctx || n_min < 1 || n_max > ctx->opt.max_n || n_min > n_max || (paths & ~3u) || !paths)
+    if (!ctx || n_min < 1 || n_max > ctx->opt.max_n || n_min > n_max || (paths & ~7u) || !paths)
         return TOR_E_INVAL;
     std::lock_guard<std::mutex> g(ctx->mu);
-    for (int real = 1; real >= 0; real--) {
-        if (!(paths & (real ? TOR_TUNE_REAL : TOR_TUNE_COMPLEX)))
+    const unsigned bit[NPATH] = {TOR_TUNE_COMPLEX, TOR_TUNE_REAL, TOR_TUNE_QUAD};
+    for (int path : {PATH_REAL, PATH_CPLX, PATH_QUAD}) {
+        if (!(paths & bit[path]))
             continue;
         for (int n = n_min; n <= n_max; n++) {
             TuneEntry best;
-            int rc = tune_one(ctx, real != 0, n, best);
+            int rc = tune_one(ctx, path, n, best);
             if (rc != TOR_OK)
                 return rc;
-            const int N = std::max(n, path_R(real != 0));
-            ctx->tune[real][std::min(N, MAX_N)] = best;
+            const int N = std::max(n, path_R(path));
+            ctx->tune[path][std::min(N, MAX_N)] = best;
         }
     }
     return TOR_OK;
@@ -1306,13 +1382,13 @@ int tor_tune_save(tor_ctx *ctx, const char *path)
         return TOR_E_INVAL;
     std::fprintf(f, "{\"arch\": \"%s\", \"cus\": %d, \"entries\": [", ctx->arch.c_str(), ctx->num_cu);
     bool first = true;
-    for (int real = 0; real < 2; real++)
+    for (int path = 0; path < NPATH; path++)
         for (int N = 0; N <= MAX_N; N++) {
-            const TuneEntry &t = ctx->tune[real][N];
+            const TuneEntry &t = ctx->tune[path][N];
             if (!t.valid)
                 continue;
             std::fprintf(f, "%s\n  {\"path\": \"%s\", \"modes\": %d, \"k\": %d, \"waves_per_cu\": %d, \"ms\": %.4f}",
-                         first ? "" : ",", real ? "real" : "complex", N, t.k, t.waves, (double)t.ms);
+                         first ? "" : ",", path_name(path), N, t.k, t.waves, (double)t.ms);
             first = false;
         }
     std::fprintf(f, "\n]}\n");
@@ -1354,8 +1430,13 @@ int tor_tune_load(tor_ctx *ctx, const char *path)
             return TOR_E_INVAL;
         if (N < 0 || N > MAX_N || k < 0 || w < 1 || w > 16)
             return TOR_E_INVAL;
-        const int real = std::strcmp(kind, "real") == 0 ? 1 : 0;
-        ctx->tune[real][N] = TuneEntry{true, k, w, (float)ms};
+        int path = -1;
+        for (int q = 0; q < NPATH; q++)
+            if (std::strcmp(kind, path_name(q)) == 0)
+                path = q;
+        if (path < 0)
+            return TOR_E_INVAL;
+        ctx->tune[path][N] = TuneEntry{true, k, w, (float)ms};
         ++p;
     }
     return TOR_OK;

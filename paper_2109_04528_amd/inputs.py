@@ -131,5 +131,22 @@ def batch_mix(count: int = 512, n_lo: int = 12, n_hi: int = 26, seed: int = 4,
     return [int(v) for v in ns], mats
 
 
+def structured_O(O: np.ndarray) -> np.ndarray:
+    """O with the exact Gaussian-state block form: I - O = [[P, Q], [conj Q,
+    conj P]] with Q symmetric, taking P and Q as the averages of the two
+    copies each block has in a numerically computed state (they agree to
+    rounding).  Inputs built this way describe the same matrix on every
+    evaluation path."""
+    n = O.shape[0] // 2
+    C = np.eye(2 * n) - O
+    C = np.tril(C) + np.tril(C, -1).conj().T
+    P, Q, P2, Q2 = C[:n, :n], C[:n, n:], C[n:, n:], C[n:, :n]
+    Pa = 0.5 * (P + P2.conj())
+    Qa = 0.25 * (Q + Q.T + (Q2 + Q2.T).conj())
+    Pa[np.diag_indices(n)] = Pa.diagonal().real
+    Ca = np.block([[Pa, Qa], [Qa.conj(), Pa.conj()]])
+    return np.eye(2 * n) - Ca
+
+
 def sha256(a: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()

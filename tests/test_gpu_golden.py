@@ -55,7 +55,7 @@ def test_against_golden(ctx, name):
     assert abs(r.sum_abs - g["sum_abs"]) <= 1e-9 * g["sum_abs"]
     assert err <= bound
     if g["n"] <= 10:
-        assert rel <= 1e-10  # the benchmark spec's target, reachable at this R
+        assert rel <= 1e-10  # the target precision, reachable at this R
 
 
 def test_dd_beats_plain_fp64_sum():

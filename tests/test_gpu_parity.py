@@ -7,7 +7,7 @@ elimination step, amplified by the conditioning kappa of I - O.  The sums
 themselves are exact on both sides (every term is a double of magnitude >= 1
 and both sides add them without rounding), so the difference is bounded by
     |Tor_gpu - Tor_oracle| <= c * N * kappa * u * sum_Z |t_Z|.
-Where that bound is below the benchmark spec's target of 1e-10 relative, the test
+Where that bound is below the target precision of 1e-10 relative, the test
 asks for 1e-10.
 """
 import math

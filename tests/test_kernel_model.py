@@ -42,3 +42,13 @@ def test_real_form_model_matches_oracle(n, k):
     assert abs(v - q.value) <= 64 * 1.1e-16 * max(n, 11) * q.sum_abs, (v, q.value)
     pad = max(n, 11) - n
     assert abs(sabs - 3.0 ** pad * q.sum_abs) <= 1e-12 * sabs
+
+
+# the double-double factor: real form, T = 3, B = 6, L = 2
+@pytest.mark.parametrize("n,k", [(6, 0), (9, 0), (11, 1), (12, 2)])
+def test_quad_config_model_matches_oracle(n, k):
+    O = gen.random_O(n, 70 + n, 0.3, 1.2, 0.9)
+    v, cnt, _ = model_tor(O, 3, 6, k, real=True, L=2)
+    q = orc.tor(O, mode=orc.QUAD)
+    assert cnt == 1 << max(n, 9)
+    assert abs(v - q.value) <= 64 * 1.1e-16 * max(n, 9) * q.sum_abs, (v, q.value)
