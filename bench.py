@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--serve", type=int, default=4096, help="requests in the mixed-n stream (0: skip)")
     ap.add_argument("--batch", type=int, default=512, help="matrices in the batched launch (0: skip)")
     ap.add_argument("--n34", type=int, default=1, help="also time one n=34 Torontonian")
+    ap.add_argument("--click", type=int, default=1024,
+                    help="click-pattern probabilities of one 32-mode state (0: skip)")
     ap.add_argument("--quad", type=int, default=1,
                     help="also time the same n=30 Torontonian with the double-double factor")
     ap.add_argument("--profile-traffic", action="store_true",
@@ -260,6 +262,24 @@ def main():
                 "factor": "double-double (TOR_FACTOR_DD), real quadrature form"}
         print("bench: double-double factor done", file=sys.stderr, flush=True)
 
+    click = None
+    if args.click > 0:
+        # patterns S of a 32-mode state (r ~ U[.5, 1], eta = .7, seed 9), |S| ~ U{4..28}
+        Oc = inputs.random_O(32, 9, 0.5, 1.0, 0.7)
+        crng = np.random.default_rng(10)
+        pats = [crng.choice(32, size=int(crng.integers(4, 29)), replace=False).tolist()
+                for _ in range(args.click)]
+        ctx.click_probs(Oc, pats[:8])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        probs, cres = ctx.click_probs(Oc, pats)
+        t1 = time.perf_counter()
+        subsets = sum(1 << len(p) for p in pats)
+        click = {"modes": 32, "patterns": args.click, "clicks_range": [4, 28], "seconds": t1 - t0,
+                 "patterns_per_s": args.click / (t1 - t0), "subset_dets_per_s": subsets / (t1 - t0),
+                 "kernel_ms": max(r.device_ms for r in cres), "min_prob": float(probs.min())}
+        print("bench: click probabilities done", file=sys.stderr, flush=True)
+
     serve = None
     if args.serve > 0:
         reqs = serve_requests(args.serve, 5)
@@ -307,6 +327,7 @@ def main():
         "batch": batch,
         "n34": big,
         "quad": quad,
+        "click": click,
         "serving": serve,
         "cpu_baseline": cpu,
     }

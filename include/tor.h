@@ -142,6 +142,23 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld,
 int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max,
                       int *k_out, double *partials, tor_result *out);
 
+/* Click probabilities of threshold detection for one Gaussian state (Sec. 1,
+ * Eq. 1-2): for each pattern S (bit q of patterns[i] set = mode q clicked,
+ * modes 0..M-1, M <= 64)
+ *     p(S) = Tor(O_S) sqrt(det(I - O)),
+ * O_S the principal submatrix of the M-mode O on rows and columns
+ * {s, s + M : s in S}.  O is 2M x 2M complex128 row-major (interleaved re,
+ * im), leading dimension ld >= 2M, device memory with TOR_INPUT_DEVICE; only
+ * its lower triangle is read.  All patterns run as one batch (tor_eval_batch)
+ * with the context's options (TOR_FACTOR_DD included); sqrt(det(I - O)) is
+ * one long-double Cholesky on the host.  probs receives count values (NaN
+ * where a pattern failed); results (may be NULL) the per-pattern Tor(O_S)
+ * records.  Errors: TOR_E_INVAL (bad sizes, a pattern with bits >= M or more
+ * than max_n clicks), TOR_E_NOT_PD (I - O not positive definite), or the
+ * first per-pattern error. */
+int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count,
+                    const unsigned long long *patterns, double *probs, tor_result *results);
+
 /* Serving: enqueue one Torontonian request.  O is copied before return.
  * *ticket identifies it for tor_poll.  TOR_E_BUSY when admission is refused. */
 int tor_submit(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long *ticket);

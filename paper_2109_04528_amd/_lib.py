@@ -40,7 +40,7 @@ EXPORTS = [
     "tor_default_options", "tor_create", "tor_destroy", "tor_workspace_size", "tor_eval",
     "tor_eval_batch", "tor_eval_plain", "tor_eval_partials", "tor_submit", "tor_poll",
     "tor_drain", "tor_debug_math", "tor_strerror", "tor_autotune", "tor_tune_save", "tor_tune_load",
-    "tor_serve_config",
+    "tor_serve_config", "tor_click_probs",
 ]
 
 TOR_TUNE_REAL = 0x1
@@ -118,6 +118,9 @@ def load(path: str = LIB_PATH):
     lib.tor_debug_math.restype = ctypes.c_int
     lib.tor_serve_config.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_double, ctypes.c_int]
     lib.tor_serve_config.restype = ctypes.c_int
+    lib.tor_click_probs.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long, ctypes.c_int,
+                                    P(ctypes.c_ulonglong), P(ctypes.c_double), ctypes.c_void_p]
+    lib.tor_click_probs.restype = ctypes.c_int
     lib.tor_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint]
     lib.tor_autotune.restype = ctypes.c_int
     lib.tor_tune_save.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
@@ -268,6 +271,32 @@ class Context:
         if rc != TOR_OK:
             raise TorError(rc, "tor_eval_partials")
         return k.value, parts[: 3 * (1 << k.value)].reshape(-1, 3), TorResult.from_c(r)
+
+    def click_probs(self, O, patterns, check: bool = True):
+        """Click probabilities p(S) = Tor(O_S) sqrt(det(I - O)) of an M-mode
+        state for each pattern: an int bitmask (bit q = mode q clicked) or an
+        iterable of clicked modes.  Returns (probs, [TorResult of O_S])."""
+        A = _host_c128(O)
+        M = A.shape[0] // 2
+        masks = []
+        for p in patterns:
+            if isinstance(p, (int, np.integer)):
+                masks.append(int(p))
+            else:
+                m = 0
+                for q in p:
+                    m |= 1 << int(q)
+                masks.append(m)
+        cnt = len(masks)
+        pat = (ctypes.c_ulonglong * max(cnt, 1))(*masks)
+        probs = np.zeros(max(cnt, 1), dtype=np.float64)
+        res = (tor_result * max(cnt, 1))()
+        rc = self._lib.tor_click_probs(self._h, M, A.ctypes.data if M else None, max(2 * M, 1), cnt, pat,
+                                       probs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       ctypes.cast(res, ctypes.c_void_p))
+        if check and rc != TOR_OK:
+            raise TorError(rc, "tor_click_probs")
+        return probs[:cnt], [TorResult.from_c(res[i]) for i in range(cnt)]
 
     def submit(self, O) -> int:
         A = _host_c128(O)

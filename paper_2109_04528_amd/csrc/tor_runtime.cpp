@@ -146,6 +146,49 @@ bool hpd_check(int n2, const std::vector<double> &C)
     return true;
 }
 
+// sqrt(det(I - O)) of the Hermitian completion of the lower triangle of
+// I - O (2M x 2M, O row-major with leading dimension ld, complex
+// interleaved), by a Cholesky factorisation in long double: the product of
+// the diagonal of L.  Returns a negative value when I - O is not positive
+// definite.
+double host_sqrt_det(int M, const double *O, long ld)
+{
+    const int m2 = 2 * M;
+    std::vector<long double> Cr((size_t)m2 * m2), Ci((size_t)m2 * m2);
+    for (int a = 0; a < m2; a++)
+        for (int b = 0; b <= a; b++) {
+            const long double orr = O[2 * ((size_t)a * ld + b)], oi = O[2 * ((size_t)a * ld + b) + 1];
+            const long double cr = (a == b ? 1.0L : 0.0L) - orr, ci = (a == b) ? 0.0L : -oi;
+            Cr[(size_t)a * m2 + b] = cr;
+            Ci[(size_t)a * m2 + b] = ci;
+        }
+    long double prod = 1.0L;
+    for (int j = 0; j < m2; j++) {
+        long double d = Cr[(size_t)j * m2 + j];
+        for (int k = 0; k < j; k++)
+            d -= Cr[(size_t)j * m2 + k] * Cr[(size_t)j * m2 + k] + Ci[(size_t)j * m2 + k] * Ci[(size_t)j * m2 + k];
+        if (!(d > 0.0L))
+            return -1.0;
+        const long double ljj = std::sqrt(d);
+        prod *= ljj;
+        Cr[(size_t)j * m2 + j] = ljj;
+        Ci[(size_t)j * m2 + j] = 0.0L;
+        for (int i = j + 1; i < m2; i++) {
+            long double sr = Cr[(size_t)i * m2 + j], si = Ci[(size_t)i * m2 + j];
+            for (int k = 0; k < j; k++) {
+                // L[i][k] conj(L[j][k])
+                const long double ar = Cr[(size_t)i * m2 + k], ai = Ci[(size_t)i * m2 + k];
+                const long double br = Cr[(size_t)j * m2 + k], bi = Ci[(size_t)j * m2 + k];
+                sr -= ar * br + ai * bi;
+                si -= ai * br - ar * bi;
+            }
+            Cr[(size_t)i * m2 + j] = sr / ljj;
+            Ci[(size_t)i * m2 + j] = si / ljj;
+        }
+    }
+    return (double)prod;
+}
+
 // Gaussian-state structure.  The sampling matrix of a Gaussian state in
 // block order has the form [[P, Q], [conj Q, conj P]] (Sec. 1: A = I - Sigma^-1
 // from the Husimi covariance), and so has C = I - O.  For such C the unitary
@@ -664,7 +707,7 @@ int run_staged(tor_ctx *ctx, std::vector<Staged *> &mats, const std::vector<int>
 }
 
 int eval_many(tor_ctx *ctx, int count, const int *n, const double *const *O, const long *ld, tor_result *out,
-              int fixed_k, std::vector<double> *slots_out, int *k_out)
+              int fixed_k, std::vector<double> *slots_out, int *k_out, unsigned flags)
 {
     std::vector<Staged> st(count);
     std::vector<int> rcs(count, TOR_OK);
@@ -676,12 +719,12 @@ int eval_many(tor_ctx *ctx, int count, const int *n, const double *const *O, con
         }
         std::vector<double> tmp;
         const double *host;
-        int rc = copy_input_to_host(n[i], O ? O[i] : nullptr, ld ? ld[i] : 0, ctx->opt.flags, tmp, host);
+        int rc = copy_input_to_host(n[i], O ? O[i] : nullptr, ld ? ld[i] : 0, flags, tmp, host);
         if (rc == TOR_OK)
-            rc = stage_matrix(n[i], host, ld ? ld[i] : 0, ctx->opt.flags, CPLX_R, st[i]);
+            rc = stage_matrix(n[i], host, ld ? ld[i] : 0, flags, CPLX_R, st[i]);
         rcs[i] = rc;
     };
-    const int nthr = (count >= 8 && !(ctx->opt.flags & TOR_INPUT_DEVICE))
+    const int nthr = (count >= 8 && !(flags & TOR_INPUT_DEVICE))
                          ? (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()))
                          : 1;
     if (nthr <= 1) {
@@ -1140,7 +1183,7 @@ int tor_eval(tor_ctx *ctx, int n, const double *O, long ld, tor_result *out)
     long lds[1] = {ld};
     int ns[1] = {n};
     tor_result r{};
-    int rc = eval_many(ctx, 1, ns, Op, lds, &r, -1, nullptr, nullptr);
+    int rc = eval_many(ctx, 1, ns, Op, lds, &r, -1, nullptr, nullptr, ctx->opt.flags);
     if (rc == TOR_E_INVAL && r.status == TOR_E_INVAL)
         return rc;
     *out = r;
@@ -1154,7 +1197,7 @@ int tor_eval_batch(tor_ctx *ctx, int count, const int *n, const double *const *O
     if (count == 0)
         return TOR_OK;
     std::lock_guard<std::mutex> g(ctx->mu);
-    return eval_many(ctx, count, n, O, ld, out, -1, nullptr, nullptr);
+    return eval_many(ctx, count, n, O, ld, out, -1, nullptr, nullptr, ctx->opt.flags);
 }
 
 int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max, int *k_out, double *partials,
@@ -1169,7 +1212,7 @@ int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max, 
     std::vector<double> slots;
     int k = 0;
     tor_result r{};
-    int rc = eval_many(ctx, 1, ns, Op, lds, &r, k_max, &slots, &k);
+    int rc = eval_many(ctx, 1, ns, Op, lds, &r, k_max, &slots, &k, ctx->opt.flags);
     if (rc != TOR_OK && rc != TOR_E_NUMERIC)
         return rc;
     *out = r;
@@ -1184,6 +1227,66 @@ int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max, 
     }
     return rc;
 }
+int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count, const unsigned long long *patterns,
+                    double *probs, tor_result *results)
+{
+    if (!ctx || M < 0 || M > 64 || count < 0 || (count > 0 && (!patterns || !probs)) || (M > 0 && !O) ||
+        (M > 0 && ld < 2L * M))
+        return TOR_E_INVAL;
+    for (int i = 0; i < count; i++) {
+        if (M < 64 && (patterns[i] >> M) != 0)
+            return TOR_E_INVAL;
+        if (__builtin_popcountll(patterns[i]) > ctx->opt.max_n)
+            return TOR_E_INVAL;
+    }
+    std::lock_guard<std::mutex> g(ctx->mu);
+    std::vector<double> tmp;
+    const double *host = O;
+    int rc = copy_input_to_host(M, O, ld, ctx->opt.flags, tmp, host);
+    if (rc != TOR_OK)
+        return rc;
+    const double sq = M > 0 ? host_sqrt_det(M, host, ld) : 1.0;
+    if (!(sq > 0.0))
+        return TOR_E_NOT_PD;
+    // the principal submatrix of every pattern: rows and columns {s, s + M}
+    std::vector<std::vector<double>> subs(count);
+    std::vector<int> ns(count);
+    std::vector<const double *> ptrs(count);
+    std::vector<long> lds(count);
+    for (int i = 0; i < count; i++) {
+        std::vector<int> sel;
+        for (int q = 0; q < M; q++)
+            if ((patterns[i] >> q) & 1ull)
+                sel.push_back(q);
+        const int k = (int)sel.size();
+        std::vector<int> idx(2 * k);
+        for (int a = 0; a < k; a++) {
+            idx[a] = sel[a];
+            idx[k + a] = sel[a] + M;
+        }
+        subs[i].assign((size_t)2 * k * 2 * k * 2, 0.0);
+        for (int a = 0; a < 2 * k; a++)
+            for (int b = 0; b < 2 * k; b++) {
+                subs[i][2 * ((size_t)a * 2 * k + b)] = host[2 * ((size_t)idx[a] * ld + idx[b])];
+                subs[i][2 * ((size_t)a * 2 * k + b) + 1] = host[2 * ((size_t)idx[a] * ld + idx[b]) + 1];
+            }
+        ns[i] = k;
+        ptrs[i] = subs[i].data();
+        lds[i] = std::max(2 * k, 1);
+    }
+    std::vector<tor_result> res(std::max(count, 1));
+    // the submatrices are host copies even when O was on the device
+    rc = count > 0 ? eval_many(ctx, count, ns.data(), ptrs.data(), lds.data(), res.data(), -1, nullptr, nullptr,
+                               ctx->opt.flags & ~(unsigned)TOR_INPUT_DEVICE)
+                   : TOR_OK;
+    for (int i = 0; i < count; i++) {
+        probs[i] = res[i].status == TOR_OK ? (res[i].tor + res[i].tor_lo) * sq : NAN;
+        if (results)
+            results[i] = res[i];
+    }
+    return rc;
+}
+
 int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long mask_begin,
                    unsigned long long mask_end, tor_result *out)
 {
