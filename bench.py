@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--serve", type=int, default=4096, help="requests in the mixed-n stream (0: skip)")
     ap.add_argument("--batch", type=int, default=512, help="matrices in the batched launch (0: skip)")
     ap.add_argument("--n34", type=int, default=1, help="also time one n=34 Torontonian")
+    ap.add_argument("--compare", type=int, default=1,
+                    help="the n=24 pair workload by the append form, the paper's removal order and plain")
     ap.add_argument("--click", type=int, default=1024,
                     help="click-pattern probabilities of one 32-mode state (0: skip)")
     ap.add_argument("--quad", type=int, default=1,
@@ -247,6 +249,28 @@ def main():
                "tor": r34.value, "cancellation_R": r34.cancellation}
         print("bench: n=34 done", file=sys.stderr, flush=True)
 
+    compare = None
+    if args.compare:
+        from paper_2109_04528_amd import TOR_FORCE_COMPLEX
+        from paper_2109_04528_amd.flops import removal_flops
+        O24 = inputs.random_O(24, 0, 0.5, 1.0, 0.7)
+        ctx.eval(O24)
+        ra = ctx.eval(O24)
+        ctx.eval_removal(O24)
+        rr = ctx.eval_removal(O24)
+        rp = ctx.eval_plain(O24)
+        with Context(device=0, stream=stream, workspace=ws, flags=TOR_FORCE_COMPLEX) as cc:
+            cc.eval(O24)
+            rc_ = cc.eval(O24)
+        compare = {"workload": "n=24, r~U[0.5,1], eta=0.7, seed 0 (2^24 subsets), kernel times",
+                   "append_real_ms": ra.device_ms, "append_complex_ms": rc_.device_ms,
+                   "removal_order_ms": rr.device_ms, "plain_ms": rp.device_ms,
+                   "removal_tflops": removal_flops(24) / (rr.device_ms * 1e-3) / 1e12,
+                   "removal_over_plain": rp.device_ms / rr.device_ms,
+                   "append_complex_over_removal": rr.device_ms / rc_.device_ms,
+                   "append_real_over_removal": rr.device_ms / ra.device_ms}
+        print("bench: method comparison done", file=sys.stderr, flush=True)
+
     quad = None
     if args.quad:
         from paper_2109_04528_amd import TOR_FACTOR_DD
@@ -328,6 +352,7 @@ def main():
         "n34": big,
         "quad": quad,
         "click": click,
+        "compare_n24": compare,
         "serving": serve,
         "cpu_baseline": cpu,
     }

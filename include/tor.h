@@ -134,6 +134,16 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld,
                    unsigned long long mask_begin, unsigned long long mask_end,
                    tor_result *out);
 
+/* The paper's own reuse order, as a second comparison (Sec. 2, Algorithm 2):
+ * modes are removed in increasing order; a child keeps its parent's Cholesky
+ * rows and columns of the kept modes below the removed mode (L11, L21) and
+ * factorises the trailing block afresh, L22 = chol(A22 - L21 L21^H).  The
+ * full Torontonian of the complex matrix (general Hermitian input; n <=
+ * min(34, max_n)), one wavefront per depth-first walk below each of 2^k
+ * roots (the removal decisions on the first k modes).  Same argument
+ * conventions and errors as tor_eval; out->device_ms is the kernel time. */
+int tor_eval_removal(tor_ctx *ctx, int n, const double *O, long ld, tor_result *out);
+
 /* Verification aid: the recursive path's per-subtree partial sums.  Root r is
  * the include/exclude decision on modes 0..k-1 given by the bits of r (bit i =
  * mode i included); partial r sums the subsets Z with Z & (2^k - 1) == r.

@@ -40,7 +40,7 @@ EXPORTS = [
     "tor_default_options", "tor_create", "tor_destroy", "tor_workspace_size", "tor_eval",
     "tor_eval_batch", "tor_eval_plain", "tor_eval_partials", "tor_submit", "tor_poll",
     "tor_drain", "tor_debug_math", "tor_strerror", "tor_autotune", "tor_tune_save", "tor_tune_load",
-    "tor_serve_config", "tor_click_probs",
+    "tor_serve_config", "tor_click_probs", "tor_eval_removal",
 ]
 
 TOR_TUNE_REAL = 0x1
@@ -121,6 +121,8 @@ def load(path: str = LIB_PATH):
     lib.tor_click_probs.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long, ctypes.c_int,
                                     P(ctypes.c_ulonglong), P(ctypes.c_double), ctypes.c_void_p]
     lib.tor_click_probs.restype = ctypes.c_int
+    lib.tor_eval_removal.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long, P(tor_result)]
+    lib.tor_eval_removal.restype = ctypes.c_int
     lib.tor_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint]
     lib.tor_autotune.restype = ctypes.c_int
     lib.tor_tune_save.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
@@ -257,6 +259,16 @@ class Context:
         rc = self._lib.tor_eval_plain(self._h, n, A.ctypes.data, 2 * n, mask_begin, mask_end, ctypes.byref(r))
         if check and rc != TOR_OK:
             raise TorError(rc, "tor_eval_plain")
+        return TorResult.from_c(r)
+
+    def eval_removal(self, O, check: bool = True) -> TorResult:
+        """The paper's removal-order algorithm (comparison kernel)."""
+        A = _host_c128(O)
+        n = A.shape[0] // 2
+        r = tor_result()
+        rc = self._lib.tor_eval_removal(self._h, n, A.ctypes.data if n else None, max(2 * n, 1), ctypes.byref(r))
+        if check and rc != TOR_OK:
+            raise TorError(rc, "tor_eval_removal")
         return TorResult.from_c(r)
 
     def eval_partials(self, O, k_max: int):

@@ -72,6 +72,19 @@ struct PlainParams {
     int chunk;                    // subsets per queue pop
 };
 
+// The removal-order comparison kernel (Algorithm 2): one wave per depth-first
+// walk over the removals of the modes k..n-1 below a root (the removal
+// decisions on modes 0..k-1).
+struct RemovalParams {
+    const void *C;                // I - O (c64), interleaved rows, lower triangle packed by pidx
+    int n, k;
+    unsigned long long *counter;  // root queue head
+    char *scratch;                // per wave: levels 0..n-k of NSZ(n) c64 each
+    long long scratch_stride;     // bytes per wave
+    double *partials;             // 4 doubles per wave
+};
+constexpr int REMOVAL_MAX_N = 34;
+
 // sum_{i=1..s} 2i(i+1): scalars of all node sizes 1..s
 __host__ __device__ constexpr long long Gsum(long long s) { return 2 * s * (s + 1) * (s + 2) / 3; }
 // scalar offset of tier-A stack slot l (covers modes [l, N)), slots 1..N-R
@@ -106,6 +119,7 @@ hipError_t launch_main(int path, bool dd, const MainParams &p, int grid, hipStre
 hipError_t launch_reduce(const ProblemDesc *probs, int nprob, double *results, bool dd, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, int count, hipStream_t s);
 hipError_t launch_plain(const PlainParams &p, int grid, hipStream_t s);
+hipError_t launch_removal(const RemovalParams &p, int grid, hipStream_t s);
 hipError_t launch_plain_reduce(const double *partials, int nwaves, double *result, hipStream_t s);
 hipError_t launch_math_probe(const double *x, double *out, int count, hipStream_t s);
 // resident one-wave workgroups of the main kernel per CU (0 on error)

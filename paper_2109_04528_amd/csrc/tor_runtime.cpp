@@ -1297,8 +1297,8 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long 
     const double *host;
     int rc = copy_input_to_host(n, O, ld, ctx->opt.flags, tmp, host);
     Staged st;
-    if (rc == TOR_OK)
-        rc = stage_matrix(n, host, ld, ctx->opt.flags, 0, st);
+    if (rc == TOR_OK)  // the comparison kernels run on the complex matrix
+        rc = stage_matrix(n, host, ld, (ctx->opt.flags & ~(unsigned)TOR_FACTOR_DD) | TOR_FORCE_COMPLEX, 0, st);
     if (rc != TOR_OK)
         return rc;
     const int chunk = 16;
@@ -1343,8 +1343,86 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long 
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
     st.N = n;
-    fill_result(st, false, h, ms, out);
+    fill_result(st, PATH_CPLX, h, ms, out);
     out->subsets = mask_end - mask_begin;
+    return out->status;
+}
+
+int tor_eval_removal(tor_ctx *ctx, int n, const double *O, long ld, tor_result *out)
+{
+    if (!ctx || !out || n < 0 || n > REMOVAL_MAX_N || n > ctx->opt.max_n)
+        return TOR_E_INVAL;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    std::vector<double> tmp;
+    const double *host;
+    int rc = copy_input_to_host(n, O, ld, ctx->opt.flags, tmp, host);
+    Staged st;
+    if (rc == TOR_OK)  // validation and the positive-definiteness check
+        rc = stage_matrix(n, host, ld, (ctx->opt.flags & ~(unsigned)TOR_FACTOR_DD) | TOR_FORCE_COMPLEX, 0, st);
+    if (rc != TOR_OK)
+        return rc;
+    // I - O in the interleaved order a_0, a_0^dag, a_1, ... (the ordering of
+    // Sec. 2), the Hermitian completion of its lower triangle, packed by rows
+    std::vector<c64> Ci((size_t)E(std::max(n, 1)), c64{0.0, 0.0});
+    for (int x = 0; x < 2 * n; x++)
+        for (int y = 0; y <= x; y++) {
+            const int bx = (x >> 1) + (x & 1) * n, by = (y >> 1) + (y & 1) * n;
+            const bool lower = bx >= by;
+            const int i = lower ? bx : by, j = lower ? by : bx;
+            const double orr = host[2 * ((size_t)i * ld + j)], oi = host[2 * ((size_t)i * ld + j) + 1];
+            c64 v{(i == j ? 1.0 : 0.0) - orr, i == j ? 0.0 : -oi};
+            if (!lower)
+                v.y = -v.y;
+            Ci[(size_t)pidx(x, y)] = v;
+        }
+    const int grid = ctx->num_cu * MAX_FIT;
+    int k = 0;
+    while (k < n && (1ll << k) < 4ll * grid)
+        ++k;
+    const size_t bC = align_up(sizeof(c64) * Ci.size(), 256);
+    const size_t bParts = align_up(sizeof(double) * 4 * grid, 256);
+    const long long stride = (long long)align_up(sizeof(c64) * (size_t)(n - k + 1) * (size_t)NSZ(n), 256);
+    const size_t bScr = (size_t)stride * grid;
+    rc = ensure_ws(ctx, bC + 256 + bParts + 256 + bScr);
+    if (rc != TOR_OK)
+        return rc;
+    char *dC = ctx->ws;
+    unsigned long long *dCounter = (unsigned long long *)(dC + bC);
+    double *dParts = (double *)((char *)dCounter + 256);
+    double *dRes = (double *)((char *)dParts + bParts);
+    char *dScr = (char *)dRes + 256;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dC, Ci.data(), sizeof(c64) * Ci.size(), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_zero(dCounter, 1, ctx->stream);
+    RemovalParams rp{};
+    rp.C = dC;
+    rp.n = n;
+    rp.k = k;
+    rp.counter = dCounter;
+    rp.scratch = dScr;
+    rp.scratch_stride = stride;
+    rp.partials = dParts;
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev0, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_removal(rp, grid, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev1, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_plain_reduce(dParts, grid, dRes, ctx->stream);
+    double h[4] = {0, 0, 0, 0};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h, dRes, sizeof(h), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    st.N = n;
+    fill_result(st, PATH_CPLX, h, ms, out);
     return out->status;
 }
 

@@ -48,3 +48,31 @@ def plain_flops_per_subset(n: int) -> float:
         c = sum(elim_cost(s) + 1 for s in range(1, d + 1)) + 2
         tot += comb(n, d) * c
     return tot / float(1 << n)
+
+
+def chol_flops(s2: int) -> int:
+    """Scalar complex Cholesky of an s2 x s2 Hermitian matrix (Algorithm 1):
+    per column a square root and a reciprocal (2), the column scaled by a
+    real (2 per entry), and the trailing lower triangle updated by one
+    complex multiply-subtract per entry (8)."""
+    tot = 0
+    for j in range(s2):
+        w = s2 - 1 - j
+        tot += 2 + 2 * w + 8 * (w * (w + 1) // 2)
+    return tot
+
+
+def removal_flops(n: int) -> int:
+    """Algorithmic FLOPs of the removal order (Sec. 2, Algorithm 2) for one
+    Torontonian of n modes: one factorisation of the full matrix, then for
+    every further subset -- remove mode i with c kept modes below it, of
+    which there are C(i, c) -- the trailing block C22 - L21 L21^H (its lower
+    triangle, 2m(2m+1)/2 entries of 2c complex multiply-subtracts, m = n-1-i)
+    and its factorisation; every subset's term costs 2 more."""
+    from math import comb
+    tot = chol_flops(2 * n) + 2 * (1 << n)
+    for i in range(n):
+        m = n - 1 - i
+        for c in range(i + 1):
+            tot += comb(i, c) * (8 * 2 * c * (2 * m * (2 * m + 1) // 2) + chol_flops(2 * m))
+    return tot
