@@ -246,7 +246,8 @@ def main():
         O34 = inputs.random_O(34, 0, 0.5, 1.0, 0.7)
         r34 = ctx.eval(O34)
         big = {"n": 34, "kernel_ms": r34.device_ms, "subset_dets_per_s": (1 << 34) / (r34.device_ms * 1e-3),
-               "tor": r34.value, "cancellation_R": r34.cancellation}
+               "tor": r34.value, "cancellation_R": r34.cancellation, "err_est": r34.err_est,
+               "note": "FP64 factor: at this R only TOR_FACTOR_DD gives a meaningful value"}
         print("bench: n=34 done", file=sys.stderr, flush=True)
 
     compare = None
