@@ -583,15 +583,33 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
 }
 
 // ---------------------------------------------------------------------------
-// per-matrix sum of the root slots, in index order
+// per-matrix sum of the root slots: thread t takes roots t, t + RED_THREADS,
+// ... in index order, then the threads are combined by a fixed tree (within
+// each wave, then across the waves), so the result does not depend on timing.
+constexpr int RED_THREADS = 1024;
+
 template <bool DD>
-__global__ void __launch_bounds__(64) tor_reduce(const ProblemDesc *probs, double *results)
+__device__ inline void red_step(double &h, double &l, double &ab, double &bad, int off)
 {
-    const int q = blockIdx.x, lane = threadIdx.x;
+    const double oh = __shfl_xor(h, off), ol = __shfl_xor(l, off);
+    if (DD)
+        dd_add2(h, l, oh, ol);
+    else
+        h += oh;
+    ab += __shfl_xor(ab, off);
+    bad = fmax(bad, __shfl_xor(bad, off));
+}
+
+template <bool DD>
+__global__ void __launch_bounds__(RED_THREADS) tor_reduce(const ProblemDesc *probs, double *results)
+{
+    constexpr int NW = RED_THREADS / 64;
+    __shared__ double part[4][NW];
+    const int q = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
     const ProblemDesc P = probs[q];
     const long long nroots = 1ll << P.k;
     double h = 0.0, l = 0.0, ab = 0.0, bad = 0.0;
-    for (long long r = lane; r < nroots; r += 64) {
+    for (long long r = t; r < nroots; r += RED_THREADS) {
         const double *s = P.slots + 4 * r;
         if (DD)
             dd_add2(h, l, s[0], s[1]);
@@ -601,20 +619,30 @@ __global__ void __launch_bounds__(64) tor_reduce(const ProblemDesc *probs, doubl
         bad = fmax(bad, s[3]);
     }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        double oh = __shfl_xor(h, off), ol = __shfl_xor(l, off);
-        if (DD)
-            dd_add2(h, l, oh, ol);
-        else
-            h += oh;
-        ab += __shfl_xor(ab, off);
-        bad = fmax(bad, __shfl_xor(bad, off));
-    }
+    for (int off = 32; off >= 1; off >>= 1)
+        red_step<DD>(h, l, ab, bad, off);
     if (lane == 0) {
-        results[4 * q + 0] = h;
-        results[4 * q + 1] = l;
-        results[4 * q + 2] = ab;
-        results[4 * q + 3] = bad;
+        part[0][w] = h;
+        part[1][w] = l;
+        part[2][w] = ab;
+        part[3][w] = bad;
+    }
+    __syncthreads();
+    if (w == 0) {
+        const bool in = lane < NW;
+        h = in ? part[0][lane] : 0.0;
+        l = in ? part[1][lane] : 0.0;
+        ab = in ? part[2][lane] : 0.0;
+        bad = in ? part[3][lane] : 0.0;
+#pragma unroll
+        for (int off = NW / 2; off >= 1; off >>= 1)
+            red_step<DD>(h, l, ab, bad, off);
+        if (lane == 0) {
+            results[4 * q + 0] = h;
+            results[4 * q + 1] = l;
+            results[4 * q + 2] = ab;
+            results[4 * q + 3] = bad;
+        }
     }
 }
 
@@ -1016,9 +1044,9 @@ int main_occupancy(int path)
 hipError_t launch_reduce(const ProblemDesc *probs, int nprob, double *results, bool dd, hipStream_t s)
 {
     if (dd)
-        hipLaunchKernelGGL((tor_reduce<true>), dim3(nprob), dim3(64), 0, s, probs, results);
+        hipLaunchKernelGGL((tor_reduce<true>), dim3(nprob), dim3(RED_THREADS), 0, s, probs, results);
     else
-        hipLaunchKernelGGL((tor_reduce<false>), dim3(nprob), dim3(64), 0, s, probs, results);
+        hipLaunchKernelGGL((tor_reduce<false>), dim3(nprob), dim3(RED_THREADS), 0, s, probs, results);
     return hipGetLastError();
 }
 

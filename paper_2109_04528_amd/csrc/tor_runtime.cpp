@@ -119,27 +119,30 @@ int hip_status(hipError_t e) { return e == hipSuccess ? TOR_OK : (e == hipErrorO
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Cholesky of the Hermitian 2n x 2n matrix C (full storage), FP64.
+// Cholesky of the Hermitian 2n x 2n matrix C (full storage), FP64, as
+// C = U^H U with U upper triangular, row by row: row j is scaled by the
+// reciprocal square root of its pivot, then subtracted from every later row
+// (contiguous updates, no serial dot products).  True when every pivot is
+// positive.
 bool hpd_check(int n2, const std::vector<double> &C)
 {
-    std::vector<double> L((size_t)n2 * n2 * 2, 0.0);
-    for (int i = 0; i < n2; i++) {
-        for (int j = 0; j <= i; j++) {
-            double sr = C[2 * ((size_t)i * n2 + j)], si = C[2 * ((size_t)i * n2 + j) + 1];
-            for (int k = 0; k < j; k++) {
-                double ar = L[2 * ((size_t)i * n2 + k)], ai = L[2 * ((size_t)i * n2 + k) + 1];
-                double br = L[2 * ((size_t)j * n2 + k)], bi = L[2 * ((size_t)j * n2 + k) + 1];
-                sr -= ar * br + ai * bi;
-                si -= ai * br - ar * bi;
-            }
-            if (i == j) {
-                if (!(sr > 0.0))
-                    return false;
-                L[2 * ((size_t)i * n2 + i)] = std::sqrt(sr);
-            } else {
-                double d = L[2 * ((size_t)j * n2 + j)];
-                L[2 * ((size_t)i * n2 + j)] = sr / d;
-                L[2 * ((size_t)i * n2 + j) + 1] = si / d;
+    std::vector<double> U(C);
+    for (int j = 0; j < n2; j++) {
+        double *uj = &U[2 * (size_t)j * n2];
+        const double d = uj[2 * j];
+        if (!(d > 0.0))
+            return false;
+        const double inv = 1.0 / std::sqrt(d);
+        for (int k = 2 * j; k < 2 * n2; k++)
+            uj[k] *= inv;
+        for (int i = j + 1; i < n2; i++) {
+            double *ui = &U[2 * (size_t)i * n2];
+            // row i -= conj(U[j][i]) * row j
+            const double fr = uj[2 * i], fi = -uj[2 * i + 1];
+            for (int k = i; k < n2; k++) {
+                const double xr = uj[2 * k], xi = uj[2 * k + 1];
+                ui[2 * k] -= fr * xr - fi * xi;
+                ui[2 * k + 1] -= fr * xi + fi * xr;
             }
         }
     }
@@ -222,23 +225,79 @@ hdd h_add(hdd a, hdd b)
 }
 hdd h_neg(hdd a) { return hdd{-a.hi, -a.lo}; }
 
-bool stage_real(int n, const std::vector<double> &C, const double *O, long ld, bool quad, Staged &st)
+// Gaussian-state structure test of C (full Hermitian storage, block order):
+// both defining relations hold to 64 units of roundoff of max |C| (cmax2 =
+// max |C|^2).  Squared magnitudes are compared, so no square root is taken.
+bool gaussian_structure(int n, const std::vector<double> &C, double cmax2)
 {
     const int n2 = 2 * n;
     auto cre = [&](int a, int b) { return C[2 * ((size_t)a * n2 + b)]; };
     auto cim = [&](int a, int b) { return C[2 * ((size_t)a * n2 + b) + 1]; };
-    double cmax = 0.0, dev = 0.0;
-    for (int a = 0; a < n2; a++)
-        for (int b = 0; b < n2; b++)
-            cmax = std::max(cmax, std::hypot(cre(a, b), cim(a, b)));
+    double dev2 = 0.0;
+    auto sq = [](double x, double y) { return x * x + y * y; };
     for (int i = 0; i < n; i++)
         for (int j = 0; j < n; j++) {
             // lower-right block = conj(upper-left); lower-left block symmetric
-            dev = std::max(dev, std::hypot(cre(i + n, j + n) - cre(i, j), cim(i + n, j + n) + cim(i, j)));
-            dev = std::max(dev, std::hypot(cre(i + n, j) - cre(j + n, i), cim(i + n, j) - cim(j + n, i)));
+            dev2 = std::max(dev2, sq(cre(i + n, j + n) - cre(i, j), cim(i + n, j + n) + cim(i, j)));
+            dev2 = std::max(dev2, sq(cre(i + n, j) - cre(j + n, i), cim(i + n, j) - cim(j + n, i)));
         }
-    if (!(dev <= 64.0 * kU * std::max(cmax, 1.0)))
-        return false;
+    const double tol = 64.0 * kU * std::max(std::sqrt(cmax2), 1.0);
+    return dev2 <= tol * tol;
+}
+
+// The real form of the symmetrised C, dense (2n x 2n, row-major, row 2 i + c
+// for component c of mode i).
+void real_form(int n, const std::vector<double> &C, std::vector<double> &R)
+{
+    const int n2 = 2 * n;
+    auto cre = [&](int a, int b) { return C[2 * ((size_t)a * n2 + b)]; };
+    auto cim = [&](int a, int b) { return C[2 * ((size_t)a * n2 + b) + 1]; };
+    R.assign((size_t)n2 * n2, 0.0);
+    for (int mi = 0; mi < n; mi++)
+        for (int mj = 0; mj < n; mj++) {
+            const double pr = 0.5 * (cre(mi, mj) + cre(mi + n, mj + n));
+            const double pi = 0.5 * (cim(mi, mj) - cim(mi + n, mj + n));
+            // Q = upper-right block, symmetrised: (Q + Q^T)/2, with Q[i][j] = C[i][j+n]
+            const double qr = 0.5 * (cre(mi, mj + n) + cre(mj, mi + n));
+            const double qi = 0.5 * (cim(mi, mj + n) + cim(mj, mi + n));
+            double *r0 = &R[(size_t)(2 * mi) * n2 + 2 * mj], *r1 = r0 + n2;
+            r0[0] = pr + qr;
+            r0[1] = qi - pi;
+            r1[0] = pi + qi;
+            r1[1] = pr - qr;
+        }
+}
+
+// Cholesky of the real symmetric m x m matrix R (row-major, full storage),
+// FP64, in a scratch copy, in the row form of hpd_check: true when every
+// pivot is positive.
+bool spd_check(int m, const std::vector<double> &R)
+{
+    std::vector<double> U(R);
+    for (int j = 0; j < m; j++) {
+        double *uj = &U[(size_t)j * m];
+        const double d = uj[j];
+        if (!(d > 0.0))
+            return false;
+        const double inv = 1.0 / std::sqrt(d);
+        for (int k = j; k < m; k++)
+            uj[k] *= inv;
+        for (int i = j + 1; i < m; i++) {
+            double *ui = &U[(size_t)i * m];
+            const double f = uj[i];
+            for (int k = i; k < m; k++)
+                ui[k] -= f * uj[k];
+        }
+    }
+    return true;
+}
+
+// Pack the real form R (dense, from real_form) for the real path, or, with
+// quad set, the same form rebuilt in double-double from O for the
+// double-double factor.
+void stage_real(int n, const std::vector<double> &R, const double *O, long ld, bool quad, Staged &st)
+{
+    const int n2 = 2 * n;
     const int N = std::max(n, quad ? QUAD_R : REAL_R);
     st.Nr = N;
     if (quad) {
@@ -275,32 +334,22 @@ bool stage_real(int n, const std::vector<double> &C, const double *O, long ld, b
                     st.packed_q[(size_t)gpos((int)sizeof(ddr), NB(N), bidx(a, b), e)] = ddr{v.hi, v.lo};
                 }
         st.path = PATH_QUAD;
-        return true;
+        return;
     }
     st.packed_r.assign((size_t)NSZ(N), 0.0);
-    // real 2x2 block of modes (mi, mj), row component ci, column component cj
-    auto rblk = [&](int mi, int mj, int ci, int cj) -> double {
-        if (mi >= n || mj >= n)
-            return (mi == mj && ci == cj) ? 0.5 : 0.0;
-        const double pr = 0.5 * (cre(mi, mj) + cre(mi + n, mj + n));
-        const double pi = 0.5 * (cim(mi, mj) - cim(mi + n, mj + n));
-        // Q = upper-right block, symmetrised: (Q + Q^T)/2, with Q[i][j] = C[i][j+n]
-        const double qr = 0.5 * (cre(mi, mj + n) + cre(mj, mi + n));
-        const double qi = 0.5 * (cim(mi, mj + n) + cim(mj, mi + n));
-        if (ci == 0 && cj == 0) return pr + qr;
-        if (ci == 0 && cj == 1) return qi - pi;
-        if (ci == 1 && cj == 0) return pi + qi;
-        return pr - qr;
+    // entry (qi, qj) of the form, interleaved order; modes >= n are padding
+    auto rel = [&](int qi, int qj) -> double {
+        if (qi >= n2 || qj >= n2)
+            return qi == qj ? 0.5 : 0.0;
+        return R[(size_t)qi * n2 + qj];
     };
     for (int a = 0; a < N; a++)
         for (int b = 0; b <= a; b++)
             for (int e = 0; e < 4; e++) {
                 const int qi = 2 * N - 1 - (2 * a + (e >> 1)), qj = 2 * N - 1 - (2 * b + (e & 1));
-                st.packed_r[(size_t)gpos((int)sizeof(double), NB(N), bidx(a, b), e)] =
-                    rblk(qi / 2, qj / 2, qi % 2, qj % 2);
+                st.packed_r[(size_t)gpos((int)sizeof(double), NB(N), bidx(a, b), e)] = rel(qi, qj);
             }
     st.path = PATH_REAL;
-    return true;
 }
 
 // Validate, check, pack one matrix.  O is host memory.
@@ -314,6 +363,7 @@ int stage_matrix(int n, const double *O, long ld, unsigned flags, int min_modes,
     const int n2 = 2 * n;
     // Hermitian completion of the lower triangle of C = I - O
     std::vector<double> C((size_t)n2 * n2 * 2);
+    double cmax2 = 0.0;  // max |C|^2
     for (int a = 0; a < n2; a++)
         for (int b = 0; b <= a; b++) {
             double orr = O[2 * ((size_t)a * ld + b)], oi = O[2 * ((size_t)a * ld + b) + 1];
@@ -321,6 +371,7 @@ int stage_matrix(int n, const double *O, long ld, unsigned flags, int min_modes,
                 return TOR_E_INVAL;
             double cr = (a == b ? 1.0 : 0.0) - orr;
             double ci = (a == b) ? 0.0 : -oi;
+            cmax2 = std::max(cmax2, cr * cr + ci * ci);
             C[2 * ((size_t)a * n2 + b)] = cr;
             C[2 * ((size_t)a * n2 + b) + 1] = ci;
             C[2 * ((size_t)b * n2 + a)] = cr;
@@ -340,12 +391,29 @@ int stage_matrix(int n, const double *O, long ld, unsigned flags, int min_modes,
         if (diff > 1e-12 * std::max(scale, 1.0))
             return TOR_E_INVAL;
     }
+    // The real path when the Gaussian-state structure holds: positive
+    // definiteness is checked on the real symmetric form the kernel factors
+    // (it has the eigenvalues of the symmetrised C), and the complex layout
+    // is not built.  The empty matrix stays on the complex path unless the
+    // double-double factor is asked for.
+    const bool dd = (flags & TOR_FACTOR_DD) != 0;
+    st.N = std::max(n, min_modes);
+    if ((dd || (n > 0 && !(flags & TOR_FORCE_COMPLEX))) && gaussian_structure(n, C, cmax2)) {
+        std::vector<double> R;
+        real_form(n, C, R);
+        if (n > 0 && !spd_check(n2, R))
+            return TOR_E_NOT_PD;
+        stage_real(n, R, O, ld, dd, st);
+        return TOR_OK;
+    }
+    // the double-double factor runs on the real form only
+    if (dd)
+        return TOR_E_INVAL;
     if (n > 0 && !hpd_check(n2, C))
         return TOR_E_NOT_PD;
     // pack: N modes, reversed interleaved rows; row q (interleaved) of mode q/2,
     // component q%2 -> block-order row (q/2) + (q%2) n; modes >= n are padding
-    const int N = std::max(n, min_modes);
-    st.N = N;
+    const int N = st.N;
     st.packed.assign((size_t)NSZ(N), c64{0.0, 0.0});
     auto elem = [&](int qi, int qj) -> c64 {
         int mi = qi / 2, ci = qi % 2, mj = qj / 2, cj = qj % 2;
@@ -364,13 +432,6 @@ int stage_matrix(int n, const double *O, long ld, unsigned flags, int min_modes,
                 st.packed[(size_t)gpos((int)sizeof(c64), NB(N), bidx(a, b), e)] = v;
             }
     st.path = PATH_CPLX;
-    if (flags & TOR_FACTOR_DD) {
-        // the double-double factor runs on the real form only
-        if (!stage_real(n, C, O, ld, true, st))
-            return TOR_E_INVAL;
-    } else if (!(flags & TOR_FORCE_COMPLEX) && n > 0) {
-        stage_real(n, C, O, ld, false, st);
-    }
     return TOR_OK;
 }
 
