@@ -22,14 +22,22 @@
  *    owns rows {i, i+n} (the problem statement of Sec. 1).
  *  * Only the lower triangle of I - O is read, as in Algorithm 1; the upper
  *    triangle is taken as its conjugate transpose.
- *  * I - O must be Hermitian positive definite.  Every principal submatrix of
- *    an HPD matrix is HPD (Cauchy interlacing), so one Cholesky of the full
- *    I - O on the host validates all 2^n subsets.  The paper takes |det| in
+ *  * Every value read must be finite (else TOR_E_INVAL).  Staging runs on the
+ *    GPU: a kernel validates the values, forms I - O, detects the
+ *    Gaussian-state block structure and packs the matrix for its kernel.
+ *  * I - O must be Hermitian positive definite.  The kernels test the pivots
+ *    of every subset they factorise; the full I - O is one of them, and every
+ *    principal submatrix of an HPD matrix is HPD (Cauchy interlacing), so a
+ *    failed pivot anywhere means I - O is not (numerically) positive
+ *    definite: the result's status is TOR_E_NOT_PD.  The paper takes |det| in
  *    Eq. 2; for HPD input det > 0 and the two agree.
  *  * n = 0 gives Tor = 1 (the empty subset only).
- *  * Unless TOR_INPUT_DEVICE is set, O is a host pointer.  The caller owns its
- *    inputs; the library copies what it needs before the call returns (for
- *    tor_submit as well).  The context owns all device state.
+ *  * Unless TOR_INPUT_DEVICE is set, O is a host pointer and is copied to the
+ *    device as it is; with TOR_INPUT_DEVICE it is device memory, read in
+ *    place by the staging kernel (the caller orders its writes to O before
+ *    the call, e.g. by synchronising).  The caller owns its inputs; the
+ *    library is done with them when the call returns (for tor_submit as
+ *    well).  The context owns all device state.
  *  * A context is internally serialised: calls on one context from several
  *    threads are safe and run one at a time.
  *  * Every function returns TOR_OK (0) or a negative TOR_E_* code; the output
@@ -48,8 +56,9 @@ extern "C" {
 #define TOR_OK 0
 #define TOR_PENDING 1          /* tor_poll: the request is still running            */
 #define TOR_E_INVAL (-1)       /* null pointer, n < 0, n > max_n, ld < 2n, NaN/Inf  */
-#define TOR_E_NOT_PD (-2)      /* I - O is not Hermitian positive definite          */
-#define TOR_E_NUMERIC (-3)     /* a pivot <= 0 or NaN inside the walk               */
+#define TOR_E_NOT_PD (-2)      /* I - O is not Hermitian positive definite (a pivot
+                                  <= 0 or NaN in some subset)                       */
+#define TOR_E_NUMERIC (-3)     /* a non-finite result with every pivot positive     */
 #define TOR_E_BUSY (-4)        /* admission refused: serving queue is full          */
 #define TOR_E_NOMEM (-5)       /* device or host allocation failed                  */
 #define TOR_E_DEVICE (-6)      /* no usable GPU, or a HIP runtime error             */
@@ -129,7 +138,9 @@ int tor_eval_batch(tor_ctx *ctx, int count, const int *n, const double *const *O
 
 /* The comparison baseline (not the method): every subset gets a fresh Cholesky
  * (Algorithm 1) on the GPU, one wavefront per subset.  Sums the subsets whose
- * bitmask lies in [mask_begin, mask_end) (pass 0 and 2^n for all of them). */
+ * bitmask lies in [mask_begin, mask_end) (pass 0 and 2^n for all of them).
+ * The positive-definiteness test covers the subsets of that range (the full
+ * I - O only when its mask 2^n - 1 is in it). */
 int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld,
                    unsigned long long mask_begin, unsigned long long mask_end,
                    tor_result *out);
@@ -160,8 +171,8 @@ int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max,
  * {s, s + M : s in S}.  O is 2M x 2M complex128 row-major (interleaved re,
  * im), leading dimension ld >= 2M, device memory with TOR_INPUT_DEVICE; only
  * its lower triangle is read.  All patterns run as one batch (tor_eval_batch)
- * with the context's options (TOR_FACTOR_DD included); sqrt(det(I - O)) is
- * one long-double Cholesky on the host.  probs receives count values (NaN
+ * with the context's options (TOR_FACTOR_DD included), each O_S staged on the
+ * device from O; sqrt(det(I - O)) is one FP64 Cholesky on the device.  probs receives count values (NaN
  * where a pattern failed); results (may be NULL) the per-pattern Tor(O_S)
  * records.  Errors: TOR_E_INVAL (bad sizes, a pattern with bits >= M or more
  * than max_n clicks), TOR_E_NOT_PD (I - O not positive definite), or the
@@ -169,7 +180,9 @@ int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max,
 int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count,
                     const unsigned long long *patterns, double *probs, tor_result *results);
 
-/* Serving: enqueue one Torontonian request.  O is copied before return.
+/* Serving: enqueue one Torontonian request.  O is copied before return and
+ * staged on the device when the request is admitted; a staging error
+ * (TOR_E_INVAL) or TOR_E_NOT_PD is reported in the polled result's status.
  * *ticket identifies it for tor_poll.  TOR_E_BUSY when admission is refused. */
 int tor_submit(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long *ticket);
 

@@ -78,6 +78,23 @@ class tor_result(ctypes.Structure):
 _lib = None
 
 
+def _torch_runtime_first():
+    """torch ships its own HIP runtime under the soname libtor links against
+    (libamdhip64.so.7), and whichever copy is loaded first serves the whole
+    process.  torch initialised after libtor was loaded reports no GPU, while
+    the other order works; so when torch is importable and sees a GPU it is
+    initialised before libtor is loaded."""
+    try:
+        import torch
+    except ImportError:
+        return
+    try:
+        if torch.cuda.device_count() > 0:
+            torch.cuda.init()
+    except RuntimeError:
+        pass
+
+
 def load(path: str = LIB_PATH):
     """Load libtor.so and declare the signatures (raises if it is missing)."""
     global _lib
@@ -86,6 +103,7 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"libtor.so not built at {path}; run __graft_entry__.build() or "
                           "python -m paper_2109_04528_amd.build")
+    _torch_runtime_first()
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER
     lib.tor_default_options.argtypes = [P(tor_options)]
@@ -184,8 +202,25 @@ def _host_c128(O) -> np.ndarray:
     return A
 
 
+def _dev_c128(O):
+    """A device matrix for a context with TOR_INPUT_DEVICE: a torch complex128
+    CUDA tensor, 2n x 2n, unit column stride.  Returns (pointer, n, ld); the
+    caller keeps O alive across the call."""
+    if not (hasattr(O, "device") and getattr(O.device, "type", None) == "cuda"):
+        raise ValueError("a context with TOR_INPUT_DEVICE takes torch CUDA tensors")
+    import torch
+    if O.dtype != torch.complex128 or O.dim() != 2 or O.shape[0] != O.shape[1] or O.shape[0] % 2:
+        raise ValueError("O must be a 2n x 2n complex128 tensor")
+    if O.shape[0] and O.stride(1) != 1:
+        raise ValueError("O needs unit column stride")
+    return O.data_ptr(), O.shape[0] // 2, max(O.stride(0), 1)
+
+
 class Context:
-    """One libtor context (device state, stream, workspace)."""
+    """One libtor context (device state, stream, workspace).  With
+    flags & TOR_INPUT_DEVICE every matrix argument is a torch complex128 CUDA
+    tensor read in place by the staging kernel; otherwise numpy arrays (or
+    tensors, copied to the host)."""
 
     def __init__(self, device: int = 0, stream=None, max_n: int = 40, split_k: int = 0,
                  waves_per_cu: int = 0, accum: str = "dd", flags: int = 0, workspace=None):
@@ -210,6 +245,16 @@ class Context:
             raise TorError(rc, "tor_create")
         self._h = h
         self._lib = lib
+        self._device_in = bool(flags & TOR_INPUT_DEVICE)
+
+    def _in(self, O):
+        """(pointer, n, ld, keep-alive) of a matrix argument."""
+        if self._device_in:
+            ptr, n, ld = _dev_c128(O)
+            return (ptr if n else None), n, ld, O
+        A = _host_c128(O)
+        n = A.shape[0] // 2
+        return (A.ctypes.data if n else None), n, max(2 * n, 1), A
 
     def close(self):
         if getattr(self, "_h", None):
@@ -229,20 +274,19 @@ class Context:
             pass
 
     def eval(self, O, check: bool = True) -> TorResult:
-        A = _host_c128(O)
-        n = A.shape[0] // 2
+        ptr, n, ld, _keep = self._in(O)
         r = tor_result()
-        rc = self._lib.tor_eval(self._h, n, A.ctypes.data if n else None, max(2 * n, 1), ctypes.byref(r))
+        rc = self._lib.tor_eval(self._h, n, ptr, ld, ctypes.byref(r))
         if check and rc != TOR_OK:
             raise TorError(rc, "tor_eval")
         return TorResult.from_c(r)
 
     def eval_batch(self, Os: Sequence, check: bool = True) -> List[TorResult]:
-        arrs = [_host_c128(O) for O in Os]
-        cnt = len(arrs)
-        ns = (ctypes.c_int * cnt)(*[a.shape[0] // 2 for a in arrs])
-        ptrs = (ctypes.c_void_p * cnt)(*[a.ctypes.data for a in arrs])
-        lds = (ctypes.c_long * cnt)(*[max(a.shape[0], 1) for a in arrs])
+        args = [self._in(O) for O in Os]
+        cnt = len(args)
+        ns = (ctypes.c_int * cnt)(*[a[1] for a in args])
+        ptrs = (ctypes.c_void_p * cnt)(*[a[0] for a in args])
+        lds = (ctypes.c_long * cnt)(*[a[2] for a in args])
         res = (tor_result * cnt)()
         rc = self._lib.tor_eval_batch(self._h, cnt, ns, ptrs, lds, res)
         if check and rc != TOR_OK:
@@ -251,33 +295,30 @@ class Context:
 
     def eval_plain(self, O, mask_begin: int = 0, mask_end: Optional[int] = None,
                    check: bool = True) -> TorResult:
-        A = _host_c128(O)
-        n = A.shape[0] // 2
+        ptr, n, ld, _keep = self._in(O)
         if mask_end is None:
             mask_end = 1 << n
         r = tor_result()
-        rc = self._lib.tor_eval_plain(self._h, n, A.ctypes.data, 2 * n, mask_begin, mask_end, ctypes.byref(r))
+        rc = self._lib.tor_eval_plain(self._h, n, ptr, ld, mask_begin, mask_end, ctypes.byref(r))
         if check and rc != TOR_OK:
             raise TorError(rc, "tor_eval_plain")
         return TorResult.from_c(r)
 
     def eval_removal(self, O, check: bool = True) -> TorResult:
         """The paper's removal-order algorithm (comparison kernel)."""
-        A = _host_c128(O)
-        n = A.shape[0] // 2
+        ptr, n, ld, _keep = self._in(O)
         r = tor_result()
-        rc = self._lib.tor_eval_removal(self._h, n, A.ctypes.data if n else None, max(2 * n, 1), ctypes.byref(r))
+        rc = self._lib.tor_eval_removal(self._h, n, ptr, ld, ctypes.byref(r))
         if check and rc != TOR_OK:
             raise TorError(rc, "tor_eval_removal")
         return TorResult.from_c(r)
 
     def eval_partials(self, O, k_max: int):
-        A = _host_c128(O)
-        n = A.shape[0] // 2
+        ptr, n, ld, _keep = self._in(O)
         parts = np.zeros(3 * (1 << k_max), dtype=np.float64)
         k = ctypes.c_int()
         r = tor_result()
-        rc = self._lib.tor_eval_partials(self._h, n, A.ctypes.data if n else None, max(2 * n, 1), k_max,
+        rc = self._lib.tor_eval_partials(self._h, n, ptr, ld, k_max,
                                          ctypes.byref(k), parts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                          ctypes.byref(r))
         if rc != TOR_OK:
@@ -288,8 +329,7 @@ class Context:
         """Click probabilities p(S) = Tor(O_S) sqrt(det(I - O)) of an M-mode
         state for each pattern: an int bitmask (bit q = mode q clicked) or an
         iterable of clicked modes.  Returns (probs, [TorResult of O_S])."""
-        A = _host_c128(O)
-        M = A.shape[0] // 2
+        ptr, M, ld, _keep = self._in(O)
         masks = []
         for p in patterns:
             if isinstance(p, (int, np.integer)):
@@ -303,7 +343,7 @@ class Context:
         pat = (ctypes.c_ulonglong * max(cnt, 1))(*masks)
         probs = np.zeros(max(cnt, 1), dtype=np.float64)
         res = (tor_result * max(cnt, 1))()
-        rc = self._lib.tor_click_probs(self._h, M, A.ctypes.data if M else None, max(2 * M, 1), cnt, pat,
+        rc = self._lib.tor_click_probs(self._h, M, ptr, ld, cnt, pat,
                                        probs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                        ctypes.cast(res, ctypes.c_void_p))
         if check and rc != TOR_OK:
@@ -311,10 +351,9 @@ class Context:
         return probs[:cnt], [TorResult.from_c(res[i]) for i in range(cnt)]
 
     def submit(self, O) -> int:
-        A = _host_c128(O)
-        n = A.shape[0] // 2
+        ptr, n, ld, _keep = self._in(O)
         t = ctypes.c_ulonglong()
-        rc = self._lib.tor_submit(self._h, n, A.ctypes.data if n else None, max(2 * n, 1), ctypes.byref(t))
+        rc = self._lib.tor_submit(self._h, n, ptr, ld, ctypes.byref(t))
         if rc != TOR_OK:
             raise TorError(rc, "tor_submit")
         return t.value

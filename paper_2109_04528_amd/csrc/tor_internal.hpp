@@ -85,6 +85,35 @@ struct RemovalParams {
 };
 constexpr int REMOVAL_MAX_N = 34;
 
+// Device staging (tor_stage.hip): one workgroup per matrix turns the
+// caller's O into the layout a kernel reads.
+enum : unsigned {
+    STAGE_CHECK_HERM = 1u,   // the upper triangle must mirror the lower one
+    STAGE_FORCE_CPLX = 2u,   // never the real quadrature form
+    STAGE_DD = 4u,           // the real form in double-double (structure required)
+    STAGE_INTERLEAVED = 8u,  // the removal-order layout (complex, interleaved rows)
+};
+constexpr int STAGE_BAD_INPUT = 1;  // a value is not finite, or a required test failed
+
+struct StageInfo {
+    int status;   // 0, or STAGE_BAD_INPUT
+    int path;     // PATH_* of the staged form
+    int N;        // its modes (after padding)
+    int unused;
+    double cmax;  // max |I - O|
+};
+
+struct StageDesc {
+    const double *O;   // complex128 row-major (re, im), leading dimension ld
+    long ld;           // in complex elements
+    const int *sel;    // null, or the n modes (increasing) of an M-mode O
+    int n, M;
+    unsigned flags;    // STAGE_*
+    int min_cplx;      // minimum modes of the complex form
+    void *out;         // the staged form (bytes: staged_bytes)
+    StageInfo *info;
+};
+
 // sum_{i=1..s} 2i(i+1): scalars of all node sizes 1..s
 __host__ __device__ constexpr long long Gsum(long long s) { return 2 * s * (s + 1) * (s + 2) / 3; }
 // scalar offset of tier-A stack slot l (covers modes [l, N)), slots 1..N-R
@@ -114,7 +143,7 @@ enum { PATH_CPLX = 0, PATH_REAL = 1, PATH_QUAD = 2, NPATH = 3 };
 constexpr int MAX_N = 48;
 constexpr int MAX_FIT = 8;  // persistent one-wave workgroups per CU, at most
 
-// host-side launchers (defined in tor_kernels.hip)
+// host-side launchers (defined in tor_kernels.hip unless noted)
 hipError_t launch_main(int path, bool dd, const MainParams &p, int grid, hipStream_t s);
 hipError_t launch_reduce(const ProblemDesc *probs, int nprob, double *results, bool dd, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, int count, hipStream_t s);
@@ -122,6 +151,9 @@ hipError_t launch_plain(const PlainParams &p, int grid, hipStream_t s);
 hipError_t launch_removal(const RemovalParams &p, int grid, hipStream_t s);
 hipError_t launch_plain_reduce(const double *partials, int nwaves, double *result, hipStream_t s);
 hipError_t launch_math_probe(const double *x, double *out, int count, hipStream_t s);
+// defined in tor_stage.hip
+hipError_t launch_stage(const StageDesc *descs, int count, hipStream_t s);
+hipError_t launch_sqrt_det(const double *O, long ld, int M, c64 *scratch, double *out, hipStream_t s);
 // resident one-wave workgroups of the main kernel per CU (0 on error)
 int main_occupancy(int path);
 

@@ -1,17 +1,17 @@
 // tor_runtime.cpp -- host runtime and C ABI of libtor (see include/tor.h).
 //
-// Host side of one evaluation:
-//   1. validate the arguments and every value of the lower triangle;
-//   2. form I - O from its lower triangle (Hermitian completion) and run one
-//      FP64 Cholesky of the full matrix: positive definiteness of I - O
-//      implies it for every principal submatrix (Cauchy interlacing), so
-//      this single check covers all 2^n subsets;
-//   3. pack the matrix in the device layout (tor_internal.hpp), padded to the
-//      kernel's minimum size with decoupled modes whose block of I - O is
-//      I/2 -- such a mode multiplies the Torontonian by 1/sqrt(1/4) - 1 = 1;
-//      Gaussian-state matrices are also packed in their real form;
-//   4. one persistent launch over all (matrix, subtree root) items, then the
+// One evaluation:
+//   1. the host checks the arguments (sizes, pointers, leading dimensions);
+//   2. a host input is copied to the device as it is (a device input is read
+//      in place); the staging kernel (tor_stage.hip) validates every value,
+//      forms I - O from its lower triangle, tests the Gaussian-state
+//      structure and packs the matrix in the layout of its path, straight
+//      into the workspace; the host reads back only the path and status;
+//   3. one persistent launch over all (matrix, subtree root) items, then the
 //      fixed-order per-matrix reduction of the root slots, one copy back.
+//      Positive definiteness is the kernel's own test: it checks the pivots
+//      of every subset, I - O itself among them, and a failed pivot is
+//      reported as TOR_E_NOT_PD.
 //
 // Serving (tor_submit / tor_poll) keeps each admitted request's matrix and
 // root slots in a device pool and runs them in chunked launches: every launch
@@ -46,19 +46,22 @@ namespace {
 constexpr double kU = 1.1102230246251565e-16;  // FP64 unit roundoff
 constexpr double kUdd = 4.930380657631324e-32; // 2^-104, double-double roundoff
 
-struct Staged {
-    int n = 0;                    // modes of the input
-    int N = 0;                    // modes after padding (complex path)
-    std::vector<c64> packed;      // complex device layout
-    int path = PATH_CPLX;         // PATH_REAL when the Gaussian-state structure is found
-    int Nr = 0;                   // modes after padding (real and double-double paths)
-    std::vector<double> packed_r; // real symmetric form, same layout
-    std::vector<ddr> packed_q;    // the same form in double-double
+// A matrix staged on the device: its form lives in the workspace at ws_off,
+// or at pool (serving).
+struct Mat {
+    int n = 0;             // modes of the input
+    int N = 0;             // modes of the staged form (padded to the path's minimum)
+    int path = PATH_CPLX;  // PATH_REAL when the Gaussian-state structure is found
+    int status = TOR_OK;
+    size_t ws_off = 0;
+    char *pool = nullptr;
 };
 
 struct Request {
     unsigned long long ticket = 0;
-    Staged st;
+    int n = 0;
+    std::vector<double> raw;  // the input, 2n x 2n complex128, compact rows
+    Mat st;
     tor_result res{};
     bool done = false;
     // device state once admitted
@@ -93,6 +96,9 @@ struct tor_ctx {
     int grid[NPATH] = {0, 0, 0}; // persistent grid per path
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::mutex mu;        // serialises device work on this context
+    // pinned host staging for uploads and read-backs (grown on demand)
+    char *hup = nullptr, *hdown = nullptr;
+    size_t hup_bytes = 0, hdown_bytes = 0;
     TuneEntry tune[NPATH][MAX_N + 1];
     std::string arch;
 
@@ -119,332 +125,9 @@ int hip_status(hipError_t e) { return e == hipSuccess ? TOR_OK : (e == hipErrorO
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Cholesky of the Hermitian 2n x 2n matrix C (full storage), FP64, as
-// C = U^H U with U upper triangular, row by row: row j is scaled by the
-// reciprocal square root of its pivot, then subtracted from every later row
-// (contiguous updates, no serial dot products).  True when every pivot is
-// positive.
-bool hpd_check(int n2, const std::vector<double> &C)
-{
-    std::vector<double> U(C);
-    for (int j = 0; j < n2; j++) {
-        double *uj = &U[2 * (size_t)j * n2];
-        const double d = uj[2 * j];
-        if (!(d > 0.0))
-            return false;
-        const double inv = 1.0 / std::sqrt(d);
-        for (int k = 2 * j; k < 2 * n2; k++)
-            uj[k] *= inv;
-        for (int i = j + 1; i < n2; i++) {
-            double *ui = &U[2 * (size_t)i * n2];
-            // row i -= conj(U[j][i]) * row j
-            const double fr = uj[2 * i], fi = -uj[2 * i + 1];
-            for (int k = i; k < n2; k++) {
-                const double xr = uj[2 * k], xi = uj[2 * k + 1];
-                ui[2 * k] -= fr * xr - fi * xi;
-                ui[2 * k + 1] -= fr * xi + fi * xr;
-            }
-        }
-    }
-    return true;
-}
-
-// sqrt(det(I - O)) of the Hermitian completion of the lower triangle of
-// I - O (2M x 2M, O row-major with leading dimension ld, complex
-// interleaved), by a Cholesky factorisation in long double: the product of
-// the diagonal of L.  Returns a negative value when I - O is not positive
-// definite.
-double host_sqrt_det(int M, const double *O, long ld)
-{
-    const int m2 = 2 * M;
-    std::vector<long double> Cr((size_t)m2 * m2), Ci((size_t)m2 * m2);
-    for (int a = 0; a < m2; a++)
-        for (int b = 0; b <= a; b++) {
-            const long double orr = O[2 * ((size_t)a * ld + b)], oi = O[2 * ((size_t)a * ld + b) + 1];
-            const long double cr = (a == b ? 1.0L : 0.0L) - orr, ci = (a == b) ? 0.0L : -oi;
-            Cr[(size_t)a * m2 + b] = cr;
-            Ci[(size_t)a * m2 + b] = ci;
-        }
-    long double prod = 1.0L;
-    for (int j = 0; j < m2; j++) {
-        long double d = Cr[(size_t)j * m2 + j];
-        for (int k = 0; k < j; k++)
-            d -= Cr[(size_t)j * m2 + k] * Cr[(size_t)j * m2 + k] + Ci[(size_t)j * m2 + k] * Ci[(size_t)j * m2 + k];
-        if (!(d > 0.0L))
-            return -1.0;
-        const long double ljj = std::sqrt(d);
-        prod *= ljj;
-        Cr[(size_t)j * m2 + j] = ljj;
-        Ci[(size_t)j * m2 + j] = 0.0L;
-        for (int i = j + 1; i < m2; i++) {
-            long double sr = Cr[(size_t)i * m2 + j], si = Ci[(size_t)i * m2 + j];
-            for (int k = 0; k < j; k++) {
-                // L[i][k] conj(L[j][k])
-                const long double ar = Cr[(size_t)i * m2 + k], ai = Ci[(size_t)i * m2 + k];
-                const long double br = Cr[(size_t)j * m2 + k], bi = Ci[(size_t)j * m2 + k];
-                sr -= ar * br + ai * bi;
-                si -= ai * br - ar * bi;
-            }
-            Cr[(size_t)i * m2 + j] = sr / ljj;
-            Ci[(size_t)i * m2 + j] = si / ljj;
-        }
-    }
-    return (double)prod;
-}
-
-// Gaussian-state structure.  The sampling matrix of a Gaussian state in
-// block order has the form [[P, Q], [conj Q, conj P]] (Sec. 1: A = I - Sigma^-1
-// from the Husimi covariance), and so has C = I - O.  For such C the unitary
-// w = [[1, 1], [-i, i]] / sqrt(2) applied to every mode pair turns each 2x2
-// mode block [[p, q], [conj q, conj p]] into the real block
-// [[Re p + Re q, Im q - Im p], [Im p + Im q, Re p - Re q]]; the result is real
-// symmetric and every principal mode-submatrix keeps its determinant
-// (w is unitary and acts inside each mode), so the Torontonian is unchanged.
-// C is taken as structured when both defining relations hold to 64 units of
-// roundoff of max |C|; it is then symmetrised exactly (P <- (P + conj P')/2,
-// Q <- (Q + Q^T)/2) before the transform.  With quad set the form is built in
-// double-double from O itself (1 - O_ii and every sum of the transform are
-// exact or rounded to 2^-106), for the double-double factor.
-// Host double-double helpers: exact sum by TwoSum, renormalised sum.
-struct hdd {
-    double hi, lo;
-};
-hdd h_two_sum(double a, double b)
-{
-    const double s = a + b, bb = s - a;
-    return hdd{s, (a - (s - bb)) + (b - bb)};
-}
-hdd h_add(hdd a, hdd b)
-{
-    hdd s = h_two_sum(a.hi, b.hi);
-    const hdd t = h_two_sum(a.lo, b.lo);
-    s.lo += t.hi;
-    s = h_two_sum(s.hi, s.lo);
-    s.lo += t.lo;
-    return h_two_sum(s.hi, s.lo);
-}
-hdd h_neg(hdd a) { return hdd{-a.hi, -a.lo}; }
-
-// Gaussian-state structure test of C (full Hermitian storage, block order):
-// both defining relations hold to 64 units of roundoff of max |C| (cmax2 =
-// max |C|^2).  Squared magnitudes are compared, so no square root is taken.
-bool gaussian_structure(int n, const std::vector<double> &C, double cmax2)
-{
-    const int n2 = 2 * n;
-    auto cre = [&](int a, int b) { return C[2 * ((size_t)a * n2 + b)]; };
-    auto cim = [&](int a, int b) { return C[2 * ((size_t)a * n2 + b) + 1]; };
-    double dev2 = 0.0;
-    auto sq = [](double x, double y) { return x * x + y * y; };
-    for (int i = 0; i < n; i++)
-        for (int j = 0; j < n; j++) {
-            // lower-right block = conj(upper-left); lower-left block symmetric
-            dev2 = std::max(dev2, sq(cre(i + n, j + n) - cre(i, j), cim(i + n, j + n) + cim(i, j)));
-            dev2 = std::max(dev2, sq(cre(i + n, j) - cre(j + n, i), cim(i + n, j) - cim(j + n, i)));
-        }
-    const double tol = 64.0 * kU * std::max(std::sqrt(cmax2), 1.0);
-    return dev2 <= tol * tol;
-}
-
-// The real form of the symmetrised C, dense (2n x 2n, row-major, row 2 i + c
-// for component c of mode i).
-void real_form(int n, const std::vector<double> &C, std::vector<double> &R)
-{
-    const int n2 = 2 * n;
-    auto cre = [&](int a, int b) { return C[2 * ((size_t)a * n2 + b)]; };
-    auto cim = [&](int a, int b) { return C[2 * ((size_t)a * n2 + b) + 1]; };
-    R.assign((size_t)n2 * n2, 0.0);
-    for (int mi = 0; mi < n; mi++)
-        for (int mj = 0; mj < n; mj++) {
-            const double pr = 0.5 * (cre(mi, mj) + cre(mi + n, mj + n));
-            const double pi = 0.5 * (cim(mi, mj) - cim(mi + n, mj + n));
-            // Q = upper-right block, symmetrised: (Q + Q^T)/2, with Q[i][j] = C[i][j+n]
-            const double qr = 0.5 * (cre(mi, mj + n) + cre(mj, mi + n));
-            const double qi = 0.5 * (cim(mi, mj + n) + cim(mj, mi + n));
-            double *r0 = &R[(size_t)(2 * mi) * n2 + 2 * mj], *r1 = r0 + n2;
-            r0[0] = pr + qr;
-            r0[1] = qi - pi;
-            r1[0] = pi + qi;
-            r1[1] = pr - qr;
-        }
-}
-
-// Cholesky of the real symmetric m x m matrix R (row-major, full storage),
-// FP64, in a scratch copy, in the row form of hpd_check: true when every
-// pivot is positive.
-bool spd_check(int m, const std::vector<double> &R)
-{
-    std::vector<double> U(R);
-    for (int j = 0; j < m; j++) {
-        double *uj = &U[(size_t)j * m];
-        const double d = uj[j];
-        if (!(d > 0.0))
-            return false;
-        const double inv = 1.0 / std::sqrt(d);
-        for (int k = j; k < m; k++)
-            uj[k] *= inv;
-        for (int i = j + 1; i < m; i++) {
-            double *ui = &U[(size_t)i * m];
-            const double f = uj[i];
-            for (int k = i; k < m; k++)
-                ui[k] -= f * uj[k];
-        }
-    }
-    return true;
-}
-
-// Pack the real form R (dense, from real_form) for the real path, or, with
-// quad set, the same form rebuilt in double-double from O for the
-// double-double factor.
-void stage_real(int n, const std::vector<double> &R, const double *O, long ld, bool quad, Staged &st)
-{
-    const int n2 = 2 * n;
-    const int N = std::max(n, quad ? QUAD_R : REAL_R);
-    st.Nr = N;
-    if (quad) {
-        // entry (a, b) of I - O from the lower triangle of O, in double-double
-        auto cdd = [&](int a, int b, hdd &re_, hdd &im_) {
-            const bool up = a < b;
-            const int i = up ? b : a, j = up ? a : b;
-            const double orr = O[2 * ((size_t)i * ld + j)], oi = O[2 * ((size_t)i * ld + j) + 1];
-            re_ = h_two_sum(i == j ? 1.0 : 0.0, -orr);
-            im_ = hdd{i == j ? 0.0 : (up ? oi : -oi), 0.0};
-        };
-        auto qblk = [&](int mi, int mj, int ci, int cj) -> hdd {
-            if (mi >= n || mj >= n)
-                return hdd{(mi == mj && ci == cj) ? 0.5 : 0.0, 0.0};
-            hdd p1r, p1i, p2r, p2i, q1r, q1i, q2r, q2i;
-            cdd(mi, mj, p1r, p1i);
-            cdd(mi + n, mj + n, p2r, p2i);
-            cdd(mi, mj + n, q1r, q1i);
-            cdd(mj, mi + n, q2r, q2i);
-            auto half = [](hdd v) { return hdd{0.5 * v.hi, 0.5 * v.lo}; };
-            const hdd pr = half(h_add(p1r, p2r)), pi = half(h_add(p1i, h_neg(p2i)));
-            const hdd qr = half(h_add(q1r, q2r)), qi = half(h_add(q1i, q2i));
-            if (ci == 0 && cj == 0) return h_add(pr, qr);
-            if (ci == 0 && cj == 1) return h_add(qi, h_neg(pi));
-            if (ci == 1 && cj == 0) return h_add(pi, qi);
-            return h_add(pr, h_neg(qr));
-        };
-        st.packed_q.assign((size_t)NSZ(N), ddr{0.0, 0.0});
-        for (int a = 0; a < N; a++)
-            for (int b = 0; b <= a; b++)
-                for (int e = 0; e < 4; e++) {
-                    const int qi = 2 * N - 1 - (2 * a + (e >> 1)), qj = 2 * N - 1 - (2 * b + (e & 1));
-                    const hdd v = qblk(qi / 2, qj / 2, qi % 2, qj % 2);
-                    st.packed_q[(size_t)gpos((int)sizeof(ddr), NB(N), bidx(a, b), e)] = ddr{v.hi, v.lo};
-                }
-        st.path = PATH_QUAD;
-        return;
-    }
-    st.packed_r.assign((size_t)NSZ(N), 0.0);
-    // entry (qi, qj) of the form, interleaved order; modes >= n are padding
-    auto rel = [&](int qi, int qj) -> double {
-        if (qi >= n2 || qj >= n2)
-            return qi == qj ? 0.5 : 0.0;
-        return R[(size_t)qi * n2 + qj];
-    };
-    for (int a = 0; a < N; a++)
-        for (int b = 0; b <= a; b++)
-            for (int e = 0; e < 4; e++) {
-                const int qi = 2 * N - 1 - (2 * a + (e >> 1)), qj = 2 * N - 1 - (2 * b + (e & 1));
-                st.packed_r[(size_t)gpos((int)sizeof(double), NB(N), bidx(a, b), e)] = rel(qi, qj);
-            }
-    st.path = PATH_REAL;
-}
-
-// Validate, check, pack one matrix.  O is host memory.
-int stage_matrix(int n, const double *O, long ld, unsigned flags, int min_modes, Staged &st)
-{
-    st.n = n;
-    if (n < 0)
-        return TOR_E_INVAL;
-    if (n > 0 && (!O || ld < 2L * n))
-        return TOR_E_INVAL;
-    const int n2 = 2 * n;
-    // Hermitian completion of the lower triangle of C = I - O
-    std::vector<double> C((size_t)n2 * n2 * 2);
-    double cmax2 = 0.0;  // max |C|^2
-    for (int a = 0; a < n2; a++)
-        for (int b = 0; b <= a; b++) {
-            double orr = O[2 * ((size_t)a * ld + b)], oi = O[2 * ((size_t)a * ld + b) + 1];
-            if (!std::isfinite(orr) || !std::isfinite(oi))
-                return TOR_E_INVAL;
-            double cr = (a == b ? 1.0 : 0.0) - orr;
-            double ci = (a == b) ? 0.0 : -oi;
-            cmax2 = std::max(cmax2, cr * cr + ci * ci);
-            C[2 * ((size_t)a * n2 + b)] = cr;
-            C[2 * ((size_t)a * n2 + b) + 1] = ci;
-            C[2 * ((size_t)b * n2 + a)] = cr;
-            C[2 * ((size_t)b * n2 + a) + 1] = -ci;
-        }
-    if (flags & TOR_CHECK_HERMITIAN) {
-        double scale = 0.0, diff = 0.0;
-        for (int a = 0; a < n2; a++)
-            for (int b = 0; b < n2; b++) {
-                double orr = O[2 * ((size_t)a * ld + b)], oi = O[2 * ((size_t)a * ld + b) + 1];
-                double tr = O[2 * ((size_t)b * ld + a)], ti = -O[2 * ((size_t)b * ld + a) + 1];
-                if (!std::isfinite(orr) || !std::isfinite(oi))
-                    return TOR_E_INVAL;
-                scale = std::max(scale, std::hypot(orr, oi));
-                diff = std::max(diff, std::hypot(orr - tr, oi - ti));
-            }
-        if (diff > 1e-12 * std::max(scale, 1.0))
-            return TOR_E_INVAL;
-    }
-    // The real path when the Gaussian-state structure holds: positive
-    // definiteness is checked on the real symmetric form the kernel factors
-    // (it has the eigenvalues of the symmetrised C), and the complex layout
-    // is not built.  The empty matrix stays on the complex path unless the
-    // double-double factor is asked for.
-    const bool dd = (flags & TOR_FACTOR_DD) != 0;
-    st.N = std::max(n, min_modes);
-    if ((dd || (n > 0 && !(flags & TOR_FORCE_COMPLEX))) && gaussian_structure(n, C, cmax2)) {
-        std::vector<double> R;
-        real_form(n, C, R);
-        if (n > 0 && !spd_check(n2, R))
-            return TOR_E_NOT_PD;
-        stage_real(n, R, O, ld, dd, st);
-        return TOR_OK;
-    }
-    // the double-double factor runs on the real form only
-    if (dd)
-        return TOR_E_INVAL;
-    if (n > 0 && !hpd_check(n2, C))
-        return TOR_E_NOT_PD;
-    // pack: N modes, reversed interleaved rows; row q (interleaved) of mode q/2,
-    // component q%2 -> block-order row (q/2) + (q%2) n; modes >= n are padding
-    const int N = st.N;
-    st.packed.assign((size_t)NSZ(N), c64{0.0, 0.0});
-    auto elem = [&](int qi, int qj) -> c64 {
-        int mi = qi / 2, ci = qi % 2, mj = qj / 2, cj = qj % 2;
-        if (mi >= n || mj >= n)
-            return (qi == qj) ? c64{0.5, 0.0} : c64{0.0, 0.0};
-        int a = mi + ci * n, b = mj + cj * n;
-        return c64{C[2 * ((size_t)a * n2 + b)], C[2 * ((size_t)a * n2 + b) + 1]};
-    };
-    for (int a = 0; a < N; a++)
-        for (int b = 0; b <= a; b++)
-            for (int e = 0; e < 4; e++) {
-                const int x = 2 * a + (e >> 1), y = 2 * b + (e & 1);
-                c64 v = elem(2 * N - 1 - x, 2 * N - 1 - y);
-                if (x == y)
-                    v.y = 0.0;
-                st.packed[(size_t)gpos((int)sizeof(c64), NB(N), bidx(a, b), e)] = v;
-            }
-    st.path = PATH_CPLX;
-    return TOR_OK;
-}
-
-
 int path_R(int path) { return path == PATH_QUAD ? QUAD_R : path == PATH_REAL ? REAL_R : CPLX_R; }
-int modes_of(const Staged &m, int path) { return path == PATH_CPLX ? m.N : m.Nr; }
 // bytes per scalar of the device layout (c64 and ddr are both 16)
 size_t path_esz(int path) { return path == PATH_REAL ? sizeof(double) : sizeof(c64); }
-const void *packed_of(const Staged &m, int path)
-{
-    return path == PATH_QUAD ? (const void *)m.packed_q.data()
-                             : path == PATH_REAL ? (const void *)m.packed_r.data() : (const void *)m.packed.data();
-}
 // tor_result.path: 1 real, 2 complex, 3 real with a double-double factor
 int api_path(int path) { return path == PATH_REAL ? 1 : path == PATH_QUAD ? 3 : 2; }
 const char *path_name(int path) { return path == PATH_REAL ? "real" : path == PATH_QUAD ? "quad" : "complex"; }
@@ -500,6 +183,249 @@ int ensure_ws(tor_ctx *ctx, size_t bytes)
     ctx->ws_bytes = want;
     return TOR_OK;
 }
+
+// Grow the workspace to at least bytes, keeping its first `keep` bytes.
+int ensure_ws_keep(tor_ctx *ctx, size_t bytes, size_t keep)
+{
+    if (bytes <= ctx->ws_bytes)
+        return TOR_OK;
+    if (!ctx->own_ws)
+        return TOR_E_NOMEM;
+    const size_t want = align_up(bytes + (bytes >> 3), 1 << 20);
+    char *nw = nullptr;
+    if (hipMalloc((void **)&nw, want) != hipSuccess)
+        return TOR_E_NOMEM;
+    hipError_t e = hipSuccess;
+    if (ctx->ws && keep > 0)
+        e = hipMemcpyAsync(nw, ctx->ws, keep, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(nw);
+        return hip_status(e);
+    }
+    if (ctx->ws)
+        (void)hipFree(ctx->ws);
+    ctx->ws = nw;
+    ctx->ws_bytes = want;
+    return TOR_OK;
+}
+
+// Pinned host buffer of at least need bytes.  Only grown between
+// synchronised calls, so no copy is in flight from the old one.
+int pin_grow(char *&buf, size_t &cap, size_t need)
+{
+    if (need <= cap)
+        return TOR_OK;
+    if (buf)
+        (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
+    const size_t want = align_up(std::max(need + (need >> 2), (size_t)1 << 16), 4096);
+    if (hipHostMalloc((void **)&buf, want, hipHostMallocDefault) != hipSuccess) {
+        buf = nullptr;
+        return TOR_E_NOMEM;
+    }
+    cap = want;
+    return TOR_OK;
+}
+
+const char *mat_ptr(const tor_ctx *ctx, const Mat &m) { return m.pool ? m.pool : ctx->ws + m.ws_off; }
+
+unsigned stage_flags(unsigned api_flags)
+{
+    return ((api_flags & TOR_CHECK_HERMITIAN) ? STAGE_CHECK_HERM : 0u) |
+           ((api_flags & TOR_FORCE_COMPLEX) ? STAGE_FORCE_CPLX : 0u) | ((api_flags & TOR_FACTOR_DD) ? STAGE_DD : 0u);
+}
+
+// Device bytes of the staged form of an n-mode matrix: the largest form the
+// staging kernel may choose under these flags.
+size_t staged_bytes(int n, unsigned sflags, int min_cplx)
+{
+    if (sflags & STAGE_INTERLEAVED)
+        return sizeof(c64) * (size_t)E(std::max(n, 1));
+    if (sflags & STAGE_DD)
+        return sizeof(ddr) * (size_t)NSZ(std::max(n, QUAD_R));
+    size_t b = sizeof(c64) * (size_t)NSZ(std::max(n, min_cplx));
+    if (!(sflags & STAGE_FORCE_CPLX))
+        b = std::max(b, sizeof(double) * (size_t)NSZ(std::max(n, REAL_R)));
+    return b;
+}
+
+// One matrix to stage: n modes of O (host or device memory, leading
+// dimension ld in complex elements); with sel (host, n increasing modes) the
+// principal submatrix of an M-mode O on rows {s, s + M}.  dst: where the
+// staged form goes when not in the workspace (the serving pool).
+struct StageIn {
+    int n = 0;
+    const double *O = nullptr;
+    long ld = 0;
+    const int *sel = nullptr;
+    int M = 0;
+    char *dst = nullptr;
+};
+
+// Enqueue one staging launch for in[0..count) on the context's stream: the
+// descriptors, the pattern lists and (for host inputs) the raw matrices go
+// up in one copy into the workspace from byte base on; the staged forms
+// follow them.  The kernel's verdicts are copied back into ctx->hdown
+// (StageInfo each, from byte 0); *end receives the first workspace byte
+// after the staging area and *down_end the first free byte of ctx->hdown.
+// stage_collect reads them after the stream has been synchronised.
+// Workspace layout of a staging launch (offsets from its base).
+struct StageLayout {
+    size_t b_desc = 0, b_info = 0, b_sel = 0, b_raw = 0, up_bytes = 0, total = 0;
+    std::vector<size_t> raw_off, out_off;
+    std::vector<const double *> raw_src;  // distinct host matrices, in upload order
+};
+
+StageLayout stage_layout(const std::vector<StageIn> &in, bool on_device, unsigned sflags, int min_cplx)
+{
+    const int count = (int)in.size();
+    StageLayout L;
+    L.b_desc = align_up(sizeof(StageDesc) * count, 256);
+    L.b_info = align_up(sizeof(StageInfo) * count, 256);
+    size_t nsel = 0;
+    for (const StageIn &x : in)
+        if (x.sel)
+            nsel += (size_t)x.n;
+    L.b_sel = align_up(sizeof(int) * std::max(nsel, (size_t)1), 256);
+    // raw inputs: one compact copy per distinct host matrix
+    L.raw_off.assign(count, 0);
+    std::vector<size_t> src_off;
+    if (!on_device)
+        for (int i = 0; i < count; i++) {
+            const int rows = 2 * (in[i].sel ? in[i].M : in[i].n);
+            if (rows == 0)
+                continue;
+            size_t j = 0;
+            while (j < L.raw_src.size() && L.raw_src[j] != in[i].O)
+                ++j;
+            if (j == L.raw_src.size()) {
+                L.raw_src.push_back(in[i].O);
+                src_off.push_back(L.b_raw);
+                L.b_raw += align_up(sizeof(c64) * (size_t)rows * rows, 256);
+            }
+            L.raw_off[i] = src_off[j];
+        }
+    L.up_bytes = L.b_desc + L.b_info + L.b_sel + L.b_raw;
+    size_t out_bytes = 0;
+    L.out_off.assign(count, 0);
+    for (int i = 0; i < count; i++)
+        if (!in[i].dst) {
+            L.out_off[i] = L.up_bytes + out_bytes;
+            out_bytes += align_up(staged_bytes(in[i].n, sflags, min_cplx), 256);
+        }
+    L.total = L.up_bytes + out_bytes;
+    return L;
+}
+
+int stage_enqueue(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, unsigned sflags, int min_cplx,
+                  size_t base, std::vector<Mat> &mats, size_t *end, size_t *down_end)
+{
+    const int count = (int)in.size();
+    mats.assign(count, Mat{});
+    *end = base;
+    *down_end = 0;
+    if (count == 0)
+        return TOR_OK;
+    const StageLayout L = stage_layout(in, on_device, sflags, min_cplx);
+    const size_t b_desc = L.b_desc, b_info = L.b_info, b_sel = L.b_sel, up_bytes = L.up_bytes;
+    const std::vector<size_t> &raw_off = L.raw_off, &out_off = L.out_off;
+    // device inputs that live in the workspace must already fit (growing
+    // it would move them)
+    int rc = ensure_ws_keep(ctx, base + L.total, base);
+    if (rc == TOR_OK)
+        rc = pin_grow(ctx->hup, ctx->hup_bytes, up_bytes);
+    if (rc == TOR_OK)  // 256 spare bytes for a caller's own read-back
+        rc = pin_grow(ctx->hdown, ctx->hdown_bytes, b_info + 256);
+    if (rc != TOR_OK)
+        return rc;
+    char *dbase = ctx->ws + base;
+    char *h = ctx->hup;
+    StageDesc *hd = (StageDesc *)h;
+    int *hsel = (int *)(h + b_desc + b_info);
+    size_t sel_at = 0;
+    std::vector<char> copied(L.raw_src.size(), 0);
+    for (int i = 0; i < count; i++) {
+        const StageIn &x = in[i];
+        StageDesc d{};
+        d.n = x.n;
+        d.M = x.sel ? x.M : x.n;
+        d.flags = sflags;
+        d.min_cplx = min_cplx;
+        d.info = (StageInfo *)(dbase + b_desc) + i;
+        d.out = x.dst ? (void *)x.dst : (void *)(dbase + out_off[i]);
+        if (x.sel) {
+            std::memcpy(hsel + sel_at, x.sel, sizeof(int) * (size_t)x.n);
+            d.sel = (const int *)(dbase + b_desc + b_info) + sel_at;
+            sel_at += (size_t)x.n;
+        }
+        const int rows = 2 * d.M;
+        if (rows > 0 && !on_device) {
+            char *dst = h + b_desc + b_info + b_sel + raw_off[i];
+            size_t si = 0;
+            while (L.raw_src[si] != x.O)
+                ++si;
+            if (!copied[si]) {
+                for (int r = 0; r < rows; r++)
+                    std::memcpy(dst + sizeof(c64) * (size_t)r * rows, x.O + 2 * (size_t)r * (size_t)x.ld,
+                                sizeof(c64) * (size_t)rows);
+                copied[si] = 1;
+            }
+            d.O = (const double *)(dbase + b_desc + b_info + b_sel + raw_off[i]);
+            d.ld = rows;
+        } else {
+            d.O = x.O;
+            d.ld = x.ld;
+        }
+        hd[i] = d;
+        mats[i].n = x.n;
+        mats[i].pool = x.dst;
+        mats[i].ws_off = x.dst ? 0 : base + out_off[i];
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    // the infos' bytes are part of the copy (their values do not matter)
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dbase, h, up_bytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_stage((const StageDesc *)dbase, count, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->hdown, dbase + b_desc, sizeof(StageInfo) * count, hipMemcpyDeviceToHost, ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    *end = base + L.total;
+    *down_end = b_info;
+    return TOR_OK;
+}
+
+// After the stream has been synchronised: each matrix's path, modes and
+// status from the staging kernel's verdicts.
+void stage_collect(const tor_ctx *ctx, std::vector<Mat> &mats)
+{
+    const StageInfo *info = (const StageInfo *)ctx->hdown;
+    for (size_t i = 0; i < mats.size(); i++) {
+        mats[i].status = info[i].status == 0 ? TOR_OK : TOR_E_INVAL;
+        mats[i].path = info[i].path;
+        mats[i].N = info[i].N;
+    }
+}
+
+// Stage, wait, collect.
+int stage_sync(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, unsigned sflags, int min_cplx,
+               size_t base, std::vector<Mat> &mats, size_t *end)
+{
+    size_t down_end = 0;
+    int rc = stage_enqueue(ctx, in, on_device, sflags, min_cplx, base, mats, end, &down_end);
+    if (rc != TOR_OK || in.empty())
+        return rc;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    stage_collect(ctx, mats);
+    return TOR_OK;
+}
+
 
 // Workspace bytes a launch needs after its matrices and slots: descriptors,
 // reduction descriptors, queue counter, results, per-wave tier-A stacks.
@@ -599,59 +525,46 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     return TOR_OK;
 }
 
-// Synchronous path: all roots of every matrix in one launch, matrices with
-// more modes first.  results: 4 doubles per matrix (input order).
-int run_recursive(tor_ctx *ctx, int path, std::vector<Staged *> &mats, std::vector<int> &ks,
-                  std::vector<double> &results, float *ms, std::vector<double> *slots_out)
+// Synchronous path: all roots of every staged matrix in one launch, matrices
+// with more modes first; their root slots and the launch's own data go into
+// the workspace from byte base on.  results: 4 doubles per matrix (input
+// order).
+int run_recursive(tor_ctx *ctx, int path, std::vector<Mat *> &mats, std::vector<int> &ks,
+                  std::vector<double> &results, float *ms, std::vector<double> *slots_out, size_t base)
 {
-    const size_t esz = path_esz(path);
     const int count = (int)mats.size();
     std::vector<int> order(count);
     for (int i = 0; i < count; i++)
         order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return modes_of(*mats[a], path) > modes_of(*mats[b], path); });
-    // workspace: matrices, then slots, then what run_launch needs
-    std::vector<size_t> c_off(count), s_off(count);
-    size_t off = 0;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mats[a]->N > mats[b]->N; });
+    // workspace: slots, then what run_launch needs
+    std::vector<size_t> s_off(count);
     long long nslots = 0;
     int Nmax = 0;
     for (int s = 0; s < count; s++) {
-        const Staged *m = mats[order[s]];
-        c_off[s] = off;
-        off = align_up(off + esz * (size_t)NSZ(modes_of(*m, path)), 256);
-        Nmax = std::max(Nmax, modes_of(*m, path));
-    }
-    for (int s = 0; s < count; s++) {
-        s_off[s] = off + sizeof(double) * 4 * (size_t)nslots;
+        s_off[s] = base + sizeof(double) * 4 * (size_t)nslots;
         nslots += 1ll << ks[order[s]];
+        Nmax = std::max(Nmax, mats[order[s]]->N);
     }
-    off = align_up(off + sizeof(double) * 4 * (size_t)nslots, 256);
+    const size_t off = align_up(base + sizeof(double) * 4 * (size_t)nslots, 256);
     const int grid = launch_grid(ctx, path, Nmax);
-    // size the workspace for everything before placing data in it
-    int rc = ensure_ws(ctx, off + launch_layout(path, count, count, Nmax).total(grid));
+    // size the workspace for everything, keeping the staged matrices below base
+    int rc = ensure_ws_keep(ctx, off + launch_layout(path, count, count, Nmax).total(grid), base);
     if (rc != TOR_OK)
         return rc;
-    std::vector<char> hbuf(s_off.empty() ? 0 : s_off[0], 0);
     std::vector<ProblemDesc> descs(count);
     std::vector<int> red(count);
     for (int s = 0; s < count; s++) {
-        const Staged *m = mats[order[s]];
-        std::memcpy(hbuf.data() + c_off[s], packed_of(*m, path), esz * (size_t)NSZ(modes_of(*m, path)));
+        const Mat *m = mats[order[s]];
         ProblemDesc &d = descs[s];
-        d.C = ctx->ws + c_off[s];
+        d.C = mat_ptr(ctx, *m);
         d.slots = (double *)(ctx->ws + s_off[s]);
-        d.N = modes_of(*m, path);
+        d.N = m->N;
         d.k = ks[order[s]];
         d.root_begin = 0;
         d.nroots = 1ll << d.k;
         red[s] = s;
     }
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e == hipSuccess && !hbuf.empty())
-        e = hipMemcpyAsync(ctx->ws, hbuf.data(), hbuf.size(), hipMemcpyHostToDevice, ctx->stream);
-    if (e != hipSuccess)
-        return hip_status(e);
     std::vector<double> res;
     rc = run_launch(ctx, path, descs, red, off, grid, &res, ms);
     if (rc != TOR_OK)
@@ -662,14 +575,15 @@ int run_recursive(tor_ctx *ctx, int path, std::vector<Staged *> &mats, std::vect
             results[4 * (size_t)order[s] + j] = res[4 * (size_t)s + j];
     if (slots_out) {
         slots_out->resize(4 * (size_t)nslots);
-        e = hipMemcpy(slots_out->data(), ctx->ws + s_off[0], sizeof(double) * 4 * nslots, hipMemcpyDeviceToHost);
+        hipError_t e = hipMemcpy(slots_out->data(), ctx->ws + s_off[0], sizeof(double) * 4 * nslots,
+                                 hipMemcpyDeviceToHost);
         if (e != hipSuccess)
             return hip_status(e);
     }
     return TOR_OK;
 }
 
-void fill_result(const Staged &st, int path, const double *r, float ms, tor_result *out)
+void fill_result(const Mat &st, int path, const double *r, float ms, tor_result *out)
 {
     std::memset(out, 0, sizeof(*out));
     out->tor = r[0];
@@ -677,7 +591,7 @@ void fill_result(const Staged &st, int path, const double *r, float ms, tor_resu
     // a padding mode (its block of I - O is I/2) turns each term t into the
     // pair -t, +2t: Tor is unchanged and the padded sum of |t| is 3 times the
     // input's, so it is scaled back (3^pad is exact for pad < 34)
-    const int pad = modes_of(st, path) - st.n;
+    const int pad = st.N - st.n;
     out->sum_abs = pad > 0 ? r[2] / std::pow(3.0, pad) : r[2];
     const double v = std::fabs(r[0] + r[1]);
     // each term carries a relative rounding error of a few units of roundoff
@@ -687,65 +601,52 @@ void fill_result(const Staged &st, int path, const double *r, float ms, tor_resu
     const double u = path == PATH_QUAD ? kUdd : kU;
     out->err_est = u * (double)std::max(st.n, 1) * R / std::sqrt(std::ldexp(1.0, st.n));
     out->subsets = 1ull << st.n;
-    out->status = (r[3] != 0.0 || !std::isfinite(r[0])) ? TOR_E_NUMERIC : TOR_OK;
+    // a pivot that is not positive in some subset: I - O is not positive
+    // definite (the all-include subset is I - O itself)
+    out->status = r[3] != 0.0 ? TOR_E_NOT_PD : !std::isfinite(r[0]) ? TOR_E_NUMERIC : TOR_OK;
     out->path = api_path(path);
     out->device_ms = ms;
-}
-
-int copy_input_to_host(int n, const double *O, long ld, unsigned flags, std::vector<double> &tmp, const double *&host)
-{
-    host = O;
-    if (!(flags & TOR_INPUT_DEVICE) || n == 0)
-        return TOR_OK;
-    if (!O || ld < 2L * n)
-        return TOR_E_INVAL;
-    tmp.resize((size_t)2 * n * ld * 2);
-    hipError_t e = hipMemcpy(tmp.data(), O, sizeof(double) * tmp.size(), hipMemcpyDeviceToHost);
-    if (e != hipSuccess)
-        return hip_status(e);
-    host = tmp.data();
-    return TOR_OK;
 }
 
 // Split depths for a launch of several matrices: roots of about equal work,
 // about four per persistent wave over the whole launch (a lone matrix keeps
 // its own tuned or default depth).
-void batch_ks(const tor_ctx *ctx, int path, const std::vector<Staged *> &grp, std::vector<int> &ks)
+void batch_ks(const tor_ctx *ctx, int path, const std::vector<Mat *> &grp, std::vector<int> &ks)
 {
     if (grp.size() == 1 || ctx->opt.split_k > 0) {
         for (size_t j = 0; j < grp.size(); j++)
-            ks[j] = choose_k(ctx, modes_of(*grp[j], path), path);
+            ks[j] = choose_k(ctx, grp[j]->N, path);
         return;
     }
     double work = 0.0;
     int Nmax = 0;
-    for (Staged *m : grp) {
-        work += std::ldexp(1.0, modes_of(*m, path));
-        Nmax = std::max(Nmax, modes_of(*m, path));
+    for (Mat *m : grp) {
+        work += std::ldexp(1.0, m->N);
+        Nmax = std::max(Nmax, m->N);
     }
     const double per_root = std::max(work / (4.0 * launch_grid(ctx, path, Nmax)), 1.0);
     const int lg = (int)std::floor(std::log2(per_root) + 0.5);
     for (size_t j = 0; j < grp.size(); j++) {
-        const int N = modes_of(*grp[j], path);
+        const int N = grp[j]->N;
         ks[j] = std::max(0, std::min(N - lg, N - path_R(path)));
     }
 }
 
-// Launch the staged matrices, one launch per arithmetic path.
-int run_staged(tor_ctx *ctx, std::vector<Staged *> &mats, const std::vector<int> &idx, int fixed_k,
-               tor_result *out, std::vector<double> *slots_out, int *k_out)
+// Launch the staged matrices, one launch per arithmetic path; the launches
+// use the workspace from byte base on.
+int run_staged(tor_ctx *ctx, std::vector<Mat *> &mats, const std::vector<int> &idx, int fixed_k, tor_result *out,
+               std::vector<double> *slots_out, int *k_out, size_t base)
 {
     int first_err = TOR_OK;
     const int order[NPATH] = {PATH_REAL, PATH_CPLX, PATH_QUAD};
     for (int path : order) {
-        std::vector<Staged *> grp;
+        std::vector<Mat *> grp;
         std::vector<int> gidx, ks;
         for (size_t j = 0; j < mats.size(); j++)
             if (mats[j]->path == path) {
                 grp.push_back(mats[j]);
                 gidx.push_back(idx[j]);
-                const int N = modes_of(*mats[j], path);
-                ks.push_back(std::min(std::max(fixed_k, 0), std::max(N - path_R(path), 0)));
+                ks.push_back(std::min(std::max(fixed_k, 0), std::max(mats[j]->N - path_R(path), 0)));
             }
         if (grp.empty())
             continue;
@@ -753,7 +654,7 @@ int run_staged(tor_ctx *ctx, std::vector<Staged *> &mats, const std::vector<int>
             batch_ks(ctx, path, grp, ks);
         std::vector<double> res;
         float ms = 0.f;
-        int rc = run_recursive(ctx, path, grp, ks, res, &ms, slots_out);
+        int rc = run_recursive(ctx, path, grp, ks, res, &ms, slots_out, base);
         if (rc != TOR_OK)
             return rc;
         for (size_t j = 0; j < grp.size(); j++) {
@@ -767,56 +668,56 @@ int run_staged(tor_ctx *ctx, std::vector<Staged *> &mats, const std::vector<int>
     return first_err;
 }
 
-int eval_many(tor_ctx *ctx, int count, const int *n, const double *const *O, const long *ld, tor_result *out,
-              int fixed_k, std::vector<double> *slots_out, int *k_out, unsigned flags)
+// Check the arguments of one matrix on the host.
+bool args_ok(const tor_ctx *ctx, int n, const double *O, long ld)
 {
-    std::vector<Staged> st(count);
-    std::vector<int> rcs(count, TOR_OK);
-    // host staging (validation, HPD check, packing) of a batch on a few threads
-    auto stage_one = [&](int i) {
-        if (n[i] > ctx->opt.max_n) {
-            rcs[i] = TOR_E_INVAL;
-            return;
-        }
-        std::vector<double> tmp;
-        const double *host;
-        int rc = copy_input_to_host(n[i], O ? O[i] : nullptr, ld ? ld[i] : 0, flags, tmp, host);
-        if (rc == TOR_OK)
-            rc = stage_matrix(n[i], host, ld ? ld[i] : 0, flags, CPLX_R, st[i]);
-        rcs[i] = rc;
-    };
-    const int nthr = (count >= 8 && !(flags & TOR_INPUT_DEVICE))
-                         ? (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()))
-                         : 1;
-    if (nthr <= 1) {
-        for (int i = 0; i < count; i++)
-            stage_one(i);
-    } else {
-        std::vector<std::thread> pool;
-        for (int t = 0; t < nthr; t++)
-            pool.emplace_back([&, t] {
-                for (int i = t; i < count; i += nthr)
-                    stage_one(i);
-            });
-        for (auto &th : pool)
-            th.join();
-    }
-    std::vector<Staged *> ok;
-    std::vector<int> idx;
+    return n >= 0 && n <= ctx->opt.max_n && (n == 0 || (O && ld >= 2L * n));
+}
+
+// Evaluate the matrices in: argument checks, device staging, then one
+// launch per path.  Matrices that fail a check or the staging get that
+// status; the call returns the first error of any matrix.
+int eval_many(tor_ctx *ctx, const std::vector<StageIn> &in, tor_result *out, int fixed_k,
+              std::vector<double> *slots_out, int *k_out, unsigned flags)
+{
+    const int count = (int)in.size();
+    std::vector<StageIn> good;
+    std::vector<int> gi;
     int first_err = TOR_OK;
     for (int i = 0; i < count; i++) {
-        if (rcs[i] != TOR_OK) {
+        const StageIn &x = in[i];
+        const bool ok = x.sel ? (x.n >= 0 && x.n <= ctx->opt.max_n && x.n <= x.M && (x.M == 0 || (x.O && x.ld >= 2L * x.M)))
+                              : args_ok(ctx, x.n, x.O, x.ld);
+        if (!ok) {
             out[i] = tor_result{};
-            out[i].status = rcs[i];
+            out[i].status = TOR_E_INVAL;
             if (first_err == TOR_OK)
-                first_err = rcs[i];
+                first_err = TOR_E_INVAL;
             continue;
         }
-        ok.push_back(&st[i]);
-        idx.push_back(i);
+        good.push_back(x);
+        gi.push_back(i);
+    }
+    std::vector<Mat> mats;
+    size_t end = 0;
+    int rc = stage_sync(ctx, good, (flags & TOR_INPUT_DEVICE) != 0, stage_flags(flags), CPLX_R, 0, mats, &end);
+    if (rc != TOR_OK)
+        return rc;
+    std::vector<Mat *> ok;
+    std::vector<int> idx;
+    for (size_t j = 0; j < mats.size(); j++) {
+        if (mats[j].status != TOR_OK) {
+            out[gi[j]] = tor_result{};
+            out[gi[j]].status = mats[j].status;
+            if (first_err == TOR_OK)
+                first_err = mats[j].status;
+            continue;
+        }
+        ok.push_back(&mats[j]);
+        idx.push_back(gi[j]);
     }
     if (!ok.empty()) {
-        int rc = run_staged(ctx, ok, idx, fixed_k, out, slots_out, k_out);
+        rc = run_staged(ctx, ok, idx, fixed_k, out, slots_out, k_out, end);
         if (rc != TOR_OK && first_err == TOR_OK)
             first_err = rc;
     }
@@ -869,10 +770,20 @@ int serve_k(const tor_ctx *ctx, const Request &r)
     return std::max(0, std::min(k, std::min(LA, 20)));
 }
 
-size_t request_bytes(const Request &r)
+// Pool bytes of a request of n modes: the largest staged form its flags
+// allow, then root slots for the deepest split any of its possible paths
+// may take (serve_k never goes beyond 20).
+size_t request_form_bytes(int n, unsigned sflags) { return align_up(staged_bytes(n, sflags, CPLX_R), 256); }
+size_t request_bytes(int n, unsigned sflags)
 {
-    const size_t esz = path_esz(r.path);
-    return align_up(esz * (size_t)NSZ(r.N), 256) + align_up(sizeof(double) * 4 * (size_t)r.nroots, 256);
+    auto slots_for = [&](int R) {
+        const int k = std::min(std::max(std::max(n, R) - R, 0), 20);
+        return align_up(sizeof(double) * 4 * ((size_t)1 << k), 256);
+    };
+    size_t slots = (sflags & STAGE_DD) ? slots_for(QUAD_R) : slots_for(CPLX_R);
+    if (!(sflags & (STAGE_DD | STAGE_FORCE_CPLX)))
+        slots = std::max(slots, slots_for(REAL_R));
+    return request_form_bytes(n, sflags) + slots;
 }
 
 // One scheduling round for one path: pick root ranges for a launch, run it,
@@ -964,11 +875,9 @@ void serve_loop(tor_ctx *ctx)
             if (ctx->stop)
                 return;
             // admission by device footprint, in arrival order
+            const unsigned sfl = stage_flags(ctx->opt.flags);
             while (!ctx->pending.empty()) {
                 Request *r = ctx->pending.front();
-                r->k = serve_k(ctx, *r);
-                r->nroots = 1ll << r->k;
-                r->root_work = 1ll << (r->N - r->k);
                 if (!ctx->pool) {
                     if (hipSetDevice(ctx->device) != hipSuccess ||
                         hipMalloc((void **)&ctx->pool, ctx->pool_bytes) != hipSuccess) {
@@ -979,13 +888,12 @@ void serve_loop(tor_ctx *ctx)
                     ctx->pool_free[0] = ctx->pool_bytes;
                 }
                 size_t off;
-                const size_t len = request_bytes(*r);
+                const size_t len = request_bytes(r->n, sfl);
                 if (!pool_alloc(ctx, len, off))
                     break;
                 r->pool_off = off;
                 r->pool_len = len;
                 r->dC = ctx->pool + off;
-                r->dSlots = (double *)(ctx->pool + off + align_up(path_esz(r->path) * (size_t)NSZ(r->N), 256));
                 ctx->pending.pop_front();
                 admit.push_back(r);
                 ++ctx->admitted;
@@ -994,25 +902,41 @@ void serve_loop(tor_ctx *ctx)
         std::vector<Request *> finished;
         {
             std::lock_guard<std::mutex> g(ctx->mu);
-            hipError_t e = hipSetDevice(ctx->device);
-            for (Request *r : admit) {
-                const void *src = packed_of(r->st, r->path);
-                const size_t bytes = path_esz(r->path) * (size_t)NSZ(r->N);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(r->dC, src, bytes, hipMemcpyHostToDevice, ctx->stream);
+            // stage the admitted requests on the device, straight into their
+            // pool slots; the path and size of each are known from here on
+            const unsigned sfl = stage_flags(ctx->opt.flags);
+            std::vector<StageIn> in(admit.size());
+            for (size_t j = 0; j < admit.size(); j++) {
+                in[j].n = admit[j]->n;
+                in[j].O = admit[j]->raw.empty() ? nullptr : admit[j]->raw.data();
+                in[j].ld = 2L * admit[j]->n;
+                in[j].dst = admit[j]->dC;
+            }
+            std::vector<Mat> mats;
+            size_t end = 0;
+            const int src = admit.empty() ? TOR_OK : stage_sync(ctx, in, false, sfl, CPLX_R, 0, mats, &end);
+            for (size_t j = 0; j < admit.size(); j++) {
+                Request *r = admit[j];
+                const int st = src != TOR_OK ? src : mats[j].status;
+                if (st != TOR_OK) {
+                    r->res = tor_result{};
+                    r->res.status = st;
+                    finished.push_back(r);
+                    continue;
+                }
+                r->st = mats[j];
+                r->path = r->st.path;
+                r->N = r->st.N;
+                r->k = serve_k(ctx, *r);
+                r->nroots = 1ll << r->k;
+                r->next_root = 0;
+                r->root_work = 1ll << (r->N - r->k);
+                r->dSlots = (double *)(r->dC + request_form_bytes(r->n, sfl));
+                std::vector<double>().swap(r->raw);
                 active.push_back(r);
             }
-            if (e != hipSuccess) {
-                for (Request *r : admit) {
-                    r->res = tor_result{};
-                    r->res.status = hip_status(e);
-                    r->next_root = r->nroots;
-                    finished.push_back(r);
-                }
-            } else {
-                for (int path : {PATH_REAL, PATH_CPLX, PATH_QUAD})
-                    serve_round(ctx, path, active, finished);
-            }
+            for (int path : {PATH_REAL, PATH_CPLX, PATH_QUAD})
+                serve_round(ctx, path, active, finished);
         }
         if (finished.empty() && admit.empty() && active.empty())
             continue;
@@ -1038,14 +962,19 @@ int tune_one(tor_ctx *ctx, int path, int n, TuneEntry &best)
     std::vector<double> O((size_t)2 * n * 2 * n * 2, 0.0);
     for (int i = 0; i < 2 * n; i++)
         O[2 * ((size_t)i * 2 * n + i)] = 0.5;
-    Staged st;
-    const unsigned fl = path == PATH_CPLX ? (unsigned)TOR_FORCE_COMPLEX : path == PATH_QUAD ? (unsigned)TOR_FACTOR_DD : 0u;
-    int rc = stage_matrix(n, O.data(), 2 * n, fl, CPLX_R, st);
+    const unsigned sfl = path == PATH_CPLX ? STAGE_FORCE_CPLX : path == PATH_QUAD ? STAGE_DD : 0u;
+    std::vector<StageIn> in(1);
+    in[0].n = n;
+    in[0].O = O.data();
+    in[0].ld = 2L * n;
+    std::vector<Mat> mats;
+    size_t base = 0;
+    int rc = stage_sync(ctx, in, false, sfl, CPLX_R, 0, mats, &base);
     if (rc != TOR_OK)
         return rc;
-    if (st.path != path)
+    if (mats[0].status != TOR_OK || mats[0].path != path)
         return TOR_E_INVAL;
-    const int N = modes_of(st, path);
+    const int N = mats[0].N;
     const int LA = std::max(N - path_R(path), 0);
     best = TuneEntry{};
     const int wave_opts[5] = {2, 4, 6, 8, ctx->fit[path]};
@@ -1061,19 +990,19 @@ int tune_one(tor_ctx *ctx, int path, int n, TuneEntry &best)
         for (int k = klo; k <= khi; ++k) {
             float tmin = 1e30f;
             for (int rep = 0; rep < 3; rep++) {
-                std::vector<Staged *> mats{&st};
+                std::vector<Mat *> ms{&mats[0]};
                 std::vector<int> ks{k};
                 // run with this grid: temporarily pin the table entry
                 TuneEntry save = ctx->tune[path][std::min(N, MAX_N)];
                 ctx->tune[path][std::min(N, MAX_N)] = TuneEntry{true, k, w, 0.f};
                 std::vector<double> res;
-                float ms = 0.f;
-                rc = run_recursive(ctx, path, mats, ks, res, &ms, nullptr);
+                float ms_ = 0.f;
+                rc = run_recursive(ctx, path, ms, ks, res, &ms_, nullptr, base);
                 ctx->tune[path][std::min(N, MAX_N)] = save;
                 if (rc != TOR_OK)
                     return rc;
                 if (rep > 0)
-                    tmin = std::min(tmin, ms);
+                    tmin = std::min(tmin, ms_);
             }
             if (!best.valid || tmin < best.ms)
                 best = TuneEntry{true, k, w, tmin};
@@ -1126,8 +1055,13 @@ size_t tor_workspace_size(int max_n, int split_k, int max_inflight)
     const long long items = (1ll << std::min(k, std::max(N - Rmin, 0))) * cnt;
     const size_t grid = 256 * MAX_FIT;
     const size_t scr = align_up(sizeof(c64) * (size_t)std::max(Gsum(N - 1) - Gsum(Rmin - 1), 1ll), 256) * grid;
-    return align_up(sizeof(c64) * (size_t)NSZ(N), 256) * cnt + 2 * align_up(sizeof(ProblemDesc) * cnt, 256) + 256 +
-           align_up(32 * (size_t)items, 256) + align_up(32 * (size_t)cnt, 256) + scr + (1 << 20);
+    // staging: descriptors and verdicts, a raw copy of each input and its
+    // staged form (16-byte scalars bound every path)
+    const size_t n2 = 2 * (size_t)std::max(max_n, 1);
+    const size_t stage = align_up(sizeof(StageDesc) * cnt, 256) + align_up(sizeof(StageInfo) * cnt, 256) + 256 +
+                         (align_up(sizeof(c64) * n2 * n2, 256) + align_up(sizeof(c64) * (size_t)NSZ(N), 256)) * cnt;
+    return stage + 2 * align_up(sizeof(ProblemDesc) * cnt, 256) + 256 + align_up(32 * (size_t)items, 256) +
+           align_up(32 * (size_t)cnt, 256) + scr + (1 << 20);
 }
 
 int tor_create(tor_ctx **out, const tor_options *opt)
@@ -1222,6 +1156,10 @@ void tor_destroy(tor_ctx *ctx)
             (void)hipFree(ctx->ws);
         if (ctx->pool)
             (void)hipFree(ctx->pool);
+        if (ctx->hup)
+            (void)hipHostFree(ctx->hup);
+        if (ctx->hdown)
+            (void)hipHostFree(ctx->hdown);
         if (ctx->ev0)
             (void)hipEventDestroy(ctx->ev0);
         if (ctx->ev1)
@@ -1240,11 +1178,12 @@ int tor_eval(tor_ctx *ctx, int n, const double *O, long ld, tor_result *out)
     if (!ctx || !out)
         return TOR_E_INVAL;
     std::lock_guard<std::mutex> g(ctx->mu);
-    const double *Op[1] = {O};
-    long lds[1] = {ld};
-    int ns[1] = {n};
+    std::vector<StageIn> in(1);
+    in[0].n = n;
+    in[0].O = O;
+    in[0].ld = ld;
     tor_result r{};
-    int rc = eval_many(ctx, 1, ns, Op, lds, &r, -1, nullptr, nullptr, ctx->opt.flags);
+    int rc = eval_many(ctx, in, &r, -1, nullptr, nullptr, ctx->opt.flags);
     if (rc == TOR_E_INVAL && r.status == TOR_E_INVAL)
         return rc;
     *out = r;
@@ -1258,7 +1197,13 @@ int tor_eval_batch(tor_ctx *ctx, int count, const int *n, const double *const *O
     if (count == 0)
         return TOR_OK;
     std::lock_guard<std::mutex> g(ctx->mu);
-    return eval_many(ctx, count, n, O, ld, out, -1, nullptr, nullptr, ctx->opt.flags);
+    std::vector<StageIn> in(count);
+    for (int i = 0; i < count; i++) {
+        in[i].n = n[i];
+        in[i].O = O[i];
+        in[i].ld = ld[i];
+    }
+    return eval_many(ctx, in, out, -1, nullptr, nullptr, ctx->opt.flags);
 }
 
 int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max, int *k_out, double *partials,
@@ -1267,19 +1212,21 @@ int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max, 
     if (!ctx || !out || !k_out || !partials || k_max < 0 || k_max > 30)
         return TOR_E_INVAL;
     std::lock_guard<std::mutex> g(ctx->mu);
-    const double *Op[1] = {O};
-    long lds[1] = {ld};
-    int ns[1] = {n};
+    std::vector<StageIn> in(1);
+    in[0].n = n;
+    in[0].O = O;
+    in[0].ld = ld;
     std::vector<double> slots;
     int k = 0;
     tor_result r{};
-    int rc = eval_many(ctx, 1, ns, Op, lds, &r, k_max, &slots, &k, ctx->opt.flags);
+    int rc = eval_many(ctx, in, &r, k_max, &slots, &k, ctx->opt.flags);
     if (rc != TOR_OK && rc != TOR_E_NUMERIC)
         return rc;
     *out = r;
     *k_out = k;
     // padding modes scale each partial's sum of |t| by 3 (see fill_result)
-    const int pad = std::max(n, path_R(r.path == 1)) - n;
+    const int path = r.path == 1 ? PATH_REAL : r.path == 3 ? PATH_QUAD : PATH_CPLX;
+    const int pad = std::max(n, path_R(path)) - n;
     const double p3 = std::pow(3.0, pad);
     for (long long i = 0; i < (1ll << k); i++) {
         partials[3 * i] = slots[4 * i];
@@ -1288,6 +1235,7 @@ int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max, 
     }
     return rc;
 }
+
 int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count, const unsigned long long *patterns,
                     double *probs, tor_result *results)
 {
@@ -1300,82 +1248,132 @@ int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count, co
         if (__builtin_popcountll(patterns[i]) > ctx->opt.max_n)
             return TOR_E_INVAL;
     }
+    if (count == 0)
+        return TOR_OK;
     std::lock_guard<std::mutex> g(ctx->mu);
-    std::vector<double> tmp;
-    const double *host = O;
-    int rc = copy_input_to_host(M, O, ld, ctx->opt.flags, tmp, host);
-    if (rc != TOR_OK)
-        return rc;
-    const double sq = M > 0 ? host_sqrt_det(M, host, ld) : 1.0;
-    if (!(sq > 0.0))
-        return TOR_E_NOT_PD;
+    // O on the device (the caller's, or one copy in the workspace), then the
+    // scratch and result of sqrt(det(I - O)), then the staged patterns
+    const int m2 = 2 * M;
+    const bool dev = (ctx->opt.flags & TOR_INPUT_DEVICE) != 0;
+    const size_t bO = dev ? 0 : align_up(sizeof(c64) * (size_t)m2 * m2, 256);
+    const size_t bScr = align_up(sizeof(c64) * (size_t)std::max(m2 * m2, 1), 256);
+    const size_t base = bO + bScr + 256;
     // the principal submatrix of every pattern: rows and columns {s, s + M}
-    std::vector<std::vector<double>> subs(count);
-    std::vector<int> ns(count);
-    std::vector<const double *> ptrs(count);
-    std::vector<long> lds(count);
+    std::vector<std::vector<int>> sels(count);
+    std::vector<StageIn> in(count);
     for (int i = 0; i < count; i++) {
-        std::vector<int> sel;
         for (int q = 0; q < M; q++)
             if ((patterns[i] >> q) & 1ull)
-                sel.push_back(q);
-        const int k = (int)sel.size();
-        std::vector<int> idx(2 * k);
-        for (int a = 0; a < k; a++) {
-            idx[a] = sel[a];
-            idx[k + a] = sel[a] + M;
-        }
-        subs[i].assign((size_t)2 * k * 2 * k * 2, 0.0);
-        for (int a = 0; a < 2 * k; a++)
-            for (int b = 0; b < 2 * k; b++) {
-                subs[i][2 * ((size_t)a * 2 * k + b)] = host[2 * ((size_t)idx[a] * ld + idx[b])];
-                subs[i][2 * ((size_t)a * 2 * k + b) + 1] = host[2 * ((size_t)idx[a] * ld + idx[b]) + 1];
-            }
-        ns[i] = k;
-        ptrs[i] = subs[i].data();
-        lds[i] = std::max(2 * k, 1);
+                sels[i].push_back(q);
+        in[i].n = (int)sels[i].size();
+        in[i].sel = sels[i].empty() ? nullptr : sels[i].data();
+        in[i].M = M;
     }
-    std::vector<tor_result> res(std::max(count, 1));
-    // the submatrices are host copies even when O was on the device
-    rc = count > 0 ? eval_many(ctx, count, ns.data(), ptrs.data(), lds.data(), res.data(), -1, nullptr, nullptr,
-                               ctx->opt.flags & ~(unsigned)TOR_INPUT_DEVICE)
-                   : TOR_OK;
+    const unsigned sfl = stage_flags(ctx->opt.flags);
+    // the workspace takes O and the staging area before O is placed in it
+    int rc = ensure_ws_keep(ctx, base + stage_layout(in, true, sfl, CPLX_R).total, 0);
+    if (rc != TOR_OK)
+        return rc;
+    hipError_t e = hipSetDevice(ctx->device);
+    const double *dO = O;
+    long dld = ld;
+    if (!dev && M > 0) {
+        e = hipMemcpy2DAsync(ctx->ws, sizeof(c64) * m2, O, sizeof(c64) * (size_t)ld, sizeof(c64) * m2, m2,
+                             hipMemcpyHostToDevice, ctx->stream);
+        dO = (const double *)ctx->ws;
+        dld = m2;
+    }
+    double *dDet = (double *)(ctx->ws + bO + bScr);
+    if (e == hipSuccess && M > 0)
+        e = launch_sqrt_det(dO, dld, M, (c64 *)(ctx->ws + bO), dDet, ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    for (int i = 0; i < count; i++) {
+        in[i].O = dO;
+        in[i].ld = dld;
+    }
+    std::vector<Mat> mats;
+    size_t end = 0, down = 0;
+    rc = stage_enqueue(ctx, in, true, sfl, CPLX_R, base, mats, &end, &down);
+    if (rc != TOR_OK)
+        return rc;
+    // stage_enqueue leaves 256 spare bytes after the verdicts (a copy into
+    // the buffer is pending, so it must not be regrown here)
+    const size_t det_at = align_up(down, 16);
+    if (det_at + 2 * sizeof(double) > ctx->hdown_bytes)
+        return TOR_E_NOMEM;
+    double *hDet = (double *)(ctx->hdown + det_at);
+    hDet[0] = 1.0;
+    hDet[1] = 0.0;
+    e = hipSuccess;
+    if (M > 0)
+        e = hipMemcpyAsync(hDet, dDet, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    stage_collect(ctx, mats);
+    const double sq = hDet[0];
+    if (hDet[1] != 0.0 || !(sq > 0.0))
+        return TOR_E_NOT_PD;
+    std::vector<tor_result> res(count);
+    std::vector<Mat *> ok;
+    std::vector<int> idx;
+    int first_err = TOR_OK;
+    for (int i = 0; i < count; i++) {
+        if (mats[i].status != TOR_OK) {
+            res[i] = tor_result{};
+            res[i].status = mats[i].status;
+            if (first_err == TOR_OK)
+                first_err = mats[i].status;
+            continue;
+        }
+        ok.push_back(&mats[i]);
+        idx.push_back(i);
+    }
+    if (!ok.empty()) {
+        rc = run_staged(ctx, ok, idx, -1, res.data(), nullptr, nullptr, end);
+        if (rc != TOR_OK && first_err == TOR_OK)
+            first_err = rc;
+    }
     for (int i = 0; i < count; i++) {
         probs[i] = res[i].status == TOR_OK ? (res[i].tor + res[i].tor_lo) * sq : NAN;
         if (results)
             results[i] = res[i];
     }
-    return rc;
+    return first_err;
 }
 
 int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long mask_begin,
                    unsigned long long mask_end, tor_result *out)
 {
-    if (!ctx || !out || n < 1 || n > 34 || mask_begin > mask_end || mask_end > (1ull << n))
+    if (!ctx || !out || n < 1 || n > 34 || mask_begin > mask_end || mask_end > (1ull << n) || !args_ok(ctx, n, O, ld))
         return TOR_E_INVAL;
     std::lock_guard<std::mutex> g(ctx->mu);
-    std::vector<double> tmp;
-    const double *host;
-    int rc = copy_input_to_host(n, O, ld, ctx->opt.flags, tmp, host);
-    Staged st;
-    if (rc == TOR_OK)  // the comparison kernels run on the complex matrix
-        rc = stage_matrix(n, host, ld, (ctx->opt.flags & ~(unsigned)TOR_FACTOR_DD) | TOR_FORCE_COMPLEX, 0, st);
+    // the comparison kernels run on the complex matrix, unpadded
+    std::vector<StageIn> in(1);
+    in[0].n = n;
+    in[0].O = O;
+    in[0].ld = ld;
+    std::vector<Mat> mats;
+    size_t end = 0;
+    const unsigned sfl = (stage_flags(ctx->opt.flags) & ~STAGE_DD) | STAGE_FORCE_CPLX;
+    int rc = stage_sync(ctx, in, (ctx->opt.flags & TOR_INPUT_DEVICE) != 0, sfl, 0, 0, mats, &end);
     if (rc != TOR_OK)
         return rc;
+    if (mats[0].status != TOR_OK)
+        return mats[0].status;
     const int chunk = 16;
-    const size_t bC = align_up(sizeof(c64) * st.packed.size(), 256);
     const int pgrid = ctx->grid[PATH_CPLX];
     const size_t bParts = align_up(sizeof(double) * 4 * pgrid, 256);
-    rc = ensure_ws(ctx, bC + 256 + bParts + 256);
+    rc = ensure_ws_keep(ctx, end + 256 + bParts + 256, end);
     if (rc != TOR_OK)
         return rc;
-    char *dC = ctx->ws;
-    unsigned long long *dCounter = (unsigned long long *)(dC + bC);
+    const char *dC = mat_ptr(ctx, mats[0]);
+    unsigned long long *dCounter = (unsigned long long *)(ctx->ws + end);
     double *dParts = (double *)((char *)dCounter + 256);
     double *dRes = (double *)((char *)dParts + bParts);
     hipError_t e = hipSetDevice(ctx->device);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(dC, st.packed.data(), sizeof(c64) * st.packed.size(), hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess)
         e = launch_zero(dCounter, 1, ctx->stream);
     PlainParams pp{};
@@ -1403,58 +1401,46 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long 
         return hip_status(e);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-    st.N = n;
-    fill_result(st, PATH_CPLX, h, ms, out);
+    fill_result(mats[0], PATH_CPLX, h, ms, out);
     out->subsets = mask_end - mask_begin;
     return out->status;
 }
 
 int tor_eval_removal(tor_ctx *ctx, int n, const double *O, long ld, tor_result *out)
 {
-    if (!ctx || !out || n < 0 || n > REMOVAL_MAX_N || n > ctx->opt.max_n)
+    if (!ctx || !out || n < 0 || n > REMOVAL_MAX_N || !args_ok(ctx, n, O, ld))
         return TOR_E_INVAL;
     std::lock_guard<std::mutex> g(ctx->mu);
-    std::vector<double> tmp;
-    const double *host;
-    int rc = copy_input_to_host(n, O, ld, ctx->opt.flags, tmp, host);
-    Staged st;
-    if (rc == TOR_OK)  // validation and the positive-definiteness check
-        rc = stage_matrix(n, host, ld, (ctx->opt.flags & ~(unsigned)TOR_FACTOR_DD) | TOR_FORCE_COMPLEX, 0, st);
-    if (rc != TOR_OK)
-        return rc;
     // I - O in the interleaved order a_0, a_0^dag, a_1, ... (the ordering of
     // Sec. 2), the Hermitian completion of its lower triangle, packed by rows
-    std::vector<c64> Ci((size_t)E(std::max(n, 1)), c64{0.0, 0.0});
-    for (int x = 0; x < 2 * n; x++)
-        for (int y = 0; y <= x; y++) {
-            const int bx = (x >> 1) + (x & 1) * n, by = (y >> 1) + (y & 1) * n;
-            const bool lower = bx >= by;
-            const int i = lower ? bx : by, j = lower ? by : bx;
-            const double orr = host[2 * ((size_t)i * ld + j)], oi = host[2 * ((size_t)i * ld + j) + 1];
-            c64 v{(i == j ? 1.0 : 0.0) - orr, i == j ? 0.0 : -oi};
-            if (!lower)
-                v.y = -v.y;
-            Ci[(size_t)pidx(x, y)] = v;
-        }
+    std::vector<StageIn> in(1);
+    in[0].n = n;
+    in[0].O = O;
+    in[0].ld = ld;
+    std::vector<Mat> mats;
+    size_t end = 0;
+    const unsigned sfl = (stage_flags(ctx->opt.flags) & STAGE_CHECK_HERM) | STAGE_INTERLEAVED;
+    int rc = stage_sync(ctx, in, (ctx->opt.flags & TOR_INPUT_DEVICE) != 0, sfl, 0, 0, mats, &end);
+    if (rc != TOR_OK)
+        return rc;
+    if (mats[0].status != TOR_OK)
+        return mats[0].status;
     const int grid = ctx->num_cu * MAX_FIT;
     int k = 0;
     while (k < n && (1ll << k) < 4ll * grid)
         ++k;
-    const size_t bC = align_up(sizeof(c64) * Ci.size(), 256);
     const size_t bParts = align_up(sizeof(double) * 4 * grid, 256);
     const long long stride = (long long)align_up(sizeof(c64) * (size_t)(n - k + 1) * (size_t)NSZ(n), 256);
     const size_t bScr = (size_t)stride * grid;
-    rc = ensure_ws(ctx, bC + 256 + bParts + 256 + bScr);
+    rc = ensure_ws_keep(ctx, end + 256 + bParts + 256 + bScr, end);
     if (rc != TOR_OK)
         return rc;
-    char *dC = ctx->ws;
-    unsigned long long *dCounter = (unsigned long long *)(dC + bC);
+    const char *dC = mat_ptr(ctx, mats[0]);
+    unsigned long long *dCounter = (unsigned long long *)(ctx->ws + end);
     double *dParts = (double *)((char *)dCounter + 256);
     double *dRes = (double *)((char *)dParts + bParts);
     char *dScr = (char *)dRes + 256;
     hipError_t e = hipSetDevice(ctx->device);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(dC, Ci.data(), sizeof(c64) * Ci.size(), hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess)
         e = launch_zero(dCounter, 1, ctx->stream);
     RemovalParams rp{};
@@ -1482,8 +1468,7 @@ int tor_eval_removal(tor_ctx *ctx, int n, const double *O, long ld, tor_result *
         return hip_status(e);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-    st.N = n;
-    fill_result(st, PATH_CPLX, h, ms, out);
+    fill_result(mats[0], PATH_CPLX, h, ms, out);
     return out->status;
 }
 
@@ -1512,29 +1497,29 @@ int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out)
 
 int tor_submit(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long *ticket)
 {
-    if (!ctx || !ticket)
+    if (!ctx || !ticket || !args_ok(ctx, n, O, ld))
         return TOR_E_INVAL;
-    if (n < 0 || n > ctx->opt.max_n)
-        return TOR_E_INVAL;
+    if (request_bytes(n, stage_flags(ctx->opt.flags)) > ctx->pool_bytes)
+        return TOR_E_NOMEM;
     Request *r = new (std::nothrow) Request();
     if (!r)
         return TOR_E_NOMEM;
-    std::vector<double> tmp;
-    const double *host;
-    int rc = copy_input_to_host(n, O, ld, ctx->opt.flags, tmp, host);
-    if (rc == TOR_OK)
-        rc = stage_matrix(n, host, ld, ctx->opt.flags, CPLX_R, r->st);
-    if (rc != TOR_OK) {
-        delete r;
-        return rc;
-    }
-    r->path = r->st.path;
-    r->N = modes_of(r->st, r->path);
-    r->k = std::min(std::max(r->N - path_R(r->path), 0), 20);  // largest split admission may choose
-    r->nroots = 1ll << r->k;
-    if (request_bytes(*r) > ctx->pool_bytes) {
-        delete r;
-        return TOR_E_NOMEM;
+    // a compact copy of the input; it is staged on the device at admission
+    const int n2 = 2 * n;
+    r->n = n;
+    r->raw.resize((size_t)n2 * n2 * 2);
+    if (n > 0) {
+        if (ctx->opt.flags & TOR_INPUT_DEVICE) {
+            hipError_t e = hipMemcpy2D(r->raw.data(), sizeof(c64) * n2, O, sizeof(c64) * (size_t)ld, sizeof(c64) * n2,
+                                       n2, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                delete r;
+                return hip_status(e);
+            }
+        } else {
+            for (int a = 0; a < n2; a++)
+                std::memcpy(r->raw.data() + 2 * (size_t)a * n2, O + 2 * (size_t)a * (size_t)ld, sizeof(c64) * n2);
+        }
     }
     {
         std::lock_guard<std::mutex> g(ctx->smu);

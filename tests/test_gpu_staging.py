@@ -1,0 +1,187 @@
+"""Device staging (tor_stage.hip): device-resident inputs read in place,
+validation, the structure test, and positive definiteness reported by the
+kernels' own pivot test.
+
+A device input and the same matrix given from host memory are staged by the
+same kernel into the same form, so every result must agree bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2109_04528_amd import inputs as gen
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(O):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(O, dtype=np.complex128)).to("cuda:0")
+    torch.cuda.synchronize()
+    return t
+
+
+def same(a, b):
+    return (a.tor, a.tor_lo, a.sum_abs, a.path, a.status) == (b.tor, b.tor_lo, b.sum_abs, b.path, b.status)
+
+
+def same_value(a, b):
+    # the double-double sum of the terms is exact, but the FP64 sum of |t|
+    # depends on the order, which serving (its own split) and the comparison
+    # kernels (roots handed to waves as they come) do not fix
+    return (a.tor, a.tor_lo, a.path, a.status) == (b.tor, b.tor_lo, b.path, b.status)
+
+
+def kappa(O):
+    C = np.eye(O.shape[0]) - O
+    C = np.tril(C) + np.tril(C, -1).conj().T
+    w = np.linalg.eigvalsh(C)
+    return float(w[-1] / w[0])
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    from paper_2109_04528_amd import Context, TOR_INPUT_DEVICE
+    h = Context(device=0)
+    d = Context(device=0, flags=TOR_INPUT_DEVICE)
+    yield h, d
+    h.close()
+    d.close()
+
+
+def test_device_input_eval_and_batch(ctxs):
+    h, d = ctxs
+    mats = [gen.random_O(14, 31, 0.3, 1.2, 0.9), gen.random_hpd_O(10, 32), gen.vacuum_O(0),
+            gen.random_O(3, 33, 0.5, 1.0, 0.7)]
+    say("case device input eval/batch")
+    for O in mats:
+        a, b = h.eval(O), d.eval(dev(O))
+        say(f"  n={O.shape[0] // 2} path={a.path} host={a.value!r} device={b.value!r}")
+        assert same(a, b)
+    ra = h.eval_batch(mats)
+    rb = d.eval_batch([dev(O) for O in mats])
+    assert all(same(x, y) for x, y in zip(ra, rb))
+
+
+def test_device_input_strided(ctxs):
+    _, d = ctxs
+    import torch
+    O = gen.random_O(9, 34, 0.3, 1.2, 0.9)
+    big = torch.zeros((30, 30), dtype=torch.complex128, device="cuda:0")
+    big[:18, :18] = torch.from_numpy(O).to("cuda:0")
+    big[:18, 18:] = float("nan")  # outside the matrix: never read
+    torch.cuda.synchronize()
+    view = big[:18, :18]
+    assert view.stride(0) == 30
+    say("case strided device input n=9, ld=30")
+    a, b = d.eval(view), d.eval(dev(O))
+    assert same(a, b)
+
+
+def test_device_input_other_entry_points(ctxs):
+    h, d = ctxs
+    O = gen.random_O(10, 35, 0.5, 1.0, 0.7)
+    say("case device input partials/plain/removal/click/submit")
+    ka, pa, ra = h.eval_partials(O, 6)
+    kb, pb, rb = d.eval_partials(dev(O), 6)
+    assert ka == kb and np.array_equal(pa, pb) and same(ra, rb)
+    assert same_value(h.eval_plain(O, 3, 900), d.eval_plain(dev(O), 3, 900))
+    assert same_value(h.eval_removal(O), d.eval_removal(dev(O)))
+    S = gen.random_O(12, 36, 0.5, 1.0, 0.7)
+    pats = [0, 0b101, 0b111100001111, (1 << 12) - 1]
+    p1, r1 = h.click_probs(S, pats)
+    p2, r2 = d.click_probs(dev(S), pats)
+    assert np.array_equal(p1, p2) and all(same(x, y) for x, y in zip(r1, r2))
+    t = d.submit(dev(O))
+    d.drain(60000)
+    r = d.poll(t)
+    assert same_value(r, h.eval(O))
+
+
+def test_only_the_lower_triangle_is_read(ctxs):
+    from paper_2109_04528_amd import Context, TOR_CHECK_HERMITIAN, TOR_E_INVAL, TorError
+    h, _ = ctxs
+    O = gen.random_O(8, 37, 0.3, 1.2, 0.9)
+    junk = O.copy()
+    iu = np.triu_indices(16, 1)
+    junk[iu] = 7.0 + 3.0j
+    junk[0, 5] = np.nan
+    say("case lower triangle only / TOR_CHECK_HERMITIAN")
+    assert same(h.eval(O), h.eval(junk))
+    with Context(device=0, flags=TOR_CHECK_HERMITIAN) as c:
+        assert same(c.eval(O), h.eval(O))
+        with pytest.raises(TorError) as ei:
+            c.eval(junk)
+        assert ei.value.code == TOR_E_INVAL
+        off = O.copy()
+        off[1, 9] += 1e-9  # breaks Hermiticity beyond 1e-12
+        with pytest.raises(TorError) as ei:
+            c.eval(off)
+        assert ei.value.code == TOR_E_INVAL
+
+
+def test_structure_tolerance(ctxs):
+    h, _ = ctxs
+    O = gen.random_O(12, 38, 0.3, 1.2, 0.9)
+    n = 12
+    say("case structure test tolerance")
+    # a change far below 64 ulp of max|C| keeps the real path; one far above
+    # it (the lower-right block no longer conj of the upper-left) does not
+    tiny, big = O.copy(), O.copy()
+    tiny[n + 3, n + 1] += 1e-18
+    tiny[n + 1, n + 3] += 1e-18
+    big[n + 3, n + 1] += 1e-9
+    big[n + 1, n + 3] += 1e-9
+    rt, rb = h.eval(tiny), h.eval(big)
+    assert rt.path == 1 and rb.path == 2
+    q = orc.tor(O, mode=orc.QUAD)
+    assert abs(rt.value - q.value) <= 8.0 * n * kappa(O) * U * q.sum_abs
+
+
+def test_not_positive_definite_from_the_kernels(ctxs):
+    from paper_2109_04528_amd import TOR_E_NOT_PD, TOR_OK, TorError
+    h, _ = ctxs
+    good = gen.random_O(9, 39, 0.3, 1.2, 0.9)
+    bad_real = gen.random_O(9, 40, 0.3, 1.2, 0.9) + 2.0 * np.eye(18)  # structured, C = -I - O'
+    bad_cplx = np.eye(14, dtype=np.complex128) * 1.5
+    bad_cplx[3, 2] = 0.2 + 0.1j  # no Gaussian-state structure
+    say("case NOT_PD: batch with one bad matrix, and each path")
+    rs = h.eval_batch([good, bad_real, bad_cplx, good], check=False)
+    assert [r.status for r in rs] == [TOR_OK, TOR_E_NOT_PD, TOR_E_NOT_PD, TOR_OK]
+    assert same_value(rs[0], h.eval(good)) and same(rs[3], rs[0])
+    with pytest.raises(TorError) as ei:
+        h.eval_batch([good, bad_real])
+    assert ei.value.code == TOR_E_NOT_PD
+    # barely positive definite stays valid: I - O = c I on the real path,
+    # Tor = (1/c - 1)^n (each mode contributes 1/sqrt(c^2) - 1)
+    O = np.eye(18, dtype=np.complex128) * (1.0 - 1e-6)
+    c = 1.0 - (1.0 - 1e-6)
+    r = h.eval(O)
+    n = 9
+    assert r.status == TOR_OK and r.path == 1
+    want = (1.0 / c - 1.0) ** n
+    assert abs(r.value - want) <= 1e-13 * want
+
+
+def test_serving_reports_staging_errors():
+    from paper_2109_04528_amd import Context, TOR_E_INVAL, TOR_E_NOT_PD
+    O = gen.random_O(8, 41, 0.3, 1.2, 0.9)
+    nanO = O.copy()
+    nanO[5, 2] = np.nan
+    badO = O + 2.0 * np.eye(16)
+    say("case serving: a NaN input and a non-PD input among good ones")
+    with Context(device=0) as c:
+        ts = [c.submit(x) for x in (O, nanO, badO, O)]
+        c.drain(60000)
+        rs = [c.poll(t) for t in ts]
+        ref = c.eval(O)
+    assert rs[1].status == TOR_E_INVAL and rs[2].status == TOR_E_NOT_PD
+    assert same_value(rs[0], ref) and same_value(rs[3], ref)
