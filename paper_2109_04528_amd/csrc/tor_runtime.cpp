@@ -347,6 +347,13 @@ int stage_enqueue(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, 
     int *hsel = (int *)(h + b_desc + b_info);
     size_t sel_at = 0;
     std::vector<char> copied(L.raw_src.size(), 0);
+    struct RawCopy {
+        char *dst;
+        const double *src;
+        long ld;
+        int rows;
+    };
+    std::vector<RawCopy> copies;
     for (int i = 0; i < count; i++) {
         const StageIn &x = in[i];
         StageDesc d{};
@@ -363,14 +370,11 @@ int stage_enqueue(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, 
         }
         const int rows = 2 * d.M;
         if (rows > 0 && !on_device) {
-            char *dst = h + b_desc + b_info + b_sel + raw_off[i];
             size_t si = 0;
             while (L.raw_src[si] != x.O)
                 ++si;
             if (!copied[si]) {
-                for (int r = 0; r < rows; r++)
-                    std::memcpy(dst + sizeof(c64) * (size_t)r * rows, x.O + 2 * (size_t)r * (size_t)x.ld,
-                                sizeof(c64) * (size_t)rows);
+                copies.push_back(RawCopy{h + b_desc + b_info + b_sel + raw_off[i], x.O, x.ld, rows});
                 copied[si] = 1;
             }
             d.O = (const double *)(dbase + b_desc + b_info + b_sel + raw_off[i]);
@@ -383,6 +387,28 @@ int stage_enqueue(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, 
         mats[i].n = x.n;
         mats[i].pool = x.dst;
         mats[i].ws_off = x.dst ? 0 : base + out_off[i];
+    }
+    // compact the host inputs into the pinned image, on a few threads for a
+    // large batch
+    auto do_copies = [&](size_t first, size_t step) {
+        for (size_t c = first; c < copies.size(); c += step) {
+            const RawCopy &rc_ = copies[c];
+            for (int r = 0; r < rc_.rows; r++)
+                std::memcpy(rc_.dst + sizeof(c64) * (size_t)r * rc_.rows, rc_.src + 2 * (size_t)r * (size_t)rc_.ld,
+                            sizeof(c64) * (size_t)rc_.rows);
+        }
+    };
+    const size_t nthr = L.b_raw > ((size_t)4 << 20) && copies.size() >= 16
+                            ? std::min<size_t>(8, std::max(1u, std::thread::hardware_concurrency()))
+                            : 1;
+    if (nthr <= 1) {
+        do_copies(0, 1);
+    } else {
+        std::vector<std::thread> pool;
+        for (size_t t = 0; t < nthr; t++)
+            pool.emplace_back(do_copies, t, nthr);
+        for (auto &th : pool)
+            th.join();
     }
     hipError_t e = hipSetDevice(ctx->device);
     // the infos' bytes are part of the copy (their values do not matter)
