@@ -205,10 +205,12 @@ def main():
     O_dev = torch.from_numpy(O).to(dev)
     torch.cuda.synchronize()
     dctx = Context(device=0, stream=stream, workspace=ws, flags=TOR_INPUT_DEVICE)
+    # the collector runs before the warm-up: a pause between warm-up and the
+    # timed steps would let the GPU clocks fall again
+    gc.collect()
     for _ in range(args.warmup):
         dctx.eval(O_dev)
     torch.cuda.synchronize()
-    gc.collect()
     kms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -247,12 +249,12 @@ def main():
     batch = None
     if args.batch > 0:
         ns, mats = inputs.batch_mix(args.batch, 12, 26, seed=4)
-        ctx.eval_batch(mats)  # sizes the workspace and staging buffers
-        torch.cuda.synchronize()
         # median of three calls, with Python's collector run beforehand (a
         # collection pause inside one call is the interpreter's, not the
-        # library's)
+        # library's), after one call that sizes the workspace and buffers
         gc.collect()
+        ctx.eval_batch(mats)
+        torch.cuda.synchronize()
         calls = []
         for _ in range(3):
             t0 = time.perf_counter()

@@ -50,19 +50,23 @@ __device__ inline void tri_ab(int t, int &a, int &b)
     b = t - a * (a + 1) / 2;
 }
 
-// the input seen as a 2n x 2n matrix
+// the input seen as a 2n x 2n matrix; with lds set, its lower triangle is
+// read from there (packed by rows, pidx) instead of global memory
 struct View {
     const double *O;
     long ld;
     int n;
     const int *sel;
     int M;
+    const c64 *lds;
     __device__ int row(int a) const { return sel ? (a < n ? sel[a] : sel[a - n] + M) : a; }
-    __device__ c64 o(int a, int b) const
+    __device__ c64 og(int a, int b) const
     {
         const double *p = O + 2 * ((size_t)row(a) * (size_t)ld + (size_t)row(b));
         return c64{p[0], p[1]};
     }
+    // entry (a, b), a >= b, of O
+    __device__ c64 o(int a, int b) const { return lds ? lds[pidx(a, b)] : og(a, b); }
     // C = I - O, Hermitian completion of the lower triangle
     __device__ c64 c(int a, int b) const
     {
@@ -167,37 +171,49 @@ __device__ inline double block_max(double v, double *red)
 
 }  // namespace
 
+// lower-triangle entries staged in LDS: inputs up to n = 40 (51.8 KB);
+// larger ones are read from global memory throughout
+constexpr int STAGE_LDS_ENTRIES = NB(80);
+
 template <int NT>
 __global__ void __launch_bounds__(NT) tor_stage(const StageDesc *descs)
 {
     __shared__ double red[NT / 64];
+    __shared__ c64 tri[STAGE_LDS_ENTRIES];
     const StageDesc D = descs[blockIdx.x];
     const int t = threadIdx.x;
     const int n = D.n, n2 = 2 * n;
-    const View v{D.O, D.ld, n, D.sel, D.M};
+    const bool in_lds = NB(n2) <= STAGE_LDS_ENTRIES;
+    View v{D.O, D.ld, n, D.sel, D.M, nullptr};
     const unsigned fl = D.flags;
 
-    // validation and the quantities of the structure test (a NaN fails every
-    // comparison below, so it is caught by the finite test alone)
+    // one pass over global memory: validation, max |C|, the Hermitian check,
+    // and the lower triangle of O into LDS (a NaN fails every comparison
+    // below, so it is caught by the finite test alone)
     double nonfin = 0.0, cmax2 = 0.0, dev2 = 0.0, hs2 = 0.0, hd2 = 0.0;
     const bool herm = (fl & STAGE_CHECK_HERM) != 0;
     for (int q = t; q < n2 * n2; q += NT) {
         const int a = q / n2, b = q - a * n2;
+        if (a < b && !herm)
+            continue;
+        const c64 x = v.og(a, b);
+        if (!isfinite(x.x) || !isfinite(x.y))
+            nonfin = 1.0;
         if (a >= b) {
-            const c64 x = v.o(a, b);
-            if (!isfinite(x.x) || !isfinite(x.y))
-                nonfin = 1.0;
-            const c64 y = v.c(a, b);
+            const c64 y = a == b ? c64{1.0 - x.x, 0.0} : c64{-x.x, -x.y};
             cmax2 = fmax(cmax2, sq(y.x, y.y));
+            if (in_lds)
+                tri[pidx(a, b)] = x;
         }
         if (herm) {
-            const c64 x = v.o(a, b), y = v.o(b, a);
-            if (!isfinite(x.x) || !isfinite(x.y))
-                nonfin = 1.0;
+            const c64 y = v.og(b, a);
             hs2 = fmax(hs2, sq(x.x, x.y));
             hd2 = fmax(hd2, sq(x.x - y.x, x.y + y.y));
         }
     }
+    __syncthreads();
+    if (in_lds)
+        v.lds = tri;
     const bool interleaved = (fl & STAGE_INTERLEAVED) != 0;
     const bool dd = (fl & STAGE_DD) != 0;
     const bool want_real = !interleaved && (dd || (n > 0 && !(fl & STAGE_FORCE_CPLX)));
@@ -323,7 +339,7 @@ __global__ void __launch_bounds__(NT) tor_sqrt_det(const double *O, long ld, int
     }
 }
 
-constexpr int STAGE_THREADS = 256;
+constexpr int STAGE_THREADS = 1024;
 constexpr int DET_THREADS = 1024;
 
 hipError_t launch_stage(const StageDesc *descs, int count, hipStream_t s)

@@ -1,5 +1,6 @@
-"""The largest sizes: n = 34 (the serving stream's largest request) and
-n = 40 (the default max_n).
+"""The largest sizes: n = 34 (the serving stream's largest request),
+n = 40 (the default max_n) and n = 41 (staged from global memory: the
+staging kernel keeps inputs up to n = 40 in LDS).
 
 At n = 34 the precision workload's cancellation is R ~ 1.5e20, so an FP64
 factor leaves ~u R / sqrt(2^n) ~ 0.1 relative: only the double-double factor
@@ -85,4 +86,24 @@ def test_n40_fp64_subtrees_against_oracle():
         b = 2 * 8.0 * 40 * kap * U * q.sum_abs
         say(f"  root {root}: gpu={got!r} oracle={q.value!r} diff={abs(got - q.value):.3e} bound={b:.3e}")
         assert q.count == 1 << (40 - k)
+        assert abs(got - q.value) <= b
+
+
+def test_n41_staged_from_global_memory():
+    from paper_2109_04528_amd import Context
+    O = gen.random_O(41, 2, 0.5, 1.0, 0.7)
+    say("case n=41 partials (staging without LDS)")
+    with Context(device=0, max_n=41) as c:
+        k, parts, res = c.eval_partials(O, 21)
+    say(f"  k={k} tor={res.value!r} R={res.cancellation:.3e} ms={res.device_ms:.1f} path={res.path}")
+    assert k == 21 and res.status == 0 and res.path == 1
+    hi, lo = dd_sum(parts)
+    assert abs((hi + lo) - res.value) <= 1e-12 * res.sum_abs
+    kap = kappa(O)
+    for root in [0x0F0F0F, 0x1FFFFF]:
+        q = orc.tor(O, mode=orc.F64, fix_mask=(1 << k) - 1, fix_val=root)
+        got = parts[root, 0] + parts[root, 1]
+        b = 2 * 8.0 * 41 * kap * U * q.sum_abs
+        say(f"  root {root}: gpu={got!r} oracle={q.value!r} diff={abs(got - q.value):.3e} bound={b:.3e}")
+        assert q.count == 1 << (41 - k)
         assert abs(got - q.value) <= b
