@@ -172,6 +172,8 @@ def main():
                     help="also time the same n=30 Torontonian with the double-double factor")
     ap.add_argument("--profile-traffic", action="store_true",
                     help="one n=30 Torontonian and one 256 MiB device copy, for the HBM counters")
+    ap.add_argument("--force-complex", action="store_true",
+                    help="time the headline on the complex path (TOR_FORCE_COMPLEX), for its profile")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -181,7 +183,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2109_04528_amd import TOR_INPUT_DEVICE, Context, inputs, workspace_size
+    from paper_2109_04528_amd import TOR_FORCE_COMPLEX, TOR_INPUT_DEVICE, Context, inputs, workspace_size
     from paper_2109_04528_amd.flops import tor_flops
 
     n = args.n
@@ -204,7 +206,8 @@ def main():
     # reads it in place
     O_dev = torch.from_numpy(O).to(dev)
     torch.cuda.synchronize()
-    dctx = Context(device=0, stream=stream, workspace=ws, flags=TOR_INPUT_DEVICE)
+    path_flags = TOR_FORCE_COMPLEX if args.force_complex else 0
+    dctx = Context(device=0, stream=stream, workspace=ws, flags=TOR_INPUT_DEVICE | path_flags)
     # the collector runs before the warm-up: a pause between warm-up and the
     # timed steps would let the GPU clocks fall again
     gc.collect()
@@ -222,7 +225,7 @@ def main():
     step_s = (t1 - t0) / args.steps
     dctx.close()
     # the same step from a host matrix (its PCIe copy included), for context
-    ctx = Context(device=0, stream=stream, workspace=ws)
+    ctx = Context(device=0, stream=stream, workspace=ws, flags=path_flags)
     ctx.eval(O)
     torch.cuda.synchronize()
     th = time.perf_counter()
@@ -278,7 +281,6 @@ def main():
 
     compare = None
     if args.compare:
-        from paper_2109_04528_amd import TOR_FORCE_COMPLEX
         from paper_2109_04528_amd.flops import removal_flops
         O24 = inputs.random_O(24, 0, 0.5, 1.0, 0.7)
         ctx.eval(O24)
