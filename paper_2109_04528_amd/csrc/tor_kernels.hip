@@ -175,6 +175,17 @@ __device__ void elim_global(const S *__restrict__ src, int snb, S *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// node_place for every stored node, evaluated at compile time
+template <int R, int BL, int ESZ>
+struct NodePlacement {
+    int off[(1 << BL) + 1];
+    constexpr NodePlacement() : off{}
+    {
+        for (int t = 0; t <= (1 << BL); ++t)
+            off[t] = node_place(R, BL, ESZ, t);
+    }
+};
+
 // tier B tables, built once per wave: for the node of level jl with id i
 // (bit jl-1-m of i = decision on the m-th mode below the tier-A leaf, 1 =
 // include; stored at (2^jl - 1) + i) the LDS offset of the stored node it
@@ -186,6 +197,7 @@ __device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcNB, u
                                              int lane)
 {
     constexpr int esz = (int)sizeof(S);
+    static constexpr NodePlacement<R, B - 1, esz> place{};
     for (int t = lane; t < (1 << B) - 1; t += 64) {
         int jl = 31 - __clz(t + 1);
         int i = t + 1 - (1 << jl);
@@ -197,7 +209,7 @@ __device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcNB, u
             int tz = __builtin_ctz(i);
             int lev = jl - tz;
             int idx = (i >> tz) >> 1;
-            srcOff[t] = (uint16_t)(node_place(R, B - 1, esz, (1 << (lev - 1)) + idx) / esz);
+            srcOff[t] = (uint16_t)(place.off[(1 << (lev - 1)) + idx] / esz);
             srcNB[t] = (uint8_t)NB(R - lev);
             srcDet[t] = (uint8_t)((1 << (lev - 1)) - 1 + idx);
         }
