@@ -113,9 +113,10 @@ __device__ __forceinline__ Piv<S> node_pivot(const S *node, int nb, int m)
 }
 
 template <class S>
-__device__ __forceinline__ void elim_block(const S *node, int nb, int m, int a, int b, const Piv<S> &pv, S *o)
+__device__ __forceinline__ void elim_block(const S *node, int nb, int m, int a, int b, int ih, const Piv<S> &pv,
+                                           S *o)
 {
-    const int ia = bidx(m, a), ib = bidx(m, b), ih = bidx(a, b);
+    const int ia = bidx(m, a), ib = bidx(m, b);
     const S ra0 = blk(node, nb, ia, 0), ra1 = blk(node, nb, ia, 1);
     const S qa0 = sub_mul(blk(node, nb, ia, 2), ra0, pv.ba), qa1 = sub_mul(blk(node, nb, ia, 3), ra1, pv.ba);
     const S rb0 = blk(node, nb, ib, 0), rb1 = blk(node, nb, ib, 1);
@@ -165,7 +166,7 @@ __device__ void elim_global(const S *__restrict__ src, int snb, S *__restrict__ 
         int a, b;
         block_ab(bi, a, b);
         S o[4];
-        elim_block(src, snb, m, a, b, pv, o);
+        elim_block(src, snb, m, a, b, bidx(a, b), pv, o);
         if (dst)
             put_block(dst, NB(m), bi, o);
         if (lds && bi < nlds)
@@ -186,38 +187,62 @@ struct NodePlacement {
     }
 };
 
-// tier B tables, built once per wave: for the node of level jl with id i
-// (bit jl-1-m of i = decision on the m-th mode below the tier-A leaf, 1 =
-// include; stored at (2^jl - 1) + i) the LDS offset of the stored node it
-// is a view of, that node's blocks per granule array, and the slot of its
-// determinant (0xff: the tier-A leaf).  The include node (lev, idx) keeps its
-// determinant at (2^(lev-1) - 1) + idx.
+// View t of the tier-B tables: for the node of level jl with id i (bit
+// jl-1-m of i = decision on the m-th mode below the tier-A leaf, 1 =
+// include; t = (2^jl - 1) + i) the LDS offset of the stored node it is a
+// view of, that node's blocks per granule array, and the slot of its
+// determinant (0xff: the tier-A leaf).  The include node (lev, idx) keeps
+// its determinant at (2^(lev-1) - 1) + idx.
+template <int R, int B, int ESZ>
+__device__ __forceinline__ void view_entry(int t, int &off, int &nb, int &det)
+{
+    static constexpr NodePlacement<R, B - 1, ESZ> place{};
+    const int jl = 31 - __clz(t + 1);
+    const int i = t + 1 - (1 << jl);
+    if (i == 0) {
+        off = 0;
+        nb = NB(R);
+        det = 0xff;
+    } else {
+        const int tz = __builtin_ctz(i);
+        const int lev = jl - tz;
+        const int idx = (i >> tz) >> 1;
+        off = place.off[(1 << (lev - 1)) + idx] / ESZ;
+        nb = NB(R - lev);
+        det = (1 << (lev - 1)) - 1 + idx;
+    }
+}
+
+// tier B tables, built once per wave: the view entries above; per include
+// node i of level J (record (2^(J-1) - 1) + i) its parent's stored offset
+// and blocks per array and its own stored offset, packed in 64 bits; per
+// block bi of a child (a, b) and its block index bidx(a, b) packed.
 template <class S, int R, int B>
-__device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcNB, uint8_t *srcDet, uint16_t *blkAB,
-                                             int lane)
+__device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcNB, uint8_t *srcDet,
+                                             unsigned long long *nodeRec, uint32_t *blkRec, int lane)
 {
     constexpr int esz = (int)sizeof(S);
-    static constexpr NodePlacement<R, B - 1, esz> place{};
     for (int t = lane; t < (1 << B) - 1; t += 64) {
-        int jl = 31 - __clz(t + 1);
-        int i = t + 1 - (1 << jl);
-        if (i == 0) {
-            srcOff[t] = 0;
-            srcNB[t] = (uint8_t)NB(R);
-            srcDet[t] = 0xff;
-        } else {
-            int tz = __builtin_ctz(i);
-            int lev = jl - tz;
-            int idx = (i >> tz) >> 1;
-            srcOff[t] = (uint16_t)(place.off[(1 << (lev - 1)) + idx] / esz);
-            srcNB[t] = (uint8_t)NB(R - lev);
-            srcDet[t] = (uint8_t)((1 << (lev - 1)) - 1 + idx);
-        }
+        int off, nb, det;
+        view_entry<R, B, esz>(t, off, nb, det);
+        srcOff[t] = (uint16_t)off;
+        srcNB[t] = (uint8_t)nb;
+        srcDet[t] = (uint8_t)det;
+    }
+    // include nodes of levels 1..B-1 (their children are views of level B-1
+    // at most)
+    for (int t = lane; t < (1 << (B - 1)) - 1; t += 64) {
+        const int J = 32 - __clz(t + 1);  // t = (2^(J-1) - 1) + i
+        const int i = t + 1 - (1 << (J - 1));
+        int poff, pnb, pdet, coff, cnb, cdet;
+        view_entry<R, B, esz>(t, poff, pnb, pdet);
+        view_entry<R, B, esz>((1 << J) + 2 * i, coff, cnb, cdet);
+        nodeRec[t] = (unsigned long long)poff | ((unsigned long long)pnb << 16) | ((unsigned long long)coff << 32);
     }
     for (int bi = lane; bi < NB(R - 1); bi += 64) {
         int a, b;
         block_ab(bi, a, b);
-        blkAB[bi] = (uint16_t)(a | (b << 8));
+        blkRec[bi] = (uint32_t)(bidx(a, b) | (a << 16) | (b << 24));
     }
 }
 
@@ -228,7 +253,8 @@ struct TierB {
     const uint16_t *srcOff; // per view: offset of its stored node
     const uint8_t *srcNB;   // per view: blocks per granule array of that node
     const uint8_t *srcDet;  // per view: determinant slot (0xff: tier-A leaf)
-    const uint16_t *blkAB;  // block index -> a | b << 8
+    const unsigned long long *nodeRec;  // per include node: parent offset | nb << 16 | own offset << 32
+    const uint32_t *blkRec;             // block index -> bidx(a, b) | a << 16 | b << 24
     RT<S> *nInv;            // per include node of a level: 1/alpha, 1/gamma1
     S *nBa;                 // per include node of a level: beta/alpha
     RT<S> *ndet;            // per include node: running determinant
@@ -259,17 +285,18 @@ __device__ __forceinline__ void tierB_level(const TierB<S> &tb, RT<S> leafDet, i
         const int it = it0 + lane;
         if (it < NN * NBO) {
             const int i = it / NBO, bi = it - i * NBO;
-            const int ab = tb.blkAB[bi];
-            const S *par = tb.buf + tb.srcOff[NN - 1 + i];
-            const int pnb = tb.srcNB[NN - 1 + i];
+            const unsigned long long rec = tb.nodeRec[NN - 1 + i];
+            const uint32_t br = tb.blkRec[bi];
+            const S *par = tb.buf + (int)(rec & 0xffffu);
+            const int pnb = (int)((rec >> 16) & 0xffu);
             Piv<S> pq;
             pq.inv_a = tb.nInv[2 * i];
             pq.inv_g = tb.nInv[2 * i + 1];
             pq.ba = tb.nBa[i];
             S o[4];
-            elim_block(par, pnb, m, ab & 0xff, ab >> 8, pq, o);
+            elim_block(par, pnb, m, (int)((br >> 16) & 0xffu), (int)(br >> 24), (int)(br & 0xffffu), pq, o);
             // the include child i of level J is view 2i+1 of that level
-            put_block(tb.buf + tb.srcOff[(1 << J) + 2 * i], NBO, bi, o);
+            put_block(tb.buf + (int)(rec >> 32), NBO, bi, o);
         }
     }
     __syncthreads();
@@ -467,14 +494,15 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
     __shared__ uint16_t srcOff[(1 << (BL + 1)) - 1];
     __shared__ uint8_t srcNB[(1 << (BL + 1)) - 1];
     __shared__ uint8_t srcDet[(1 << (BL + 1)) - 1];
-    __shared__ uint16_t blkAB[NB(R - 1)];
+    __shared__ uint32_t blkRec[NB(R - 1)];
+    __shared__ unsigned long long nodeRec[(1 << BL) - 1];
     __shared__ RT<S> sdet[MAX_N + 1];
     __shared__ int sinc[MAX_N + 1];
 
     const int lane = threadIdx.x;
-    build_tables<S, R, BL + 1>(srcOff, srcNB, srcDet, blkAB, lane);
+    build_tables<S, R, BL + 1>(srcOff, srcNB, srcDet, nodeRec, blkRec, lane);
     __syncthreads();
-    const TierB<S> tb{bufB, srcOff, srcNB, srcDet, blkAB, nInv, nBa, ndet};
+    const TierB<S> tb{bufB, srcOff, srcNB, srcDet, nodeRec, blkRec, nInv, nBa, ndet};
     S *wscr = reinterpret_cast<S *>(prm.scratch + (long long)blockIdx.x * prm.scratch_stride);
 
     for (;;) {
