@@ -25,12 +25,13 @@
  *  * Every value read must be finite (else TOR_E_INVAL).  Staging runs on the
  *    GPU: a kernel validates the values, forms I - O, detects the
  *    Gaussian-state block structure and packs the matrix for its kernel.
- *  * I - O must be Hermitian positive definite.  The kernels test the pivots
- *    of every subset they factorise; the full I - O is one of them, and every
- *    principal submatrix of an HPD matrix is HPD (Cauchy interlacing), so a
- *    failed pivot anywhere means I - O is not (numerically) positive
- *    definite: the result's status is TOR_E_NOT_PD.  The paper takes |det| in
- *    Eq. 2; for HPD input det > 0 and the two agree.
+ *  * I - O must be Hermitian positive definite.  The recursive kernels test
+ *    every 2x2 pivot of the factorisation of I - O itself (the all-include
+ *    subset): all of them positive is the block form of Sylvester's
+ *    criterion, and every principal submatrix of an HPD matrix is HPD
+ *    (Cauchy interlacing).  A failed pivot makes the result's status
+ *    TOR_E_NOT_PD.  The paper takes |det| in Eq. 2; for HPD input det > 0
+ *    and the two agree.
  *  * n = 0 gives Tor = 1 (the empty subset only).
  *  * Unless TOR_INPUT_DEVICE is set, O is a host pointer and is copied to the
  *    device as it is; with TOR_INPUT_DEVICE it is device memory, read in
@@ -56,9 +57,10 @@ extern "C" {
 #define TOR_OK 0
 #define TOR_PENDING 1          /* tor_poll: the request is still running            */
 #define TOR_E_INVAL (-1)       /* null pointer, n < 0, n > max_n, ld < 2n, NaN/Inf  */
-#define TOR_E_NOT_PD (-2)      /* I - O is not Hermitian positive definite (a pivot
-                                  <= 0 or NaN in some subset)                       */
-#define TOR_E_NUMERIC (-3)     /* a non-finite result with every pivot positive     */
+#define TOR_E_NOT_PD (-2)      /* I - O is not Hermitian positive definite (a
+                                  tested pivot <= 0 or NaN)                         */
+#define TOR_E_NUMERIC (-3)     /* a non-finite result with every tested pivot
+                                  positive                                          */
 #define TOR_E_BUSY (-4)        /* admission refused: serving queue is full          */
 #define TOR_E_NOMEM (-5)       /* device or host allocation failed                  */
 #define TOR_E_DEVICE (-6)      /* no usable GPU, or a HIP runtime error             */

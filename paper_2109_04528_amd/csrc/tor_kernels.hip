@@ -351,8 +351,6 @@ __device__ __forceinline__ void tail(const S *h, RT<S> det, Acc &acc, int &bad)
         const S b = h[1];
         const RT<S> g = re(h[2]);
         const RT<S> pd = det_last(a, b, g);  // det of the last 2x2 block
-        if (!is_pos(a) || !is_pos(pd))
-            bad = 1;
         acc.template add_pair<SG>(rsqrt_nr(det), rsqrt_nr(rmul(det, pd)));
     } else {
         tail<S, M - 1, -SG, Acc>(h, det, acc, bad);  // exclude the next mode
@@ -361,11 +359,34 @@ __device__ __forceinline__ void tail(const S *h, RT<S> det, Acc &acc, int &bad)
         const S b = h[pidx(p + 1, p)];
         const RT<S> g = re(h[pidx(p + 1, p + 1)]);
         const Piv<S> pq = pivot(a, b, g);
+        S hn[E(M - 1)];
+        elim_regs<S, M>(h, pq, hn);
+        tail<S, M - 1, SG, Acc>(hn, rmul(det, pq.pdet), acc, bad);
+    }
+}
+
+// The include chain of a register-resident node of M modes: its 2x2 pivots
+// in turn, each tested (alpha > 0, alpha gamma1 > 0), down to the last mode.
+// Run on the lane that holds the all-include subset, this completes the test
+// of every pivot of the factorisation of I - O itself: positive definiteness
+// of I - O is equivalent to all of them passing (the block form of
+// Sylvester's criterion), and it implies it for every other subset.
+template <class S, int M>
+__device__ __forceinline__ void include_chain_test(const S *h, int &bad)
+{
+    if constexpr (M == 1) {
+        const RT<S> a = re(h[0]);
+        if (!is_pos(a) || !is_pos(det_last(a, h[1], re(h[2]))))
+            bad = 1;
+    } else if constexpr (M > 1) {
+        constexpr int p = 2 * M - 2;
+        const RT<S> a = re(h[pidx(p, p)]);
+        const Piv<S> pq = pivot(a, h[pidx(p + 1, p)], re(h[pidx(p + 1, p + 1)]));
         if (!is_pos(a) || !is_pos(pq.pdet))
             bad = 1;
         S hn[E(M - 1)];
         elim_regs<S, M>(h, pq, hn);
-        tail<S, M - 1, SG, Acc>(hn, rmul(det, pq.pdet), acc, bad);
+        include_chain_test<S, M - 1>(hn, bad);
     }
 }
 
@@ -404,7 +425,7 @@ __device__ __forceinline__ Piv<S> lane_pivot(RT<S> a, S b, RT<S> g, bool inc, in
 // the T-mode result are held in registers.
 template <class S, int T, int B, int L, class Acc>
 __device__ __forceinline__ void tierC(const TierB<S> &tb, RT<S> leafDet, int leafInc, int N, int lane, Acc &acc,
-                                      int &bad)
+                                      int &bad, bool full_leaf)
 {
     static_assert(L == 1 || L == 2, "one or two lane levels");
     constexpr int NP = (1 << (B - L)) - 1;  // table base of level B-L
@@ -477,6 +498,8 @@ __device__ __forceinline__ void tierC(const TierB<S> &tb, RT<S> leafDet, int lea
     }
     const int excluded = (N - T) - includes;
     acc.set_frame((excluded & 1) ? -1.0 : 1.0);
+    if (full_leaf)  // wave-uniform: the leaf that holds the all-include subset
+        include_chain_test<S, T>(hT, bad);
     tail<S, T, 1, Acc>(hT, det, acc, bad);
 }
 
@@ -596,7 +619,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
             }
             __syncthreads();
             tierB<S, R, 1, BL + 1>(tb, ldet, lane, bad);
-            tierC<S, T, B, L, Acc>(tb, ldet, linc, N, lane, acc, bad);
+            tierC<S, T, B, L, Acc>(tb, ldet, linc, N, lane, acc, bad, root == (1ll << k) - 1 && x == nleaf - 1);
             __syncthreads();
         }
 

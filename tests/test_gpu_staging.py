@@ -185,3 +185,34 @@ def test_serving_reports_staging_errors():
         ref = c.eval(O)
     assert rs[1].status == TOR_E_INVAL and rs[2].status == TOR_E_NOT_PD
     assert same_value(rs[0], ref) and same_value(rs[3], ref)
+
+
+def coupled_O(n, i, j, c):
+    """O = I - C for a Gaussian-state C = I/2 except the 2x2 mode coupling c
+    between modes i and j (P = I/2 + c (E_ij + E_ji), Q = 0): positive
+    definite iff |c| < 1/2.  Eliminating mode i first, mode j's pivot is
+    1/2 - 2 c^2, the first to fail when |c| >= 1/2."""
+    P = 0.5 * np.eye(n)
+    P[i, j] = P[j, i] = c
+    C = np.zeros((2 * n, 2 * n), dtype=np.complex128)
+    C[:n, :n] = P
+    C[n:, n:] = P
+    return np.eye(2 * n) - C
+
+
+@pytest.mark.parametrize("n,i,j", [(30, 0, 29), (30, 0, 27), (30, 3, 21), (12, 0, 11), (8, 2, 7)])
+def test_not_positive_definite_at_every_depth(ctxs, n, i, j):
+    """The failing pivot is the last one of the factorisation order (inside
+    the register tail), in the last few modes, in the tier-B range, and for
+    matrices smaller than the kernel's minimum (padded)."""
+    from paper_2109_04528_amd import Context, TOR_E_NOT_PD, TOR_FACTOR_DD, TOR_FORCE_COMPLEX, TOR_OK
+    h, _ = ctxs
+    say(f"case NOT_PD coupling modes {i},{j} of n={n}")
+    good, bad = coupled_O(n, i, j, 0.49), coupled_O(n, i, j, 0.51)
+    assert h.eval(good).status == TOR_OK
+    assert h.eval(bad, check=False).status == TOR_E_NOT_PD
+    if n <= 12:
+        for fl in (TOR_FORCE_COMPLEX, TOR_FACTOR_DD):
+            with Context(device=0, flags=fl) as c:
+                assert c.eval(good).status == TOR_OK
+                assert c.eval(bad, check=False).status == TOR_E_NOT_PD
