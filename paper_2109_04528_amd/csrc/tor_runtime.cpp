@@ -33,6 +33,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -272,11 +273,14 @@ struct StageIn {
 // (StageInfo each, from byte 0); *end receives the first workspace byte
 // after the staging area and *down_end the first free byte of ctx->hdown.
 // stage_collect reads them after the stream has been synchronised.
-// Workspace layout of a staging launch (offsets from its base).
+// Workspace layout of a staging launch (offsets from its base).  A host
+// matrix given several times (the same pointer, leading dimension and size,
+// as for click patterns) is uploaded once: raw_first[i] is set for the input
+// that carries each distinct copy.
 struct StageLayout {
     size_t b_desc = 0, b_info = 0, b_sel = 0, b_raw = 0, up_bytes = 0, total = 0;
     std::vector<size_t> raw_off, out_off;
-    std::vector<const double *> raw_src;  // distinct host matrices, in upload order
+    std::vector<char> raw_first;
 };
 
 StageLayout stage_layout(const std::vector<StageIn> &in, bool on_device, unsigned sflags, int min_cplx)
@@ -292,21 +296,21 @@ StageLayout stage_layout(const std::vector<StageIn> &in, bool on_device, unsigne
     L.b_sel = align_up(sizeof(int) * std::max(nsel, (size_t)1), 256);
     // raw inputs: one compact copy per distinct host matrix
     L.raw_off.assign(count, 0);
-    std::vector<size_t> src_off;
+    L.raw_first.assign(count, 0);
+    std::map<std::tuple<const double *, long, int>, size_t> seen;
     if (!on_device)
         for (int i = 0; i < count; i++) {
             const int rows = 2 * (in[i].sel ? in[i].M : in[i].n);
             if (rows == 0)
                 continue;
-            size_t j = 0;
-            while (j < L.raw_src.size() && L.raw_src[j] != in[i].O)
-                ++j;
-            if (j == L.raw_src.size()) {
-                L.raw_src.push_back(in[i].O);
-                src_off.push_back(L.b_raw);
+            const auto key = std::make_tuple(in[i].O, in[i].ld, rows);
+            auto it = seen.find(key);
+            if (it == seen.end()) {
+                it = seen.emplace(key, L.b_raw).first;
+                L.raw_first[i] = 1;
                 L.b_raw += align_up(sizeof(c64) * (size_t)rows * rows, 256);
             }
-            L.raw_off[i] = src_off[j];
+            L.raw_off[i] = it->second;
         }
     L.up_bytes = L.b_desc + L.b_info + L.b_sel + L.b_raw;
     size_t out_bytes = 0;
@@ -346,7 +350,6 @@ int stage_enqueue(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, 
     StageDesc *hd = (StageDesc *)h;
     int *hsel = (int *)(h + b_desc + b_info);
     size_t sel_at = 0;
-    std::vector<char> copied(L.raw_src.size(), 0);
     struct RawCopy {
         char *dst;
         const double *src;
@@ -370,13 +373,8 @@ int stage_enqueue(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, 
         }
         const int rows = 2 * d.M;
         if (rows > 0 && !on_device) {
-            size_t si = 0;
-            while (L.raw_src[si] != x.O)
-                ++si;
-            if (!copied[si]) {
+            if (L.raw_first[i])
                 copies.push_back(RawCopy{h + b_desc + b_info + b_sel + raw_off[i], x.O, x.ld, rows});
-                copied[si] = 1;
-            }
             d.O = (const double *)(dbase + b_desc + b_info + b_sel + raw_off[i]);
             d.ld = rows;
         } else {
@@ -508,17 +506,23 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     double *dRes = (double *)((char *)dCounter + Lo.b_counter);
     char *dScr = (char *)dRes + Lo.b_res;
     const long long stride = Lo.stride;
-    // descriptors and reduction descriptors at their exact byte offsets
-    std::vector<char> hdesc(Lo.b_probs + Lo.b_red, 0);
-    std::memcpy(hdesc.data(), descs.data(), sizeof(ProblemDesc) * count);
+    // descriptors and reduction descriptors at their exact byte offsets and
+    // the zeroed queue counter after them: one copy from pinned memory (the
+    // previous use of the buffer has been synchronised)
+    const size_t up = Lo.b_probs + Lo.b_red + sizeof(unsigned long long);
+    rc = pin_grow(ctx->hup, ctx->hup_bytes, up);
+    if (rc == TOR_OK)
+        rc = pin_grow(ctx->hdown, ctx->hdown_bytes, sizeof(double) * 4 * (size_t)std::max(nred, 1));
+    if (rc != TOR_OK)
+        return rc;
+    std::memset(ctx->hup, 0, up);
+    std::memcpy(ctx->hup, descs.data(), sizeof(ProblemDesc) * count);
     if (nred)
-        std::memcpy(hdesc.data() + Lo.b_probs, red.data(), sizeof(ProblemDesc) * nred);
+        std::memcpy(ctx->hup + Lo.b_probs, red.data(), sizeof(ProblemDesc) * nred);
 
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(dProbs, hdesc.data(), hdesc.size(), hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess)
-        e = launch_zero(dCounter, 1, ctx->stream);
+        e = hipMemcpyAsync(dProbs, ctx->hup, up, hipMemcpyHostToDevice, ctx->stream);
     MainParams mp{};
     mp.probs = (const ProblemDesc *)dProbs;
     mp.nprob = count;
@@ -534,11 +538,11 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
         e = launch_main(path, dd, mp, grid, ctx->stream);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev1, ctx->stream);  // device_ms: the main kernel alone
-    std::vector<double> hres(4 * (size_t)std::max(nred, 1));
+    const double *hres = (const double *)ctx->hdown;
     if (e == hipSuccess && nred > 0) {
         e = launch_reduce((const ProblemDesc *)dRed, nred, dRes, dd, ctx->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(hres.data(), dRes, sizeof(double) * 4 * nred, hipMemcpyDeviceToHost, ctx->stream);
+            e = hipMemcpyAsync(ctx->hdown, dRes, sizeof(double) * 4 * nred, hipMemcpyDeviceToHost, ctx->stream);
     }
     if (e == hipSuccess)
         e = hipStreamSynchronize(ctx->stream);
@@ -547,7 +551,7 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     if (ms)
         (void)hipEventElapsedTime(ms, ctx->ev0, ctx->ev1);
     if (results)
-        results->assign(hres.begin(), hres.begin() + 4 * nred);
+        results->assign(hres, hres + 4 * (size_t)nred);
     return TOR_OK;
 }
 

@@ -297,7 +297,7 @@ template <int NT>
 __global__ void __launch_bounds__(NT) tor_sqrt_det(const double *O, long ld, int M, c64 *A, double *out)
 {
     const int t = threadIdx.x, m2 = 2 * M;
-    const View v{O, ld, M, nullptr, M};
+    const View v{O, ld, M, nullptr, M, nullptr};
     for (int q = t; q < m2 * m2; q += NT) {
         const int a = q / m2, b = q - a * m2;
         if (a >= b)

@@ -216,3 +216,25 @@ def test_not_positive_definite_at_every_depth(ctxs, n, i, j):
             with Context(device=0, flags=fl) as c:
                 assert c.eval(good).status == TOR_OK
                 assert c.eval(bad, check=False).status == TOR_E_NOT_PD
+
+
+def test_same_host_pointer_with_different_sizes(ctxs):
+    """Through the C ABI: one host array passed twice in a batch, once whole
+    and once as its leading 2m x 2m block (same pointer, larger leading
+    dimension); the upload keeps one copy per (pointer, ld, size)."""
+    import ctypes
+    from paper_2109_04528_amd import _lib
+    h, _ = ctxs
+    O = np.ascontiguousarray(gen.random_O(10, 42, 0.3, 1.2, 0.9))
+    sub = np.ascontiguousarray(O[:12, :12])
+    say("case one host pointer, two sizes, one batch")
+    ns = (ctypes.c_int * 3)(10, 6, 10)
+    ptrs = (ctypes.c_void_p * 3)(O.ctypes.data, O.ctypes.data, O.ctypes.data)
+    lds = (ctypes.c_long * 3)(20, 20, 20)
+    res = (_lib.tor_result * 3)()
+    rc = h._lib.tor_eval_batch(h._h, 3, ns, ptrs, lds, res)
+    assert rc == 0
+    got = [_lib.TorResult.from_c(res[i]) for i in range(3)]
+    a, b = h.eval(O), h.eval(sub)
+    assert same_value(got[0], a) and same_value(got[2], a)
+    assert same_value(got[1], b)
