@@ -152,21 +152,26 @@ __device__ inline hd quad_entry(const View &v, int mi, int mj, int ci, int cj)
 
 __device__ inline double sq(double x, double y) { return x * x + y * y; }
 
-// block-wide max of v (all threads receive it)
-template <int NT>
-__device__ inline double block_max(double v, double *red)
+// block-wide maxima of the K values v (every thread receives them); red
+// holds K * NT / 64 doubles
+template <int NT, int K>
+__device__ inline void block_max(double (&v)[K], double *red)
 {
     const int t = threadIdx.x;
-    for (int off = 32; off >= 1; off >>= 1)
-        v = fmax(v, __shfl_xor(v, off));
+    for (int k = 0; k < K; ++k)
+        for (int off = 32; off >= 1; off >>= 1)
+            v[k] = fmax(v[k], __shfl_xor(v[k], off));
     __syncthreads();
     if ((t & 63) == 0)
-        red[t >> 6] = v;
+        for (int k = 0; k < K; ++k)
+            red[k * (NT / 64) + (t >> 6)] = v[k];
     __syncthreads();
-    double r = red[0];
-    for (int w = 1; w < NT / 64; ++w)
-        r = fmax(r, red[w]);
-    return r;
+    for (int k = 0; k < K; ++k) {
+        double r = red[k * (NT / 64)];
+        for (int w = 1; w < NT / 64; ++w)
+            r = fmax(r, red[k * (NT / 64) + w]);
+        v[k] = r;
+    }
 }
 
 }  // namespace
@@ -178,7 +183,7 @@ constexpr int STAGE_LDS_ENTRIES = NB(80);
 template <int NT>
 __global__ void __launch_bounds__(NT) tor_stage(const StageDesc *descs)
 {
-    __shared__ double red[NT / 64];
+    __shared__ double red[5 * (NT / 64)];
     __shared__ c64 tri[STAGE_LDS_ENTRIES];
     const StageDesc D = descs[blockIdx.x];
     const int t = threadIdx.x;
@@ -192,21 +197,30 @@ __global__ void __launch_bounds__(NT) tor_stage(const StageDesc *descs)
     // below, so it is caught by the finite test alone)
     double nonfin = 0.0, cmax2 = 0.0, dev2 = 0.0, hs2 = 0.0, hd2 = 0.0;
     const bool herm = (fl & STAGE_CHECK_HERM) != 0;
-    for (int q = t; q < n2 * n2; q += NT) {
-        const int a = q / n2, b = q - a * n2;
-        if (a < b && !herm)
-            continue;
+    auto lower = [&](int q, int a, int b) {
         const c64 x = v.og(a, b);
         if (!isfinite(x.x) || !isfinite(x.y))
             nonfin = 1.0;
-        if (a >= b) {
-            const c64 y = a == b ? c64{1.0 - x.x, 0.0} : c64{-x.x, -x.y};
-            cmax2 = fmax(cmax2, sq(y.x, y.y));
-            if (in_lds)
-                tri[pidx(a, b)] = x;
+        const c64 y = a == b ? c64{1.0 - x.x, 0.0} : c64{-x.x, -x.y};
+        cmax2 = fmax(cmax2, sq(y.x, y.y));
+        if (in_lds)
+            tri[q] = x;
+    };
+    if (!herm) {
+        // the lower triangle only, entry q = pidx(a, b)
+        for (int q = t; q < NB(n2); q += NT) {
+            int a, b;
+            tri_ab(q, a, b);
+            lower(q, a, b);
         }
-        if (herm) {
-            const c64 y = v.og(b, a);
+    } else {
+        for (int q = t; q < n2 * n2; q += NT) {
+            const int a = q / n2, b = q - a * n2;
+            if (a >= b)
+                lower(pidx(a, b), a, b);
+            const c64 x = v.og(a, b), y = v.og(b, a);
+            if (!isfinite(x.x) || !isfinite(x.y))
+                nonfin = 1.0;
             hs2 = fmax(hs2, sq(x.x, x.y));
             hd2 = fmax(hd2, sq(x.x - y.x, x.y + y.y));
         }
@@ -227,13 +241,13 @@ __global__ void __launch_bounds__(NT) tor_stage(const StageDesc *descs)
             dev2 = fmax(dev2, sq(d2a.x - d2b.x, d2a.y - d2b.y));
         }
     }
-    nonfin = block_max<NT>(nonfin, red);
-    cmax2 = block_max<NT>(cmax2, red);
-    dev2 = block_max<NT>(dev2, red);
-    if (herm) {
-        hs2 = block_max<NT>(hs2, red);
-        hd2 = block_max<NT>(hd2, red);
-    }
+    double mx[5] = {nonfin, cmax2, dev2, hs2, hd2};
+    block_max<NT, 5>(mx, red);
+    nonfin = mx[0];
+    cmax2 = mx[1];
+    dev2 = mx[2];
+    hs2 = mx[3];
+    hd2 = mx[4];
     const double tol = 64.0 * kStageU * fmax(sqrt(cmax2), 1.0);
     const bool structured = want_real && dev2 <= tol * tol;
     int status = 0;
