@@ -176,7 +176,7 @@ def main():
                     help="time the headline on the complex path (TOR_FORCE_COMPLEX), for its profile")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+        print(f"bench.py: this benchmark runs on one GPU only (asked for {args.gpus}); "
               "the subtree roots would shard across GPUs with one 16-byte reduction per Torontonian, "
               "but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)

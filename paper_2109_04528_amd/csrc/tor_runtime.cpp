@@ -269,7 +269,7 @@ struct StageIn {
 // Enqueue one staging launch for in[0..count) on the context's stream: the
 // descriptors, the pattern lists and (for host inputs) the raw matrices go
 // up in one copy into the workspace from byte base on; the staged forms
-// follow them.  The kernel's verdicts are copied back into ctx->hdown
+// follow them.  The kernel's status records are copied back into ctx->hdown
 // (StageInfo each, from byte 0); *end receives the first workspace byte
 // after the staging area and *down_end the first free byte of ctx->hdown.
 // stage_collect reads them after the stream has been synchronised.
@@ -424,7 +424,7 @@ int stage_enqueue(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, 
 }
 
 // After the stream has been synchronised: each matrix's path, modes and
-// status from the staging kernel's verdicts.
+// status from the staging kernel's records.
 void stage_collect(const tor_ctx *ctx, std::vector<Mat> &mats)
 {
     const StageInfo *info = (const StageInfo *)ctx->hdown;
@@ -1085,7 +1085,7 @@ size_t tor_workspace_size(int max_n, int split_k, int max_inflight)
     const long long items = (1ll << std::min(k, std::max(N - Rmin, 0))) * cnt;
     const size_t grid = 256 * MAX_FIT;
     const size_t scr = align_up(sizeof(c64) * (size_t)std::max(Gsum(N - 1) - Gsum(Rmin - 1), 1ll), 256) * grid;
-    // staging: descriptors and verdicts, a raw copy of each input and its
+    // staging: descriptors and status records, a raw copy of each input and its
     // staged form (16-byte scalars bound every path)
     const size_t n2 = 2 * (size_t)std::max(max_n, 1);
     const size_t stage = align_up(sizeof(StageDesc) * cnt, 256) + align_up(sizeof(StageInfo) * cnt, 256) + 256 +
@@ -1327,7 +1327,7 @@ int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count, co
     rc = stage_enqueue(ctx, in, true, sfl, CPLX_R, base, mats, &end, &down);
     if (rc != TOR_OK)
         return rc;
-    // stage_enqueue leaves 256 spare bytes after the verdicts (a copy into
+    // stage_enqueue leaves 256 spare bytes after the status records (a copy into
     // the buffer is pending, so it must not be regrown here)
     const size_t det_at = align_up(down, 16);
     if (det_at + 2 * sizeof(double) > ctx->hdown_bytes)
