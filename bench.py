@@ -223,6 +223,7 @@ def main():
     t1 = time.perf_counter()
     print(f"bench: {args.steps} steps done", file=sys.stderr, flush=True)
     step_s = (t1 - t0) / args.steps
+    fma_tflops, _ = dctx.fma_peak()  # the FP64 peak confirmed on this device
     dctx.close()
     # the same step from a host matrix (its PCIe copy included), for context
     ctx = Context(device=0, stream=stream, workspace=ws, flags=path_flags)
@@ -376,6 +377,7 @@ def main():
         "cancellation_R": r.cancellation,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": stored_traffic() if real_path else None,
+                     "peak_measured": fma_tflops, "frac_of_measured": achieved / fma_tflops,
                      "flop_per_launch": flops,
                      "kernel": "tor_main<double, T=5, B=6, L=2>" if real_path else "tor_main<c64, T=3, B=6, L=2>"},
         "plain": plain,

@@ -203,6 +203,14 @@ int tor_drain(tor_ctx *ctx, int timeout_ms);
  * third-order correction), then the two raw hardware seeds. */
 int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out);
 
+/* Measurement aid: the device's FP64 FMA throughput, to confirm the vector
+ * peak the roofline is quoted against.  One kernel of 16 workgroups of 256
+ * lanes per CU, each lane running 16 independent FMA chains of iters steps
+ * (1 <= iters <= 2^20), timed with HIP events after one untimed launch.
+ * *tflops receives 2 * 16 * iters * lanes / time; *ms (may be NULL) the
+ * kernel time.  Uses the context's workspace. */
+int tor_debug_fma_peak(tor_ctx *ctx, int iters, double *tflops, float *ms);
+
 /* Serving policy.  Each serving launch runs at most chunk_subsets subsets
  * (default 2^29, about 2.5 ms at n = 30 rates) taken from the admitted
  * requests: oldest_share of it (default 0.5) goes to the oldest request, the

@@ -39,7 +39,7 @@ TOR_FACTOR_DD = 0x8
 EXPORTS = [
     "tor_default_options", "tor_create", "tor_destroy", "tor_workspace_size", "tor_eval",
     "tor_eval_batch", "tor_eval_plain", "tor_eval_partials", "tor_submit", "tor_poll",
-    "tor_drain", "tor_debug_math", "tor_strerror", "tor_autotune", "tor_tune_save", "tor_tune_load",
+    "tor_drain", "tor_debug_math", "tor_debug_fma_peak", "tor_strerror", "tor_autotune", "tor_tune_save", "tor_tune_load",
     "tor_serve_config", "tor_click_probs", "tor_eval_removal",
 ]
 
@@ -134,6 +134,8 @@ def load(path: str = LIB_PATH):
     lib.tor_drain.restype = ctypes.c_int
     lib.tor_debug_math.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]
     lib.tor_debug_math.restype = ctypes.c_int
+    lib.tor_debug_fma_peak.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_float)]
+    lib.tor_debug_fma_peak.restype = ctypes.c_int
     lib.tor_serve_config.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_double, ctypes.c_int]
     lib.tor_serve_config.restype = ctypes.c_int
     lib.tor_click_probs.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long, ctypes.c_int,
@@ -401,6 +403,15 @@ class Context:
         if rc != TOR_OK:
             raise TorError(rc, "tor_debug_math")
         return out.reshape(-1, 4)
+
+    def fma_peak(self, iters: int = 4096):
+        """Measured FP64 FMA throughput of the device: (TFLOP/s, kernel ms)."""
+        tf = ctypes.c_double()
+        ms = ctypes.c_float()
+        rc = self._lib.tor_debug_fma_peak(self._h, iters, ctypes.byref(tf), ctypes.byref(ms))
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_debug_fma_peak")
+        return tf.value, ms.value
 
 
 def workspace_size(max_n: int, split_k: int = 0, max_inflight: int = 1) -> int:

@@ -151,6 +151,9 @@ hipError_t launch_plain(const PlainParams &p, int grid, hipStream_t s);
 hipError_t launch_removal(const RemovalParams &p, int grid, hipStream_t s);
 hipError_t launch_plain_reduce(const double *partials, int nwaves, double *result, hipStream_t s);
 hipError_t launch_math_probe(const double *x, double *out, int count, hipStream_t s);
+// FP64 FMA throughput probe: blocks x 256 lanes, iters x 16 FMAs each
+hipError_t launch_fma_peak(double *out, int blocks, int iters, hipStream_t s);
+constexpr int FMA_PROBE_CHAINS = 16;
 // defined in tor_stage.hip
 hipError_t launch_stage(const StageDesc *descs, int count, hipStream_t s);
 hipError_t launch_sqrt_det(const double *O, long ld, int M, c64 *scratch, double *out, hipStream_t s);

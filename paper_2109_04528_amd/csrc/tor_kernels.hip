@@ -1060,18 +1060,6 @@ __global__ void __launch_bounds__(64) tor_plain_reduce(const double *parts, int 
     }
 }
 
-// accuracy probe of the device reciprocal / reciprocal square root
-__global__ void tor_math_probe(const double *x, double *out, int count)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) {
-        out[4 * i] = rsqrt_nr(x[i]);
-        out[4 * i + 1] = rcp_nr(x[i]);
-        out[4 * i + 2] = __builtin_amdgcn_rsq(x[i]);
-        out[4 * i + 3] = __builtin_amdgcn_rcp(x[i]);
-    }
-}
-
 // ---------------------------------------------------------------------------
 hipError_t launch_main(int path, bool dd, const MainParams &p, int grid, hipStream_t s)
 {
@@ -1137,10 +1125,5 @@ hipError_t launch_plain_reduce(const double *partials, int nwaves, double *resul
     return hipGetLastError();
 }
 
-hipError_t launch_math_probe(const double *x, double *out, int count, hipStream_t s)
-{
-    hipLaunchKernelGGL(tor_math_probe, dim3((count + 63) / 64), dim3(64), 0, s, x, out, count);
-    return hipGetLastError();
-}
 
 }  // namespace tor

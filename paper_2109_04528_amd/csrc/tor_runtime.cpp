@@ -1523,6 +1523,39 @@ int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out)
     return hip_status(e);
 }
 
+int tor_debug_fma_peak(tor_ctx *ctx, int iters, double *tflops, float *ms_out)
+{
+    if (!ctx || !tflops || iters < 1 || iters > (1 << 20))
+        return TOR_E_INVAL;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    // 16 workgroups of 256 lanes per CU: every SIMD holds several waves
+    const int blocks = 16 * ctx->num_cu;
+    const size_t bytes = sizeof(double) * 256 * (size_t)blocks;
+    int rc = ensure_ws(ctx, bytes);
+    if (rc != TOR_OK)
+        return rc;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess)  // one launch to bring the clocks up, then the timed one
+        e = launch_fma_peak((double *)ctx->ws, blocks, iters, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev0, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_fma_peak((double *)ctx->ws, blocks, iters, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev1, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    const double flop = 2.0 * FMA_PROBE_CHAINS * (double)iters * 256.0 * (double)blocks;
+    *tflops = ms > 0.f ? flop / ((double)ms * 1e-3) / 1e12 : 0.0;
+    if (ms_out)
+        *ms_out = ms;
+    return TOR_OK;
+}
+
 // ---- serving ---------------------------------------------------------------
 
 int tor_submit(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long *ticket)

@@ -86,6 +86,15 @@ def test_math_probe(ctx):
     assert ulps(out[:, 1], rc).max() <= 1
 
 
+def test_fma_peak_probe(ctx):
+    """The FP64 FMA probe reaches a throughput of the order of the published
+    vector peak (78.6 TFLOP/s): more than half of it, and not above it by
+    more than the clock's headroom."""
+    tf, ms = ctx.fma_peak(2048)
+    say(f"case fma peak: {tf:.1f} TFLOP/s in {ms:.3f} ms")
+    assert 39.3 < tf < 100.0
+
+
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 8, 9, 10, 11, 12, 13])
 def test_small_n_against_quad(ctx, n):
     O = gen.random_O(n, 100 + n, 0.5, 1.0, 0.7) if n else gen.vacuum_O(0)
