@@ -175,6 +175,31 @@ def test_n30_partials_sampled_against_oracle(ctx):
         assert abs(parts[root, 2] - q.sum_abs) <= 1e-12 * q.sum_abs
 
 
+@pytest.mark.parametrize("label,n,gen_fn", [
+    ("complex path, precision workload", 30, lambda: gen.random_O(30, 0, 0.3, 1.2, 0.9)),
+    ("complex path, generic HPD", 26, lambda: gen.random_hpd_O(26, 77, 0.05, 0.9)),
+])
+def test_complex_path_partials_sampled_against_oracle(label, n, gen_fn):
+    # the general Hermitian path at full size: subtrees against the oracle
+    # restricted to the same roots
+    from paper_2109_04528_amd import Context, TOR_FORCE_COMPLEX
+    O = gen_fn()
+    say(f"case {label} n={n} partials")
+    with Context(device=0, flags=TOR_FORCE_COMPLEX) as c:
+        k, parts, res = c.eval_partials(O, 12)
+    say(f"  k={k} tor={res.value!r} R={res.cancellation:.3e} ms={res.device_ms:.2f} path={res.path}")
+    assert k == 12 and res.status == 0 and res.path == 2
+    rng = np.random.default_rng(2)
+    for root in [0, (1 << k) - 1] + [int(v) for v in rng.integers(1, (1 << k) - 1, 2)]:
+        q = orc.tor(O, mode=orc.F64, fix_mask=(1 << k) - 1, fix_val=root)
+        got = parts[root, 0] + parts[root, 1]
+        bound = 2 * term_bound(O, q.sum_abs)  # both sides round each term in FP64
+        say(f"  root {root}: gpu={got!r} oracle={q.value!r} diff={abs(got - q.value):.3e} bound={bound:.3e}")
+        assert q.count == 1 << (n - k)
+        assert abs(got - q.value) <= bound
+        assert abs(parts[root, 2] - q.sum_abs) <= 1e-12 * q.sum_abs
+
+
 def test_batch_is_bitwise_equal_to_single(ctx):
     ns = [12, 9, 15, 3, 11, 0, 14]
     Os = [gen.random_O(n, 200 + i, 0.5, 1.0, 0.3 + 0.1 * i) if n else gen.vacuum_O(0) for i, n in enumerate(ns)]
