@@ -534,8 +534,10 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     const bool dd = ctx->opt.accum != TOR_ACCUM_FP64 || path == PATH_QUAD;
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev0, ctx->stream);
+    // no more persistent waves than queue items: a launch of few roots (a
+    // small matrix) does not pay for starting the whole grid
     if (e == hipSuccess && total > 0)
-        e = launch_main(path, dd, mp, grid, ctx->stream);
+        e = launch_main(path, dd, mp, (int)std::min<long long>(grid, total), ctx->stream);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev1, ctx->stream);  // device_ms: the main kernel alone
     const double *hres = (const double *)ctx->hdown;
