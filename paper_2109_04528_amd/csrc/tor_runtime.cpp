@@ -1396,7 +1396,9 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long 
     if (mats[0].status != TOR_OK)
         return mats[0].status;
     const int chunk = 16;
-    const int pgrid = ctx->grid[PATH_CPLX];
+    // no more waves than chunks of the mask range
+    const unsigned long long nchunks = (mask_end - mask_begin + chunk - 1) / chunk;
+    const int pgrid = (int)std::max<unsigned long long>(1, std::min<unsigned long long>(ctx->grid[PATH_CPLX], nchunks));
     const size_t bParts = align_up(sizeof(double) * 4 * pgrid, 256);
     rc = ensure_ws_keep(ctx, end + 256 + bParts + 256, end);
     if (rc != TOR_OK)
