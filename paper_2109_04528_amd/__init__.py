@@ -21,6 +21,10 @@ from ._lib import (  # noqa: F401
 
 
 def tor(O, **ctx_kwargs) -> float:
-    """Torontonian of one matrix with a throw-away context."""
+    """Torontonian of one matrix with a throw-away context.  A torch CUDA
+    tensor is read in place (TOR_INPUT_DEVICE); anything else is copied
+    from host memory."""
+    if getattr(getattr(O, "device", None), "type", None) == "cuda":
+        ctx_kwargs["flags"] = ctx_kwargs.get("flags", 0) | TOR_INPUT_DEVICE
     with Context(**ctx_kwargs) as ctx:
         return ctx.eval(O).value

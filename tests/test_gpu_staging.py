@@ -71,6 +71,12 @@ def test_device_input_eval_and_batch(ctxs):
     assert all(same(x, y) for x, y in zip(ra, rb))
 
 
+def test_convenience_function_takes_host_and_device_matrices():
+    from paper_2109_04528_amd import tor
+    O = gen.random_O(9, 43, 0.3, 1.2, 0.9)
+    assert tor(O) == tor(dev(O))
+
+
 def test_device_input_strided(ctxs):
     _, d = ctxs
     import torch
