@@ -114,6 +114,7 @@ struct tor_ctx {
     int admitted = 0;
     int max_queue = 1 << 16;
     long long chunk_subsets = 1ll << 29;  // work per serving launch
+    long long express_subsets = 1ll << 24; // requests this small run ahead, whole
     double oldest_share = 0.5;            // of it, guaranteed to the oldest request
     char *pool = nullptr;
     size_t pool_bytes = 256ull << 20;
@@ -819,12 +820,16 @@ size_t request_bytes(int n, unsigned sflags)
 }
 
 // One scheduling round for one path: pick root ranges for a launch, run it,
-// retire the finished requests.  Called with ctx->mu held.
-int serve_round(tor_ctx *ctx, int path, std::vector<Request *> &active, std::vector<Request *> &finished)
+// retire the finished requests.  With express set, the launch takes only the
+// requests whose remaining work is at most ctx->express_subsets, whole.
+// Called with ctx->mu held.
+int serve_round(tor_ctx *ctx, int path, std::vector<Request *> &active, std::vector<Request *> &finished,
+                bool express)
 {
     std::vector<Request *> cand;
     for (Request *r : active)
-        if (r->path == path && r->next_root < r->nroots)
+        if (r->path == path && r->next_root < r->nroots &&
+            (!express || (r->nroots - r->next_root) * r->root_work <= ctx->express_subsets))
             cand.push_back(r);
     if (cand.empty())
         return TOR_OK;
@@ -835,7 +840,7 @@ int serve_round(tor_ctx *ctx, int path, std::vector<Request *> &active, std::vec
     std::stable_sort(cand.begin(), cand.end(), [](Request *a, Request *b) {
         return (a->nroots - a->next_root) * a->root_work < (b->nroots - b->next_root) * b->root_work;
     });
-    long long budget = ctx->chunk_subsets;
+    long long budget = express ? (long long)1 << 62 : ctx->chunk_subsets;
     std::vector<ProblemDesc> descs;
     std::vector<Request *> used;
     auto take = [&](Request *r, long long share) {
@@ -899,6 +904,22 @@ int serve_round(tor_ctx *ctx, int path, std::vector<Request *> &active, std::vec
 void serve_loop(tor_ctx *ctx)
 {
     std::vector<Request *> active;
+    // retire finished requests: release their pool memory and wake pollers
+    auto publish = [&](std::vector<Request *> &fin) {
+        if (fin.empty())
+            return;
+        {
+            std::lock_guard<std::mutex> g(ctx->smu);
+            for (Request *r : fin) {
+                pool_release(ctx, r->pool_off, r->pool_len);
+                r->done = true;
+                --ctx->admitted;
+                active.erase(std::remove(active.begin(), active.end(), r), active.end());
+            }
+        }
+        ctx->scv.notify_all();
+        fin.clear();
+    };
     for (;;) {
         std::vector<Request *> admit;
         {
@@ -967,21 +988,16 @@ void serve_loop(tor_ctx *ctx)
                 std::vector<double>().swap(r->raw);
                 active.push_back(r);
             }
+            // small requests first, in launches of their own, and their
+            // results published before the chunked launch starts, so that
+            // they wait for at most one large launch
             for (int path : {PATH_REAL, PATH_CPLX, PATH_QUAD})
-                serve_round(ctx, path, active, finished);
+                serve_round(ctx, path, active, finished, true);
+            publish(finished);
+            for (int path : {PATH_REAL, PATH_CPLX, PATH_QUAD})
+                serve_round(ctx, path, active, finished, false);
         }
-        if (finished.empty() && admit.empty() && active.empty())
-            continue;
-        {
-            std::lock_guard<std::mutex> g(ctx->smu);
-            for (Request *r : finished) {
-                pool_release(ctx, r->pool_off, r->pool_len);
-                r->done = true;
-                --ctx->admitted;
-                active.erase(std::remove(active.begin(), active.end(), r), active.end());
-            }
-        }
-        ctx->scv.notify_all();
+        publish(finished);
     }
 }
 
