@@ -214,7 +214,10 @@ int tor_debug_fma_peak(tor_ctx *ctx, int iters, double *tflops, float *ms);
 /* Serving policy.  Each serving launch runs at most chunk_subsets subsets
  * (default 2^29, about 2.5 ms at n = 30 rates) taken from the admitted
  * requests: oldest_share of it (default 0.5) goes to the oldest request, the
- * rest to the requests with the least remaining work.  max_queue bounds the
+ * rest to the requests with the least remaining work.  Before each such
+ * launch, the requests with at most 2^24 subsets of work left (n <= 24) run
+ * whole in a launch of their own, and their results can be polled before the
+ * chunked launch starts.  max_queue bounds the
  * requests held (admitted or waiting); tor_submit beyond it returns
  * TOR_E_BUSY.  Applies from the next launch on. */
 int tor_serve_config(tor_ctx *ctx, long long chunk_subsets, double oldest_share, int max_queue);
