@@ -873,11 +873,6 @@ int serve_round(tor_ctx *ctx, int path, std::vector<Request *> &active, std::vec
     for (size_t i = 0; i < used.size(); i++)
         if (used[i]->next_root == used[i]->nroots && std::find(used.begin(), used.begin() + i, used[i]) == used.begin() + i)
             red.push_back((int)i);
-    std::vector<ProblemDesc> rdesc;
-    for (int i : red) {
-        ProblemDesc d = descs[i];
-        rdesc.push_back(d);
-    }
     std::vector<double> res;
     float ms = 0.f;
     int rc = run_launch(ctx, path, descs, red, 0, launch_grid(ctx, path, Nmax), &res, &ms);
@@ -934,7 +929,17 @@ void serve_loop(tor_ctx *ctx)
                 if (!ctx->pool) {
                     if (hipSetDevice(ctx->device) != hipSuccess ||
                         hipMalloc((void **)&ctx->pool, ctx->pool_bytes) != hipSuccess) {
+                        // no device memory for the pool: every waiting
+                        // request completes with TOR_E_NOMEM (the next
+                        // submission tries again)
                         ctx->pool = nullptr;
+                        for (Request *q : ctx->pending) {
+                            q->res = tor_result{};
+                            q->res.status = TOR_E_NOMEM;
+                            q->done = true;
+                        }
+                        ctx->pending.clear();
+                        ctx->scv.notify_all();
                         break;
                     }
                     ctx->pool_free.clear();
