@@ -92,7 +92,7 @@ typedef struct tor_ctx tor_ctx;
 typedef struct {
     int device;             /* HIP device ordinal                                     */
     void *stream;           /* hipStream_t to run on (NULL: the library creates one)  */
-    void *workspace;        /* caller-owned device buffer or NULL (library allocates) */
+    void *workspace;        /* caller-owned device buffer, 256-byte aligned, or NULL  */
     size_t workspace_bytes; /* its size; see tor_workspace_size                       */
     int max_n;              /* largest n this context accepts (0: 40)                 */
     int split_k;            /* roots = 2^split_k per matrix (0: automatic)            */
@@ -118,7 +118,8 @@ typedef struct {
 void tor_default_options(tor_options *opt);
 
 /* Create a context on opt->device.  *out receives the handle.
- * Errors: TOR_E_INVAL (null out), TOR_E_DEVICE (no GPU), TOR_E_NOMEM. */
+ * Errors: TOR_E_INVAL (null out, an option out of range, a workspace not
+ * aligned to 256 bytes), TOR_E_DEVICE (no GPU), TOR_E_NOMEM. */
 int tor_create(tor_ctx **out, const tor_options *opt);
 
 /* Wait for in-flight work, then free every device and host resource. */

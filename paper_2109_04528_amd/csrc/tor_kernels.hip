@@ -44,42 +44,77 @@ namespace tor {
 // LDS placement of the nodes tier B stores: node 0 is the tier-A leaf (R
 // modes), node 2^(j-1) + i the include node i of level j (R - j modes), for
 // j = 1..BL.  Nodes follow one another in that order, each on a 16-byte
-// boundary.  Tier C reads the same entry of 16 different nodes in one
-// instruction, so each node is moved forward (by at most 15 granules) to the
-// first place where the starts of its granule arrays, taken as 16-byte slots
-// modulo 16 (a bank group in a 256-byte row of banks), clash with as few
-// earlier nodes' starts of the same array as possible.  Returns the byte
-// offset of node `stop`, or the total size for stop = 2^BL.
-__host__ __device__ constexpr int node_place(int R, int BL, int esz, int stop)
-{
-    const int gpb = 4 / EPG(esz);  // granule arrays per node
-    unsigned used[4] = {0u, 0u, 0u, 0u};
-    int off = 0;
-    for (int t = 0; t < (1 << BL); ++t) {
+// boundary.  Tier C reads the same entry of all 2^BL nodes in one
+// instruction, 2^L lanes per node (lane l reads the node that level-BL view
+// l >> L stands for).  LDS serves such an access in groups of lanes that move
+// 128 bytes per cycle (256 with 64 banks), and two lanes of one group that
+// touch different words of one bank wait for each other.  Each node is
+// therefore moved forward (by at most 15 granules) to the first place where
+// the start of each of its granule arrays, as a 16-byte slot modulo 8 (and
+// modulo 16), differs from that of the other nodes read by the same group of
+// lanes; failing that, to the place with the fewest such clashes.
+template <int R, int BL, int ESZ, int L>
+struct NodePlacement {
+    static constexpr int NN = 1 << BL;
+    int off[NN + 1];
+    // the level-BL view whose stored node is t: the include node i of
+    // level j is followed by excludes only
+    static constexpr int reader(int t)
+    {
+        if (t == 0)
+            return 0;
         int lev = 0;
         while ((1 << lev) <= t)
             ++lev;
-        const int nb = NB(R - lev);
-        const int b0 = (off + 15) & ~15;
-        int best = b0, bestc = 5;
-        for (int k = 0; k < 16 && bestc > 0; ++k) {
-            const int b = b0 + 16 * k;
-            int c = 0;
-            for (int g = 0; g < gpb; ++g)
-                c += (int)((used[g] >> (((b >> 4) + g * nb) & 15)) & 1u);
-            if (c < bestc) {
-                bestc = c;
-                best = b;
-            }
-        }
-        if (t == stop)
-            return best;
-        for (int g = 0; g < gpb; ++g)
-            used[g] |= 1u << (((best >> 4) + g * nb) & 15);
-        off = best + esz * NSZ(R - lev);
+        const int idx = t - (1 << (lev - 1));
+        return ((idx << 1) | 1) << (BL - lev);
     }
-    return off;
-}
+    static constexpr int level(int t)
+    {
+        int lev = 0;
+        while ((1 << lev) <= t)
+            ++lev;
+        return lev;
+    }
+    constexpr NodePlacement() : off{}
+    {
+        constexpr int gpb = 4 / EPG(ESZ);          // granule arrays per node
+        constexpr int acc = ESZ == 8 ? 8 : 16;     // bytes per lane per access
+        // nodes per lane group and slot modulus: 32 banks, then 64 banks
+        constexpr int grp[2] = {(128 / acc) >> L, (256 / acc) >> L};
+        constexpr int mods[2] = {8, 16};
+        int slot[NN] = {};
+        int pos = 0;
+        for (int t = 0; t < NN; ++t) {
+            const int nb = NB(R - level(t));
+            const int b0 = (pos + 15) & ~15;
+            int best = b0, bestc = 1 << 30;
+            for (int k = 0; k < 16 && bestc > 0; ++k) {
+                const int st = (b0 >> 4) + k;
+                int c = 0;
+                for (int u = 0; u < t; ++u) {
+                    const int unb = NB(R - level(u));
+                    for (int mdl = 0; mdl < 2; ++mdl) {
+                        const int G = grp[mdl] > 1 ? grp[mdl] : 1;
+                        if (reader(u) / G != reader(t) / G)
+                            continue;
+                        for (int g = 0; g < gpb; ++g)
+                            if ((st + g * nb) % mods[mdl] == (slot[u] + g * unb) % mods[mdl])
+                                ++c;
+                    }
+                }
+                if (c < bestc) {
+                    bestc = c;
+                    best = b0 + 16 * k;
+                }
+            }
+            off[t] = best;
+            slot[t] = best >> 4;
+            pos = best + ESZ * NSZ(R - level(t));
+        }
+        off[NN] = pos;
+    }
+};
 
 // 2x2 pivot of the highest mode m of a node, and the update of one output
 // block (a, b), a >= b, m > a:
@@ -97,12 +132,38 @@ __device__ __forceinline__ const S &blk(const S *node, int nb, int bi, int e)
 {
     return node[gpos((int)sizeof(S), nb, bi, e)];
 }
+// a whole block moves as 16-byte granules (node bases and granule arrays
+// are 16-byte aligned), one 128-bit access each: lanes on neighbouring
+// blocks then touch neighbouring 16-byte words, which LDS serves without
+// bank conflicts (two 64-bit halves of a 16-byte stride would conflict)
+template <class S>
+struct __align__(16) Gran {
+    S e[EPG((int)sizeof(S))];
+};
+template <class S>
+__device__ __forceinline__ void get_block(const S *node, int nb, int bi, S *v)
+{
+    constexpr int G = EPG((int)sizeof(S));
+#pragma unroll
+    for (int g = 0; g < 4 / G; ++g) {
+        const Gran<S> q = *reinterpret_cast<const Gran<S> *>(node + gpos((int)sizeof(S), nb, bi, g * G));
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            v[g * G + j] = q.e[j];
+    }
+}
 template <class S>
 __device__ __forceinline__ void put_block(S *node, int nb, int bi, const S *o)
 {
+    constexpr int G = EPG((int)sizeof(S));
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-        blk(node, nb, bi, e) = o[e];
+    for (int g = 0; g < 4 / G; ++g) {
+        Gran<S> q;
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            q.e[j] = o[g * G + j];
+        *reinterpret_cast<Gran<S> *>(node + gpos((int)sizeof(S), nb, bi, g * G)) = q;
+    }
 }
 
 template <class S>
@@ -116,17 +177,20 @@ template <class S>
 __device__ __forceinline__ void elim_block(const S *node, int nb, int m, int a, int b, int ih, const Piv<S> &pv,
                                            S *o)
 {
-    const int ia = bidx(m, a), ib = bidx(m, b);
-    const S ra0 = blk(node, nb, ia, 0), ra1 = blk(node, nb, ia, 1);
-    const S qa0 = sub_mul(blk(node, nb, ia, 2), ra0, pv.ba), qa1 = sub_mul(blk(node, nb, ia, 3), ra1, pv.ba);
-    const S rb0 = blk(node, nb, ib, 0), rb1 = blk(node, nb, ib, 1);
-    const S qb0 = sub_mul(blk(node, nb, ib, 2), rb0, pv.ba), qb1 = sub_mul(blk(node, nb, ib, 3), rb1, pv.ba);
+    S A[4], Bk[4], H[4];
+    get_block(node, nb, bidx(m, a), A);
+    get_block(node, nb, bidx(m, b), Bk);
+    get_block(node, nb, ih, H);
+    const S ra0 = A[0], ra1 = A[1];
+    const S qa0 = sub_mul(A[2], ra0, pv.ba), qa1 = sub_mul(A[3], ra1, pv.ba);
+    const S rb0 = Bk[0], rb1 = Bk[1];
+    const S qb0 = sub_mul(Bk[2], rb0, pv.ba), qb1 = sub_mul(Bk[3], rb1, pv.ba);
     const S ua0 = scale(ra0, pv.inv_a), ua1 = scale(ra1, pv.inv_a);
     const S va0 = scale(qa0, pv.inv_g), va1 = scale(qa1, pv.inv_g);
-    o[0] = upd(blk(node, nb, ih, 0), ua0, rb0, va0, qb0);
-    o[1] = upd(blk(node, nb, ih, 1), ua0, rb1, va0, qb1);
-    o[2] = upd(blk(node, nb, ih, 2), ua1, rb0, va1, qb0);
-    o[3] = upd(blk(node, nb, ih, 3), ua1, rb1, va1, qb1);
+    o[0] = upd(H[0], ua0, rb0, va0, qb0);
+    o[1] = upd(H[1], ua0, rb1, va0, qb1);
+    o[2] = upd(H[2], ua1, rb0, va1, qb0);
+    o[3] = upd(H[3], ua1, rb1, va1, qb1);
     if (a == b) {  // diagonal block: real diagonal, conjugate upper entry
         o[0] = fix_diag(o[0]);
         o[3] = fix_diag(o[3]);
@@ -176,27 +240,16 @@ __device__ void elim_global(const S *__restrict__ src, int snb, S *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// node_place for every stored node, evaluated at compile time
-template <int R, int BL, int ESZ>
-struct NodePlacement {
-    int off[(1 << BL) + 1];
-    constexpr NodePlacement() : off{}
-    {
-        for (int t = 0; t <= (1 << BL); ++t)
-            off[t] = node_place(R, BL, ESZ, t);
-    }
-};
-
 // View t of the tier-B tables: for the node of level jl with id i (bit
 // jl-1-m of i = decision on the m-th mode below the tier-A leaf, 1 =
 // include; t = (2^jl - 1) + i) the LDS offset of the stored node it is a
 // view of, that node's blocks per granule array, and the slot of its
 // determinant (0xff: the tier-A leaf).  The include node (lev, idx) keeps
 // its determinant at (2^(lev-1) - 1) + idx.
-template <int R, int B, int ESZ>
+template <int R, int B, int ESZ, int L>
 __device__ __forceinline__ void view_entry(int t, int &off, int &nb, int &det)
 {
-    static constexpr NodePlacement<R, B - 1, ESZ> place{};
+    static constexpr NodePlacement<R, B - 1, ESZ, L> place{};
     const int jl = 31 - __clz(t + 1);
     const int i = t + 1 - (1 << jl);
     if (i == 0) {
@@ -217,14 +270,14 @@ __device__ __forceinline__ void view_entry(int t, int &off, int &nb, int &det)
 // node i of level J (record (2^(J-1) - 1) + i) its parent's stored offset
 // and blocks per array and its own stored offset, packed in 64 bits; per
 // block bi of a child (a, b) and its block index bidx(a, b) packed.
-template <class S, int R, int B>
+template <class S, int R, int B, int L>
 __device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcNB, uint8_t *srcDet,
                                              unsigned long long *nodeRec, uint32_t *blkRec, int lane)
 {
     constexpr int esz = (int)sizeof(S);
     for (int t = lane; t < (1 << B) - 1; t += 64) {
         int off, nb, det;
-        view_entry<R, B, esz>(t, off, nb, det);
+        view_entry<R, B, esz, L>(t, off, nb, det);
         srcOff[t] = (uint16_t)off;
         srcNB[t] = (uint8_t)nb;
         srcDet[t] = (uint8_t)det;
@@ -235,8 +288,8 @@ __device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcNB, u
         const int J = 32 - __clz(t + 1);  // t = (2^(J-1) - 1) + i
         const int i = t + 1 - (1 << (J - 1));
         int poff, pnb, pdet, coff, cnb, cdet;
-        view_entry<R, B, esz>(t, poff, pnb, pdet);
-        view_entry<R, B, esz>((1 << J) + 2 * i, coff, cnb, cdet);
+        view_entry<R, B, esz, L>(t, poff, pnb, pdet);
+        view_entry<R, B, esz, L>((1 << J) + 2 * i, coff, cnb, cdet);
         nodeRec[t] = (unsigned long long)poff | ((unsigned long long)pnb << 16) | ((unsigned long long)coff << 32);
     }
     for (int bi = lane; bi < NB(R - 1); bi += 64) {
@@ -249,7 +302,7 @@ __device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcNB, u
 // LDS tables of tier B (see build_tables) and its per-node pivot scalars
 template <class S>
 struct TierB {
-    S *buf;                 // stored nodes (node_place)
+    S *buf;                 // stored nodes (NodePlacement)
     const uint16_t *srcOff; // per view: offset of its stored node
     const uint8_t *srcNB;   // per view: blocks per granule array of that node
     const uint8_t *srcDet;  // per view: determinant slot (0xff: tier-A leaf)
@@ -510,7 +563,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
     constexpr int R = T + B;
     constexpr int BL = B - L;                // levels expanded in LDS
     constexpr int NN_MAX = 1 << (BL - 1);    // include nodes of the last LDS level
-    __shared__ S bufB[node_place(R, BL, (int)sizeof(S), 1 << BL) / (int)sizeof(S)];
+    __shared__ S bufB[NodePlacement<R, BL, (int)sizeof(S), L>{}.off[1 << BL] / (int)sizeof(S)];
     __shared__ S nBa[NN_MAX];
     __shared__ RT<S> nInv[2 * NN_MAX];
     __shared__ RT<S> ndet[1 << BL];
@@ -523,7 +576,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
     __shared__ int sinc[MAX_N + 1];
 
     const int lane = threadIdx.x;
-    build_tables<S, R, BL + 1>(srcOff, srcNB, srcDet, nodeRec, blkRec, lane);
+    build_tables<S, R, BL + 1, L>(srcOff, srcNB, srcDet, nodeRec, blkRec, lane);
     __syncthreads();
     const TierB<S> tb{bufB, srcOff, srcNB, srcDet, nodeRec, blkRec, nInv, nBa, ndet};
     S *wscr = reinterpret_cast<S *>(prm.scratch + (long long)blockIdx.x * prm.scratch_stride);
@@ -571,6 +624,16 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
         Acc acc;
         const long long nleaf = 1ll << D;
         for (long long x = 0; x < nleaf; ++x) {
+            // double-double factor: an empty asm hides that the lane index
+            // is the same in every leaf, so what the tiers derive from it
+            // (block and node indices, table entries) is recomputed in each
+            // leaf instead of being held in registers across the whole loop.
+            // That brings the kernel to 256 registers, two waves per SIMD;
+            // the FP64 kernels already fit and run faster with the values
+            // held.
+            int lane = threadIdx.x;
+            if constexpr (std::is_same<S, ddr>::value)
+                __asm__ volatile("" : "+v"(lane));
             RT<S> ldet;
             int linc;
             if (x == 0) {

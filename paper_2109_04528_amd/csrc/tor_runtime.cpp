@@ -1130,7 +1130,8 @@ int tor_create(tor_ctx **out, const tor_options *opt)
         o.max_n = 40;
     if (o.max_n > MAX_N || o.split_k < 0 || o.split_k > 40 || o.waves_per_cu < 0 || o.waves_per_cu > 16 ||
         (o.accum != TOR_ACCUM_DD && o.accum != TOR_ACCUM_FP64) ||
-        ((o.flags & TOR_FACTOR_DD) && (o.flags & TOR_FORCE_COMPLEX)))
+        ((o.flags & TOR_FACTOR_DD) && (o.flags & TOR_FORCE_COMPLEX)) ||
+        ((uintptr_t)o.workspace & 255))  // the kernels read 16-byte granules
         return TOR_E_INVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0 || o.device < 0 || o.device >= ndev)

@@ -59,3 +59,25 @@ def test_create_reports_missing_device():
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
     assert _lib.load().tor_create(ctypes.byref(h), None) == _lib.TOR_E_DEVICE
+
+
+def test_create_rejects_bad_options_before_touching_a_device():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    bad = []
+    o = _lib.tor_options()
+    lib.tor_default_options(ctypes.byref(o))
+    o.workspace = 0x1000 + 16  # the kernels need a 256-byte aligned workspace
+    o.workspace_bytes = 1 << 20
+    bad.append(o)
+    o = _lib.tor_options()
+    lib.tor_default_options(ctypes.byref(o))
+    o.max_n = 1000
+    bad.append(o)
+    o = _lib.tor_options()
+    lib.tor_default_options(ctypes.byref(o))
+    o.accum = 7
+    bad.append(o)
+    for o in bad:
+        assert lib.tor_create(ctypes.byref(h), ctypes.byref(o)) == _lib.TOR_E_INVAL
+        assert not h.value
