@@ -572,8 +572,6 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
     __shared__ uint8_t srcDet[(1 << (BL + 1)) - 1];
     __shared__ uint32_t blkRec[NB(R - 1)];
     __shared__ unsigned long long nodeRec[(1 << BL) - 1];
-    __shared__ RT<S> sdet[MAX_N + 1];
-    __shared__ int sinc[MAX_N + 1];
 
     const int lane = threadIdx.x;
     build_tables<S, R, BL + 1, L>(srcOff, srcNB, srcDet, nodeRec, blkRec, lane);
@@ -600,6 +598,10 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
         const long long root = P.root_begin + ((long long)item - P.item_begin);
         const int N = P.N, k = P.k, LA = N - R, D = LA - k;
         const S *C = reinterpret_cast<const S *>(P.C);
+        // running determinants of the tier-A levels on the current path, in
+        // the stack's slot of level LA: that slot never holds a node when the
+        // root has more than one leaf, and only then is it used
+        RT<S> *sdet = reinterpret_cast<RT<S> *>(wscr + slot_off(N, LA));
         int bad = 0;
 
         // root: decisions on modes 0..k-1 given by the bits of root
@@ -665,7 +667,9 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                     s = wscr + slot_off(N, sl);
                     snb = NB(N - sl);
                     sd = sdet[sl];
-                    si = sinc[sl];
+                    // includes on the path down to level sl: the root's and
+                    // the tier-A decisions above sl, bits LA-1-l of x
+                    si = rinc + __popcll((unsigned long long)x >> (LA - sl));
                 }
                 // the deepest slot (level LA) is never the source of a later
                 // step: that child goes to LDS only; shallower ones also go to
@@ -675,10 +679,8 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                 elim_global<S>(s, snb, dst, bufB, NB(R), N - lvl, lane, pd, bad);
                 ldet = rmul(sd, pd);
                 linc = si + 1;
-                if (lane == 0) {
+                if (lane == 0)
                     sdet[lvl + 1] = ldet;
-                    sinc[lvl + 1] = linc;
-                }
             }
             __syncthreads();
             tierB<S, R, 1, BL + 1>(tb, ldet, lane, bad);

@@ -129,6 +129,9 @@ def model_tor(O: np.ndarray, T: int = 3, B: int = 6, k: int = 0, real: bool = Fa
                 else:
                     sl = LA - (((xr & -xr).bit_length() - 1) + t + 1)
                     s, sd, si = slots[sl], sdet[sl], sinc[sl]
+                    # the kernel does not store the count: it is the root's
+                    # includes plus the set bits of x above level sl
+                    assert si == rinc + bin(x >> (LA - sl)).count("1")
                 dst, pd = eliminate(s, N - lvl)
                 slots[lvl + 1] = dst
                 sdet[lvl + 1] = sd * pd

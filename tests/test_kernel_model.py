@@ -9,7 +9,8 @@ from paper_2109_04528_amd import inputs as gen
 
 
 # the complex path: T = 3 register modes, B = 6 (64 lanes), L = 2 lane levels
-@pytest.mark.parametrize("n,k", [(0, 0), (1, 0), (5, 0), (9, 0), (10, 1), (11, 2), (12, 3)])
+# (12, 0) walks three tier-A levels (stack slots, stored determinants)
+@pytest.mark.parametrize("n,k", [(0, 0), (1, 0), (5, 0), (9, 0), (10, 1), (11, 2), (12, 3), (12, 0)])
 def test_model_matches_oracle(n, k):
     O = gen.random_O(n, 3 + n, 0.5, 1.0, 0.7) if n else gen.vacuum_O(0)
     v, cnt, sabs = model_tor(O, 3, 6, k, L=2)
@@ -33,7 +34,7 @@ def test_model_product_state_closed_form():
 
 
 # the real path: T = 5, B = 6, L = 2
-@pytest.mark.parametrize("n,k", [(4, 0), (11, 0), (12, 1), (13, 2)])
+@pytest.mark.parametrize("n,k", [(4, 0), (11, 0), (12, 1), (13, 2), (14, 0)])
 def test_real_form_model_matches_oracle(n, k):
     O = gen.random_O(n, 50 + n, 0.3, 1.2, 0.9)
     v, cnt, sabs = model_tor(O, 5, 6, k, real=True, L=2)
@@ -45,7 +46,7 @@ def test_real_form_model_matches_oracle(n, k):
 
 
 # the double-double factor: real form, T = 3, B = 6, L = 2
-@pytest.mark.parametrize("n,k", [(6, 0), (9, 0), (11, 1), (12, 2)])
+@pytest.mark.parametrize("n,k", [(6, 0), (9, 0), (11, 1), (12, 2), (12, 0)])
 def test_quad_config_model_matches_oracle(n, k):
     O = gen.random_O(n, 70 + n, 0.3, 1.2, 0.9)
     v, cnt, _ = model_tor(O, 3, 6, k, real=True, L=2)
