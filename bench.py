@@ -13,7 +13,9 @@ reduction and the copy of the result.  The same step from a host matrix
 Printed as one JSON line, with
 * roofline: the recursive kernel's algorithmic FLOP (paper_2109_04528_amd/flops.py)
   over its average duration, measured with HIP events on the stream the kernel
-  runs on, against the MI355X FP64 vector peak;
+  runs on, against the MI355X FP64 vector peak; beside it the HBM traffic and
+  the FP64 FLOP the kernel issues, both from rocprofv3 counters recorded in
+  profiles/ for the current kernel sources;
 * plain: the per-subset-Cholesky comparison kernel on a sampled mask range;
 * cpu_baseline: the CPU oracle timed on a bounded subtree of the same workload;
 * with --serve, p50/p99 latency of a Poisson stream of mixed-n requests.
@@ -33,6 +35,7 @@ METRIC = "Tor evals/s + subset dets/s at n=30 FP64; p50/p99 latency, mixed-n str
 KERNEL_SOURCES = ["paper_2109_04528_amd/csrc/tor_kernels.hip", "paper_2109_04528_amd/csrc/tor_device.hpp",
                   "paper_2109_04528_amd/csrc/tor_internal.hpp"]
 TRAFFIC_FILE = "profiles/tor_main_real_n30_traffic.md"
+COUNTERS_FILE = "profiles/tor_main_real_n30_trace_and_counters.md"
 COPY_BYTES = 256 << 20  # calibration copy for the HBM counters
 
 
@@ -44,11 +47,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def stored_traffic():
-    """HBM bytes per launch of the recursive kernel measured with rocprofv3
-    (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size), valid only
-    while the kernel sources are the ones that were profiled."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+def stored_field(path, key):
+    """A figure recorded in a profile summary (a "- key: value" line), valid
+    only while the kernel sources hash to the summary's kernel_source_sha256."""
+    path = os.path.join(ROOT, path)
     if not os.path.exists(path):
         return None
     fields = {}
@@ -59,9 +61,25 @@ def stored_traffic():
     if fields.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
-        return float(fields["hbm_bytes_per_launch"])
+        return float(fields[key])
     except (KeyError, ValueError):
         return None
+
+
+def stored_traffic():
+    """HBM bytes per launch of the recursive kernel measured with rocprofv3
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size)."""
+    return stored_field(TRAFFIC_FILE, "hbm_bytes_per_launch")
+
+
+def stored_issued_flop():
+    """FP64 FLOP the recursive kernel issues per launch, from the
+    SQ_INSTS_VALU_{FMA,MUL,ADD}_F64 counters (64 lanes per instruction, an FMA
+    counting 2): the vector unit's own work, exclude lanes and masked lanes
+    included, as opposed to the algorithmic FLOP of the method."""
+    return stored_field(COUNTERS_FILE, "issued_fp64_flop_per_launch")
+
+
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
 
 
@@ -238,6 +256,10 @@ def main():
     real_path = r.path == 1
     flops = tor_flops(n, real=real_path)
     achieved = flops / (kernel_ms * 1e-3) / 1e12
+    # profiled figures hold for the real-path kernel on the n = 30 workload only
+    profiled = real_path and n == 30
+    traffic = stored_traffic() if profiled else None
+    issued = stored_issued_flop() if profiled else None
 
     plain = None
     if args.plain_masks > 0 and n <= 34:
@@ -376,9 +398,11 @@ def main():
         "tor": r.value,
         "cancellation_R": r.cancellation,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": stored_traffic() if real_path else None,
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "peak_measured": fma_tflops, "frac_of_measured": achieved / fma_tflops,
                      "flop_per_launch": flops,
+                     "issued_flop_per_launch": issued,
+                     "issued_frac": None if issued is None else issued / (kernel_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                      "kernel": "tor_main<double, T=5, B=6, L=2>" if real_path else "tor_main<c64, T=3, B=6, L=2>"},
         "plain": plain,
         "batch": batch,
