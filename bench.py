@@ -202,7 +202,7 @@ def main():
     import numpy as np
     import torch
     from paper_2109_04528_amd import TOR_FORCE_COMPLEX, TOR_INPUT_DEVICE, Context, inputs, workspace_size
-    from paper_2109_04528_amd.flops import tor_flops
+    from paper_2109_04528_amd.flops import plain_flops_per_subset, tor_flops
 
     n = args.n
     O = inputs.random_O(n, 0, 0.3, 1.2, 0.9)
@@ -268,7 +268,11 @@ def main():
         ctx.eval_plain(O, lo, lo + m)
         p = ctx.eval_plain(O, lo, lo + m)
         plain_dets = m / (p.device_ms * 1e-3)
+        plain_real = p.path == 1
+        plain_tflops = plain_dets * plain_flops_per_subset(n, real=plain_real) / 1e12
         plain = {"masks": m, "kernel_ms": p.device_ms, "subset_dets_per_s": plain_dets,
+                 "form": "real quadrature" if plain_real else "complex",
+                 "tflops": plain_tflops, "frac": plain_tflops / FP64_PEAK_TFLOPS,
                  "recursive_speedup": ((1 << n) / (kernel_ms * 1e-3)) / plain_dets}
         print("bench: plain comparison done", file=sys.stderr, flush=True)
 
@@ -310,10 +314,10 @@ def main():
         ra = ctx.eval(O24)
         ctx.eval_removal(O24)
         rr = ctx.eval_removal(O24)
-        rp = ctx.eval_plain(O24)
         with Context(device=0, stream=stream, workspace=ws, flags=TOR_FORCE_COMPLEX) as cc:
             cc.eval(O24)
             rc_ = cc.eval(O24)
+            rp = cc.eval_plain(O24)  # complex, as the removal order is
         compare = {"workload": "n=24, r~U[0.5,1], eta=0.7, seed 0 (2^24 subsets), kernel times",
                    "append_real_ms": ra.device_ms, "append_complex_ms": rc_.device_ms,
                    "removal_order_ms": rr.device_ms, "plain_ms": rp.device_ms,

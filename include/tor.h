@@ -140,10 +140,12 @@ int tor_eval_batch(tor_ctx *ctx, int count, const int *n, const double *const *O
                    const long *ld, tor_result *out);
 
 /* The comparison baseline (not the method): every subset gets a fresh Cholesky
- * (Algorithm 1) on the GPU, one wavefront per subset.  Sums the subsets whose
- * bitmask lies in [mask_begin, mask_end) (pass 0 and 2^n for all of them).
- * The positive-definiteness test covers the subsets of that range (the full
- * I - O only when its mask 2^n - 1 is in it). */
+ * (Algorithm 1) on the GPU, one wavefront per subset, in FP64 on the form the
+ * recursive kernel would use (the real quadrature form of a Gaussian-state
+ * matrix, else the complex matrix; TOR_FORCE_COMPLEX forces the latter).
+ * Sums the subsets whose bitmask lies in [mask_begin, mask_end) (pass 0 and
+ * 2^n for all of them); n <= 34.  The positive-definiteness test covers the
+ * subsets of that range (the full I - O only when its mask 2^n - 1 is in it). */
 int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld,
                    unsigned long long mask_begin, unsigned long long mask_end,
                    tor_result *out);

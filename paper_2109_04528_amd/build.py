@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtor.so")
 ARCH = os.environ.get("TOR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["tor_kernels.hip", "tor_stage.hip", "tor_probe.hip", "tor_runtime.cpp"]
+SOURCES = ["tor_kernels.hip", "tor_compare.hip", "tor_stage.hip", "tor_probe.hip", "tor_runtime.cpp"]
 
 
 def hipcc() -> str:

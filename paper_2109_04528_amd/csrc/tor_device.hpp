@@ -222,6 +222,31 @@ __device__ __forceinline__ ddr rsqrt_nr(ddr x)
     return fast2sum(y0, 0.5 * y0 * r);
 }
 
+// ---- node entries
+// entry e of block bi of a node whose granule arrays hold nb blocks
+template <class S>
+__device__ __forceinline__ S &blk(S *node, int nb, int bi, int e)
+{
+    return node[gpos((int)sizeof(S), nb, bi, e)];
+}
+template <class S>
+__device__ __forceinline__ const S &blk(const S *node, int nb, int bi, int e)
+{
+    return node[gpos((int)sizeof(S), nb, bi, e)];
+}
+
+// triangular index -> (a, b), a >= b, with a(a+1)/2 + b = bi: the mode block
+// of a block index (bidx), or the row and column of a packed entry (pidx)
+__device__ __forceinline__ void block_ab(int bi, int &a, int &b)
+{
+    a = (int)((sqrtf(8.0f * (float)bi + 1.0f) - 1.0f) * 0.5f);
+    if (a * (a + 1) / 2 > bi)
+        --a;
+    if ((a + 1) * (a + 2) / 2 <= bi)
+        ++a;
+    b = bi - a * (a + 1) / 2;
+}
+
 // ---- wave-uniform broadcast ------------------------------------------------
 // The value of the first active lane, in scalar registers.  Loop bounds and
 // exits built from it are provably uniform, so the compiler emits scalar

@@ -64,8 +64,9 @@ struct MainParams {
 };
 
 struct PlainParams {
-    const void *C;                // packed reversed matrix, n modes (no padding)
-    int n;
+    const void *C;                // packed reversed matrix of N modes
+    int n;                        // modes of the problem: subsets are masks below 2^n
+    int N;                        // modes of the staged form (N >= n; modes n.. are padding)
     unsigned long long mask_begin, mask_end;
     unsigned long long *counter;  // chunk queue head
     double *partials;             // 4 doubles per wave
@@ -147,7 +148,7 @@ constexpr int MAX_FIT = 8;  // persistent one-wave workgroups per CU, at most
 hipError_t launch_main(int path, bool dd, const MainParams &p, int grid, hipStream_t s);
 hipError_t launch_reduce(const ProblemDesc *probs, int nprob, double *results, bool dd, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, int count, hipStream_t s);
-hipError_t launch_plain(const PlainParams &p, int grid, hipStream_t s);
+hipError_t launch_plain(const PlainParams &p, bool real, int grid, hipStream_t s);
 hipError_t launch_removal(const RemovalParams &p, int grid, hipStream_t s);
 hipError_t launch_plain_reduce(const double *partials, int nwaves, double *result, hipStream_t s);
 hipError_t launch_math_probe(const double *x, double *out, int count, hipStream_t s);

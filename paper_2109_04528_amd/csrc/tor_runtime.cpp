@@ -1404,19 +1404,22 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long 
     if (!ctx || !out || n < 1 || n > 34 || mask_begin > mask_end || mask_end > (1ull << n) || !args_ok(ctx, n, O, ld))
         return TOR_E_INVAL;
     std::lock_guard<std::mutex> g(ctx->mu);
-    // the comparison kernels run on the complex matrix, unpadded
+    // the form the recursive kernel would use (the real quadrature form of a
+    // Gaussian-state matrix, else the complex matrix; TOR_FORCE_COMPLEX
+    // forces the latter), FP64, unpadded
     std::vector<StageIn> in(1);
     in[0].n = n;
     in[0].O = O;
     in[0].ld = ld;
     std::vector<Mat> mats;
     size_t end = 0;
-    const unsigned sfl = (stage_flags(ctx->opt.flags) & ~STAGE_DD) | STAGE_FORCE_CPLX;
+    const unsigned sfl = stage_flags(ctx->opt.flags) & ~STAGE_DD;
     int rc = stage_sync(ctx, in, (ctx->opt.flags & TOR_INPUT_DEVICE) != 0, sfl, 0, 0, mats, &end);
     if (rc != TOR_OK)
         return rc;
     if (mats[0].status != TOR_OK)
         return mats[0].status;
+    const bool real = mats[0].path == PATH_REAL;
     const int chunk = 16;
     // no more waves than chunks of the mask range
     const unsigned long long nchunks = (mask_end - mask_begin + chunk - 1) / chunk;
@@ -1435,6 +1438,7 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long 
     PlainParams pp{};
     pp.C = dC;
     pp.n = n;
+    pp.N = mats[0].N;
     pp.mask_begin = mask_begin;
     pp.mask_end = mask_end;
     pp.counter = dCounter;
@@ -1443,7 +1447,7 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long 
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev0, ctx->stream);
     if (e == hipSuccess)
-        e = launch_plain(pp, pgrid, ctx->stream);
+        e = launch_plain(pp, real, pgrid, ctx->stream);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev1, ctx->stream);
     if (e == hipSuccess)
@@ -1457,7 +1461,7 @@ int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long 
         return hip_status(e);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-    fill_result(mats[0], PATH_CPLX, h, ms, out);
+    fill_result(mats[0], mats[0].path, h, ms, out);
     out->subsets = mask_end - mask_begin;
     return out->status;
 }

@@ -39,13 +39,13 @@ def flops_per_subset(n: int, real: bool = False) -> float:
     return tor_flops(n, real) / float(1 << n)
 
 
-def plain_flops_per_subset(n: int) -> float:
+def plain_flops_per_subset(n: int, real: bool = False) -> float:
     """A fresh factorisation per subset: sum over subsets of the eliminations
-    of sizes d, d-1, ..., 1 for |Z| = d (complex path), averaged."""
+    of sizes d, d-1, ..., 1 for |Z| = d, averaged (real: the quadrature form)."""
     from math import comb
     tot = 0
     for d in range(n + 1):
-        c = sum(elim_cost(s) + 1 for s in range(1, d + 1)) + 2
+        c = sum(elim_cost(s, real) + 1 for s in range(1, d + 1)) + 2
         tot += comb(n, d) * c
     return tot / float(1 << n)
 

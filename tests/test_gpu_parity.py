@@ -232,6 +232,30 @@ def test_plain_kernel_against_oracle(ctx, n):
     assert abs(pr.value - math.fsum(ts)) <= term_bound(O, sum(abs(t) for t in ts))
 
 
+@pytest.mark.parametrize("n", [6, 12])
+def test_plain_kernel_real_and_complex_forms(ctx, n):
+    # a Gaussian-state matrix runs on the real quadrature form (padded to the
+    # recursive kernel's 11 modes when n is smaller); the forced complex form
+    # must give the same sum, and both the oracle's
+    from paper_2109_04528_amd import Context, TOR_FORCE_COMPLEX
+    O = gen.random_O(n, 310 + n, 0.4, 1.1, 0.8)
+    say(f"case plain real/complex n={n}")
+    pr = ctx.eval_plain(O)
+    with Context(device=0, flags=TOR_FORCE_COMPLEX) as cc:
+        pc = cc.eval_plain(O)
+        lo_, hi_ = 3, (1 << n) - 5
+        pcr = cc.eval_plain(O, lo_, hi_)
+    prr = ctx.eval_plain(O, lo_, hi_)
+    assert pr.path == 1 and pc.path == 2
+    q = orc.tor(O, mode=orc.QUAD)
+    tol = term_bound(O, q.sum_abs)
+    assert abs(pr.value - q.value) <= tol and abs(pc.value - q.value) <= tol
+    ts = [orc.det(O, Z)[1] for Z in range(lo_, hi_)]
+    want = math.fsum(ts)
+    tol_r = term_bound(O, sum(abs(t) for t in ts))
+    assert abs(prr.value - want) <= tol_r and abs(pcr.value - want) <= tol_r
+
+
 def test_error_codes(ctx):
     from paper_2109_04528_amd import TorError, TOR_E_INVAL, TOR_E_NOT_PD
     say("case error codes")
