@@ -75,6 +75,14 @@ class tor_result(ctypes.Structure):
     ]
 
 
+# the same layout as a numpy record, to read an array of results at once
+_RESULT_DTYPE = np.dtype({
+    "names": [f[0] for f in tor_result._fields_],
+    "formats": ["<f8", "<f8", "<f8", "<f8", "<u8", "<i4", "<i4", "<f4"],
+    "offsets": [getattr(tor_result, f[0]).offset for f in tor_result._fields_],
+    "itemsize": ctypes.sizeof(tor_result),
+})
+
 _lib = None
 
 
@@ -187,8 +195,17 @@ class TorResult:
         return cls(r.tor, r.tor_lo, r.sum_abs, r.err_est, int(r.subsets), r.status, r.path, r.device_ms)
 
 
+def _results(res, cnt: int) -> List["TorResult"]:
+    """TorResults of a tor_result array, read through one structured view."""
+    a = np.frombuffer(res, dtype=_RESULT_DTYPE, count=cnt)
+    return [TorResult(*row) for row in a.tolist()]
+
+
 def _host_c128(O) -> np.ndarray:
     """Marshal O (numpy array or torch tensor) to a contiguous host complex128 array."""
+    if (type(O) is np.ndarray and O.dtype == np.complex128 and O.ndim == 2 and O.flags.c_contiguous
+            and O.shape[0] == O.shape[1] and O.shape[0] % 2 == 0):
+        return O  # already in the form the library reads
     try:
         import torch  # noqa: F401
         if hasattr(O, "detach") and hasattr(O, "device"):
@@ -256,7 +273,7 @@ class Context:
             return (ptr if n else None), n, ld, O
         A = _host_c128(O)
         n = A.shape[0] // 2
-        return (A.ctypes.data if n else None), n, max(2 * n, 1), A
+        return (A.__array_interface__["data"][0] if n else None), n, max(2 * n, 1), A
 
     def close(self):
         if getattr(self, "_h", None):
@@ -293,7 +310,7 @@ class Context:
         rc = self._lib.tor_eval_batch(self._h, cnt, ns, ptrs, lds, res)
         if check and rc != TOR_OK:
             raise TorError(rc, "tor_eval_batch")
-        return [TorResult.from_c(res[i]) for i in range(cnt)]
+        return _results(res, cnt)
 
     def eval_plain(self, O, mask_begin: int = 0, mask_end: Optional[int] = None,
                    check: bool = True) -> TorResult:
