@@ -84,7 +84,7 @@ extern "C" {
  * form only: a matrix without the Gaussian-state block structure is rejected
  * with TOR_E_INVAL; tor_create rejects it together with TOR_FORCE_COMPLEX.
  * The input itself is FP64; I - O and the real form are formed from it in
- * double-double (exactly, or rounded to 2^-106).  About 20x the FP64 time. */
+ * double-double (exactly, or rounded to 2^-106).  About 9x the FP64 time. */
 #define TOR_FACTOR_DD 0x8u
 
 typedef struct tor_ctx tor_ctx;
@@ -187,8 +187,10 @@ int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count,
 
 /* Serving: enqueue one Torontonian request.  O is copied before return and
  * staged on the device when the request is admitted; a staging error
- * (TOR_E_INVAL) or TOR_E_NOT_PD is reported in the polled result's status.
- * *ticket identifies it for tor_poll.  TOR_E_BUSY when admission is refused. */
+ * (TOR_E_INVAL), TOR_E_NOT_PD, or TOR_E_NOMEM when the device pool of the
+ * serving loop cannot be allocated, is reported in the polled result's status.
+ * *ticket identifies it for tor_poll.  TOR_E_BUSY when admission is refused;
+ * TOR_E_NOMEM at once for a request larger than the whole pool. */
 int tor_submit(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long *ticket);
 
 /* Serving: non-blocking.  TOR_OK and *out filled once the request is done
