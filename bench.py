@@ -201,7 +201,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2109_04528_amd import TOR_FORCE_COMPLEX, TOR_INPUT_DEVICE, Context, inputs, workspace_size
+    from paper_2109_04528_amd import TOR_FORCE_COMPLEX, TOR_INPUT_DEVICE, TOR_TUNE_REAL, Context, inputs, workspace_size
     from paper_2109_04528_amd.flops import plain_flops_per_subset, tor_flops
 
     n = args.n
@@ -291,10 +291,27 @@ def main():
             res = ctx.eval_batch(mats)
             calls.append(time.perf_counter() - t0)
         sec = float(np.median(calls))
+        # the same calls on a context whose autotuner has picked (k, waves/CU)
+        # for every size of the mix on this device (tuning time reported apart)
+        with Context(device=0, stream=stream) as tctx:
+            ta = time.perf_counter()
+            tctx.autotune(12, 26, TOR_TUNE_REAL)
+            tune_s = time.perf_counter() - ta
+            gc.collect()
+            tctx.eval_batch(mats)
+            torch.cuda.synchronize()
+            tcalls = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                tres = tctx.eval_batch(mats)
+                tcalls.append(time.perf_counter() - t0)
+        tsec = float(np.median(tcalls))
         subsets = sum(1 << n for n in ns)
-        batch = {"matrices": args.batch, "n_range": [12, 26], "seconds": sec,
-                 "tor_per_s": args.batch / sec, "subset_dets_per_s": subsets / sec,
-                 "kernel_ms": max(r.device_ms for r in res), "launches": len({r.path for r in res})}
+        batch = {"matrices": args.batch, "n_range": [12, 26], "seconds": tsec,
+                 "tor_per_s": args.batch / tsec, "subset_dets_per_s": subsets / tsec,
+                 "kernel_ms": max(r.device_ms for r in tres), "launches": len({r.path for r in tres}),
+                 "autotuned": True, "autotune_s": tune_s,
+                 "untuned_seconds": sec, "untuned_kernel_ms": max(r.device_ms for r in res)}
         print("bench: batch done", file=sys.stderr, flush=True)
 
     big = None
