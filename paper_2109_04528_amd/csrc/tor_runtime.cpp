@@ -162,7 +162,12 @@ int choose_k(const tor_ctx *ctx, int N, int path)
     int g = 1;
     while ((1 << g) < default_grid(ctx, path))
         ++g;
-    return std::min(LA, g + 2);
+    // about 4 roots per persistent wave on the real path; the 16-byte paths
+    // (complex, double-double) have leaves a quarter the size and slower
+    // subsets, and end their launches more evenly with about 8 (measured
+    // with the autotuner at n = 30: complex 10.0 ms at k = g + 3 against
+    // 10.9 at g + 2, double-double 24.1 against 24.9)
+    return std::min(LA, path == PATH_REAL ? g + 2 : g + 3);
 }
 
 int ensure_ws(tor_ctx *ctx, size_t bytes)
