@@ -166,8 +166,12 @@ int choose_k(const tor_ctx *ctx, int N, int path)
     // (complex, double-double) have leaves a quarter the size and slower
     // subsets, and end their launches more evenly with about 8 (measured
     // with the autotuner at n = 30: complex 10.0 ms at k = g + 3 against
-    // 10.9 at g + 2, double-double 24.1 against 24.9)
-    return std::min(LA, path == PATH_REAL ? g + 2 : g + 3);
+    // 10.9 at g + 2, double-double 24.1 against 24.9), when a root then
+    // still holds at least 4 tier-A leaves (complex n = 24 keeps k = g + 2:
+    // 0.33 ms, against 0.44 at k = 14)
+    if (path != PATH_REAL && LA - 2 >= g + 3)
+        return g + 3;
+    return std::min(LA, g + 2);
 }
 
 int ensure_ws(tor_ctx *ctx, size_t bytes)
