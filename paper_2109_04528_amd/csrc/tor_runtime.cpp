@@ -171,6 +171,13 @@ int choose_k(const tor_ctx *ctx, int N, int path)
     // 0.33 ms, against 0.44 at k = 14)
     if (path != PATH_REAL && LA - 2 >= g + 3)
         return g + 3;
+    // on the real path at least one root per wave (2^g), up to 4 per wave
+    // (g + 2), but no more roots than leave each one 64 tier-A leaves: every
+    // root first recomputes its k eliminations in global memory, which a
+    // short root does not amortise (autotuner at n = 26: k = 11, 0.26 ms,
+    // against 0.34 at k = 13; n = 28: 0.83 against 0.91)
+    if (path == PATH_REAL)
+        return std::min(LA, std::max(g, std::min(g + 2, LA - 6)));
     return std::min(LA, g + 2);
 }
 
