@@ -162,23 +162,18 @@ int choose_k(const tor_ctx *ctx, int N, int path)
     int g = 1;
     while ((1 << g) < default_grid(ctx, path))
         ++g;
-    // about 4 roots per persistent wave on the real path; the 16-byte paths
-    // (complex, double-double) have leaves a quarter the size and slower
-    // subsets, and end their launches more evenly with about 8 (measured
-    // with the autotuner at n = 30: complex 10.0 ms at k = g + 3 against
-    // 10.9 at g + 2, double-double 24.1 against 24.9), when a root then
-    // still holds at least 4 tier-A leaves (complex n = 24 keeps k = g + 2:
-    // 0.33 ms, against 0.44 at k = 14)
-    if (path != PATH_REAL && LA - 2 >= g + 3)
-        return g + 3;
-    // on the real path at least one root per wave (2^g), up to 4 per wave
-    // (g + 2), but no more roots than leave each one 64 tier-A leaves: every
-    // root first recomputes its k eliminations in global memory, which a
-    // short root does not amortise (autotuner at n = 26: k = 11, 0.26 ms,
-    // against 0.34 at k = 13; n = 28: 0.83 against 0.91)
-    if (path == PATH_REAL)
-        return std::min(LA, std::max(g, std::min(g + 2, LA - 6)));
-    return std::min(LA, g + 2);
+    // Every root first recomputes its k eliminations in global memory, which a
+    // short root does not amortise, so no more roots than leave each about
+    // 64 tier-A leaves (k <= LA - 6), within [g, g + 2] on the real path (one
+    // to four roots per wave of the 2^g grid) and [g - 1, g + 3] on the
+    // 16-byte paths, whose leaves are a quarter the size and whose launches
+    // end more evenly with more roots.  The autotuner's picks this follows:
+    // real n = 26 k = 11 (0.26 ms against 0.34 at k = 13), n = 30 k = 13;
+    // complex n = 24 k = 10 (0.26 against 0.33 at 13), n = 30 k = 14 (10.1
+    // against 10.9 at 13); double-double n = 30 k = 14 (24.1 against 24.9).
+    const int lo = path == PATH_REAL ? g : g - 1;
+    const int hi = path == PATH_REAL ? g + 2 : g + 3;
+    return std::min(LA, std::max(lo, std::min(hi, LA - 6)));
 }
 
 int ensure_ws(tor_ctx *ctx, size_t bytes)
