@@ -163,8 +163,11 @@ int tor_eval_removal(tor_ctx *ctx, int n, const double *O, long ld, tor_result *
 /* Verification aid: the recursive path's per-subtree partial sums.  Root r is
  * the include/exclude decision on modes 0..k-1 given by the bits of r (bit i =
  * mode i included); partial r sums the subsets Z with Z & (2^k - 1) == r.
- * *k_out receives k; partials receives 2^k (hi, lo, sum_abs) triples and must
- * hold 3 * 2^k doubles (k <= k_max; fails with TOR_E_INVAL otherwise). */
+ * The split depth is k = min(k_max, modes above the kernel's LDS and register
+ * levels: n - 11 on the real path, n - 9 on the complex and double-double
+ * paths, at least 0), not the context's own choice of k.  *k_out receives k;
+ * partials receives 2^k (hi, lo, sum_abs) triples and must hold 3 * 2^k
+ * doubles (0 <= k_max <= 30, else TOR_E_INVAL). */
 int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max,
                       int *k_out, double *partials, tor_result *out);
 
