@@ -4,7 +4,9 @@ Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this module.  It loads ``libtororacle.so`` (built from
 ``tor_oracle.c`` by ``oracle/build.py``) and shares nothing with the GPU
 library.  What it computes is the plain definition of the Torontonian (Eq. 2)
-with a fresh Cholesky (Algorithm 1) per subset; the C source documents it.
+with a fresh factorisation of every subset's matrix (the square-root-free
+form of the Cholesky factor of Sec. 2, det = product of the pivots); the C
+source documents it.
 """
 from __future__ import annotations
 
@@ -19,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libtororacle.so")
 
 F64 = 0
 QUAD = 1
+LD = 2  # x87 extended precision (64-bit significand)
 
 _lib = None
 
@@ -52,6 +55,7 @@ class OracleResult:
     lo: float
     sum_abs: float
     count: int
+    sum_sq: float = float("nan")  # sum of t^2
 
     @property
     def value(self) -> float:
@@ -75,13 +79,13 @@ def tor(O, mode: int = F64, threads: int = 0, fix_mask: int = 0, fix_val: int = 
     """Sum of (-1)^(n-|Z|)/sqrt(det (I-O)_Z) over Z with (Z & fix_mask) == fix_val."""
     O = _as_c128(O)
     n = O.shape[0] // 2
-    out = (ctypes.c_double * 4)()
+    out = (ctypes.c_double * 5)()
     rc = _load().oracle_tor(n, O.ctypes.data if n else None, max(2 * n, 1), mode, threads,
                             fix_mask, fix_val, out)
     if rc != 0:
         raise OracleError({-1: "invalid argument", -2: "I - O not positive definite",
                            -3: "out of memory"}.get(rc, str(rc)))
-    return OracleResult(out[0], out[1], out[2], int(out[3]))
+    return OracleResult(out[0], out[1], out[2], int(out[3]), out[4])
 
 
 def det(O, Z: int, mode: int = F64):

@@ -11,21 +11,31 @@
  *     Tor(O) = sum over Z subset {0..n-1} of (-1)^(n-|Z|) / sqrt(det(I - O)_Z)
  *
  * where (I - O)_Z keeps rows and columns {i, i+n : i in Z} (mode i owns the
- * pair a_i, a_i^dagger in block order).  Each determinant comes from a fresh
- * Cholesky decomposition of that submatrix (Algorithm 1 of the paper, row by
- * row: off-diagonal L_ij by forward substitution, then L_ii as the square root
- * of the remaining diagonal), and det = prod |L_ii|^2 (Sec. 2).  The empty
- * subset contributes (-1)^n, so n = 0 gives 1.
+ * pair a_i, a_i^dagger in block order).  The empty subset contributes
+ * (-1)^n, so n = 0 gives 1.
  *
- * Only the lower triangle of (I - O) is read, as Algorithm 1 needs.  Rows of
- * the submatrix are taken in increasing original index, so every element read
- * lies in the lower triangle of I - O.
+ * Determinants.  Sec. 2 takes det A = prod |L_ii|^2 from the Cholesky factor
+ * A = L L^H of a Hermitian positive definite A (Algorithm 1 defines L).  Here
+ * every subset's matrix gets a fresh factorisation in its square-root-free
+ * form, by Gaussian elimination on the lower triangle: eliminating column k
+ * with the pivot p = A_kk replaces the trailing block by its Schur complement
+ * A_ij - A_ik conj(A_jk) / p.  The pivots are the squared diagonal entries
+ * |L_kk|^2 of the Cholesky factor, so det = prod p_k, and all of them are
+ * positive exactly when A is positive definite (Sylvester's criterion);
+ * a pivot that is not positive is reported as ORACLE_ENOTPD.  Only the lower
+ * triangle of (I - O) is read: rows of the submatrix are taken in increasing
+ * original index, so every element read lies in the lower triangle of I - O.
  *
- * Two precisions:
- *   ORACLE_F64  : FP64 Cholesky, FP64 determinant and term, terms summed in
- *                 __float128 (so summation adds no error on top of the FP64
- *                 per-term rounding);
- *   ORACLE_QUAD : everything in __float128 (input converted exactly).
+ * Three precisions:
+ *   ORACLE_F64  : FP64 elimination, determinant and term;
+ *   ORACLE_QUAD : everything in __float128 (input converted exactly);
+ *   ORACLE_LD   : everything in the x87 extended format (64-bit significand;
+ *                 input converted exactly), the reference where __float128
+ *                 is too slow (2^30 subsets) and FP64 too coarse.
+ * In every mode the terms are summed in __float128, so summation adds no
+ * error on top of the per-term rounding.  Beside the sum the oracle reports
+ * sum |t| (the cancellation R = sum |t| / |Tor|) and sum t^2, whose square
+ * root scales the spread of independent per-term rounding errors.
  *
  * Subsets are split over POSIX threads in contiguous ranges; the per-thread
  * partial sums are combined in thread order.
@@ -43,6 +53,7 @@
 
 #define ORACLE_F64 0
 #define ORACLE_QUAD 1
+#define ORACLE_LD 2
 
 #define ORACLE_OK 0
 #define ORACLE_EINVAL (-1)
@@ -50,79 +61,50 @@
 #define ORACLE_ENOMEM (-3)
 
 typedef __float128 q_t;
+typedef long double ld_t;
 
-/* ---- one determinant, FP64 ------------------------------------------------ */
-
-/* C is I - O as interleaved (re, im) doubles, 2n x 2n, leading dim ldc complex.
- * idx[0..m) are increasing row indices.  L is m*m complex scratch (lower part).
- * Returns 0 and det in *det, or ORACLE_ENOTPD. */
-static int det_f64(const double *C, long ldc, const int *idx, int m, double *L,
-                   double *det)
-{
-    double d = 1.0;
-    for (int i = 0; i < m; i++) {
-        const double *crow = C + 2 * ((long)idx[i] * ldc);
-        double *li = L + 2 * (long)i * m;
-        for (int j = 0; j < i; j++) {
-            const double *lj = L + 2 * (long)j * m;
-            double sr = crow[2 * idx[j]], si = crow[2 * idx[j] + 1];
-            for (int k = 0; k < j; k++) {
-                /* s -= L_ik * conj(L_jk) */
-                double ar = li[2 * k], ai = li[2 * k + 1];
-                double br = lj[2 * k], bi = lj[2 * k + 1];
-                sr -= ar * br + ai * bi;
-                si -= ai * br - ar * bi;
-            }
-            double ljj = lj[2 * j]; /* real, positive */
-            li[2 * j] = sr / ljj;
-            li[2 * j + 1] = si / ljj;
-        }
-        double s = crow[2 * idx[i]];
-        for (int k = 0; k < i; k++)
-            s -= li[2 * k] * li[2 * k] + li[2 * k + 1] * li[2 * k + 1];
-        if (!(s > 0.0))
-            return ORACLE_ENOTPD;
-        d *= s; /* |L_ii|^2 */
-        li[2 * i] = sqrt(s);
-        li[2 * i + 1] = 0.0;
+/* ---- one determinant --------------------------------------------------------
+ *
+ * C is I - O as interleaved (re, im) pairs of type T, 2n x 2n, leading dim ldc
+ * complex.  idx[0..m) are increasing row indices.  W is m*m complex scratch:
+ * the submatrix's lower triangle is copied into it and eliminated in place.
+ * Returns ORACLE_OK and det in *det, or ORACLE_ENOTPD.  The same elimination
+ * is instantiated for each precision. */
+#define DEFINE_DET(NAME, T)                                                      \
+    static int NAME(const T *C, long ldc, const int *idx, int m, T *W, T *det)   \
+    {                                                                            \
+        for (int i = 0; i < m; i++)                                              \
+            for (int j = 0; j <= i; j++) {                                       \
+                const T *c = C + 2 * ((long)idx[i] * ldc + idx[j]);              \
+                W[2 * ((long)i * m + j)] = c[0];                                 \
+                W[2 * ((long)i * m + j) + 1] = c[1];                             \
+            }                                                                    \
+        T d = 1;                                                                 \
+        for (int k = 0; k < m; k++) {                                            \
+            const T p = W[2 * ((long)k * m + k)]; /* the diagonal is real */     \
+            if (!(p > 0))                                                        \
+                return ORACLE_ENOTPD;                                            \
+            d *= p;                                                              \
+            for (int i = k + 1; i < m; i++) {                                    \
+                /* multiplier of row i: A_ik / p */                              \
+                const T lr = W[2 * ((long)i * m + k)] / p;                       \
+                const T li = W[2 * ((long)i * m + k) + 1] / p;                   \
+                for (int j = k + 1; j <= i; j++) {                               \
+                    /* A_ij -= (A_ik / p) conj(A_jk) */                          \
+                    const T br = W[2 * ((long)j * m + k)];                       \
+                    const T bi = W[2 * ((long)j * m + k) + 1];                   \
+                    W[2 * ((long)i * m + j)] -= lr * br + li * bi;               \
+                    W[2 * ((long)i * m + j) + 1] -= li * br - lr * bi;           \
+                }                                                                \
+            }                                                                    \
+        }                                                                        \
+        *det = d;                                                                \
+        return ORACLE_OK;                                                        \
     }
-    *det = d;
-    return ORACLE_OK;
-}
 
-/* ---- one determinant, __float128 ----------------------------------------- */
-
-static int det_quad(const q_t *C, long ldc, const int *idx, int m, q_t *L, q_t *det)
-{
-    q_t d = 1;
-    for (int i = 0; i < m; i++) {
-        const q_t *crow = C + 2 * ((long)idx[i] * ldc);
-        q_t *li = L + 2 * (long)i * m;
-        for (int j = 0; j < i; j++) {
-            const q_t *lj = L + 2 * (long)j * m;
-            q_t sr = crow[2 * idx[j]], si = crow[2 * idx[j] + 1];
-            for (int k = 0; k < j; k++) {
-                q_t ar = li[2 * k], ai = li[2 * k + 1];
-                q_t br = lj[2 * k], bi = lj[2 * k + 1];
-                sr -= ar * br + ai * bi;
-                si -= ai * br - ar * bi;
-            }
-            q_t ljj = lj[2 * j];
-            li[2 * j] = sr / ljj;
-            li[2 * j + 1] = si / ljj;
-        }
-        q_t s = crow[2 * idx[i]];
-        for (int k = 0; k < i; k++)
-            s -= li[2 * k] * li[2 * k] + li[2 * k + 1] * li[2 * k + 1];
-        if (!(s > 0))
-            return ORACLE_ENOTPD;
-        d *= s;
-        li[2 * i] = sqrtq(s);
-        li[2 * i + 1] = 0;
-    }
-    *det = d;
-    return ORACLE_OK;
-}
+DEFINE_DET(det_f64, double)
+DEFINE_DET(det_ld, ld_t)
+DEFINE_DET(det_quad, q_t)
 
 /* rows {i, i+n : i in Z} in increasing order */
 static int subset_rows(int n, uint64_t Z, int *idx)
@@ -137,16 +119,60 @@ static int subset_rows(int n, uint64_t Z, int *idx)
     return m;
 }
 
+/* I - O of one precision (full square copy; the lower triangle is what is
+ * read) */
+typedef struct {
+    double *f64;
+    ld_t *ld;
+    q_t *q;
+} cmat_t;
+
+/* The signed term (-1)^(n-|Z|) / sqrt(det) of one subset, rounded to the
+ * mode's precision and returned exactly as __float128; W is scratch of the
+ * mode's type. */
+static int subset_term(int n, int mode, const cmat_t *C, const int *idx, int m, void *W, q_t *t)
+{
+    const int N = 2 * n;
+    const int neg = (n - m / 2) & 1;
+    if (m == 0) {
+        *t = neg ? -1 : 1;
+        return ORACLE_OK;
+    }
+    if (mode == ORACLE_F64) {
+        double det;
+        if (det_f64(C->f64, N, idx, m, (double *)W, &det) != ORACLE_OK)
+            return ORACLE_ENOTPD;
+        const double td = 1.0 / sqrt(det);
+        *t = (q_t)(neg ? -td : td);
+    } else if (mode == ORACLE_LD) {
+        ld_t det;
+        if (det_ld(C->ld, N, idx, m, (ld_t *)W, &det) != ORACLE_OK)
+            return ORACLE_ENOTPD;
+        const ld_t tl = 1.0L / sqrtl(det);
+        *t = (q_t)(neg ? -tl : tl);
+    } else {
+        q_t det;
+        if (det_quad(C->q, N, idx, m, (q_t *)W, &det) != ORACLE_OK)
+            return ORACLE_ENOTPD;
+        const q_t tq = 1 / sqrtq(det);
+        *t = neg ? -tq : tq;
+    }
+    return ORACLE_OK;
+}
+
+static size_t scalar_size(int mode)
+{
+    return mode == ORACLE_F64 ? sizeof(double) : mode == ORACLE_LD ? sizeof(ld_t) : sizeof(q_t);
+}
+
 /* ---- threaded sum ---------------------------------------------------------- */
 
 typedef struct {
     int n, mode;
-    const double *C64; /* I - O, FP64, ld = 2n */
-    const q_t *Cq;     /* I - O, quad,  ld = 2n */
+    const cmat_t *C;
     uint64_t free_mask, fix_val;
-    int nfree;
     uint64_t lo, hi; /* range of free-bit counters */
-    q_t sum, sum_abs;
+    q_t sum, sum_abs, sum_sq;
     uint64_t count;
     int status;
 } job_t;
@@ -169,71 +195,77 @@ static void *run_job(void *arg)
     job_t *jb = (job_t *)arg;
     int n = jb->n, N = 2 * n;
     int *idx = (int *)malloc(sizeof(int) * (N > 0 ? N : 1));
-    double *L64 = NULL;
-    q_t *Lq = NULL;
-    if (jb->mode == ORACLE_F64)
-        L64 = (double *)malloc(sizeof(double) * 2 * (size_t)(N > 0 ? N * N : 1));
-    else
-        Lq = (q_t *)malloc(sizeof(q_t) * 2 * (size_t)(N > 0 ? N * N : 1));
-    if (!idx || (!L64 && !Lq)) {
+    void *W = malloc(2 * scalar_size(jb->mode) * (size_t)(N > 0 ? N * N : 1));
+    if (!idx || !W) {
         jb->status = ORACLE_ENOMEM;
-        free(idx); free(L64); free(Lq);
+        free(idx);
+        free(W);
         return NULL;
     }
-    q_t sum = 0, sum_abs = 0;
+    q_t sum = 0, sum_abs = 0, sum_sq = 0;
     for (uint64_t c = jb->lo; c < jb->hi; c++) {
         uint64_t Z = deposit(c, jb->free_mask) | jb->fix_val;
         int m = subset_rows(n, Z, idx);
-        int sign_neg = ((n - m / 2) & 1);
         q_t t;
-        if (jb->mode == ORACLE_F64) {
-            double det = 1.0;
-            if (m > 0 && det_f64(jb->C64, N, idx, m, L64, &det) != ORACLE_OK) {
-                jb->status = ORACLE_ENOTPD;
-                break;
-            }
-            double td = 1.0 / sqrt(det);
-            t = (q_t)(sign_neg ? -td : td);
-        } else {
-            q_t det = 1;
-            if (m > 0 && det_quad(jb->Cq, N, idx, m, Lq, &det) != ORACLE_OK) {
-                jb->status = ORACLE_ENOTPD;
-                break;
-            }
-            q_t tq = 1 / sqrtq(det);
-            t = sign_neg ? -tq : tq;
+        if (subset_term(n, jb->mode, jb->C, idx, m, W, &t) != ORACLE_OK) {
+            jb->status = ORACLE_ENOTPD;
+            break;
         }
         sum += t;
         sum_abs += (t < 0 ? -t : t);
+        sum_sq += t * t;
         jb->count++;
     }
     jb->sum = sum;
     jb->sum_abs = sum_abs;
-    free(idx); free(L64); free(Lq);
+    jb->sum_sq = sum_sq;
+    free(idx);
+    free(W);
     return NULL;
 }
 
-/* Build C = I - O (full square copy, lower triangle is what is read). */
-static void make_c(int n, const double *O, long ld, double *C64, q_t *Cq)
+/* Build C = I - O in the mode's precision; each input double is converted
+ * exactly, and 1 - o on the diagonal is rounded once in that precision. */
+static int make_c(int n, const double *O, long ld, int mode, cmat_t *C)
 {
-    int N = 2 * n;
+    const int N = 2 * n;
+    const size_t cnt = 2 * (size_t)N * N;
+    memset(C, 0, sizeof(*C));
+    if (mode == ORACLE_F64)
+        C->f64 = (double *)malloc(sizeof(double) * cnt);
+    else if (mode == ORACLE_LD)
+        C->ld = (ld_t *)malloc(sizeof(ld_t) * cnt);
+    else
+        C->q = (q_t *)malloc(sizeof(q_t) * cnt);
+    if (!C->f64 && !C->ld && !C->q)
+        return ORACLE_ENOMEM;
     for (int i = 0; i < N; i++)
         for (int j = 0; j < N; j++) {
-            double re = -O[2 * ((long)i * ld + j)];
-            double im = -O[2 * ((long)i * ld + j) + 1];
-            if (C64) {
-                C64[2 * ((long)i * N + j)] = (i == j ? 1.0 - O[2 * ((long)i * ld + j)] : re);
-                C64[2 * ((long)i * N + j) + 1] = im;
-            }
-            if (Cq) {
-                /* exact conversion of the input, then 1 - o in quad */
-                q_t ore = (q_t)O[2 * ((long)i * ld + j)];
-                q_t oim = (q_t)O[2 * ((long)i * ld + j) + 1];
-                Cq[2 * ((long)i * N + j)] = (i == j ? (q_t)1 - ore : -ore);
-                Cq[2 * ((long)i * N + j) + 1] = -oim;
+            const double ore = O[2 * ((long)i * ld + j)];
+            const double oim = O[2 * ((long)i * ld + j) + 1];
+            const size_t at = 2 * ((size_t)i * N + j);
+            if (C->f64) {
+                C->f64[at] = i == j ? 1.0 - ore : -ore;
+                C->f64[at + 1] = -oim;
+            } else if (C->ld) {
+                C->ld[at] = i == j ? 1.0L - (ld_t)ore : -(ld_t)ore;
+                C->ld[at + 1] = -(ld_t)oim;
+            } else {
+                C->q[at] = i == j ? (q_t)1 - (q_t)ore : -(q_t)ore;
+                C->q[at + 1] = -(q_t)oim;
             }
         }
+    return ORACLE_OK;
 }
+
+static void free_c(cmat_t *C)
+{
+    free(C->f64);
+    free(C->ld);
+    free(C->q);
+}
+
+static int mode_ok(int mode) { return mode == ORACLE_F64 || mode == ORACLE_QUAD || mode == ORACLE_LD; }
 
 /*
  * oracle_tor: sum over subsets Z with (Z & fix_mask) == fix_val.
@@ -241,30 +273,21 @@ static void make_c(int n, const double *O, long ld, double *C64, q_t *Cq)
  *   out[0], out[1] : the sum as a double-double (hi, lo)
  *   out[2]  : sum of |term|
  *   out[3]  : number of subsets summed
+ *   out[4]  : sum of term^2
  * Returns ORACLE_OK, ORACLE_EINVAL, ORACLE_ENOTPD or ORACLE_ENOMEM.
  */
 int oracle_tor(int n, const double *O, long ld, int mode, int nthreads,
                uint64_t fix_mask, uint64_t fix_val, double *out)
 {
-    if (n < 0 || n > 62 || !out || (n > 0 && (!O || ld < 2 * n)))
+    if (n < 0 || n > 62 || !out || (n > 0 && (!O || ld < 2 * n)) || !mode_ok(mode))
         return ORACLE_EINVAL;
-    if (mode != ORACLE_F64 && mode != ORACLE_QUAD)
-        return ORACLE_EINVAL;
-    uint64_t full = (n == 64) ? ~0ull : ((1ull << n) - 1);
+    uint64_t full = (1ull << n) - 1;
     if ((fix_mask & ~full) || (fix_val & ~fix_mask))
         return ORACLE_EINVAL;
-    int N = 2 * n;
-    double *C64 = NULL;
-    q_t *Cq = NULL;
-    if (n > 0) {
-        if (mode == ORACLE_F64)
-            C64 = (double *)malloc(sizeof(double) * 2 * (size_t)N * N);
-        else
-            Cq = (q_t *)malloc(sizeof(q_t) * 2 * (size_t)N * N);
-        if (!C64 && !Cq)
-            return ORACLE_ENOMEM;
-        make_c(n, O, ld, C64, Cq);
-    }
+    cmat_t C;
+    memset(&C, 0, sizeof(C));
+    if (n > 0 && make_c(n, O, ld, mode, &C) != ORACLE_OK)
+        return ORACLE_ENOMEM;
     uint64_t free_mask = full & ~fix_mask;
     int nfree = __builtin_popcountll(free_mask);
     uint64_t total = 1ull << nfree;
@@ -276,18 +299,20 @@ int oracle_tor(int n, const double *O, long ld, int mode, int nthreads,
         nthreads = (int)total;
     job_t *jobs = (job_t *)calloc((size_t)nthreads, sizeof(job_t));
     pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
-    if (!jobs || !th) {
-        free(jobs); free(th); free(C64); free(Cq);
+    int *started = (int *)calloc((size_t)nthreads, sizeof(int));
+    if (!jobs || !th || !started) {
+        free(jobs);
+        free(th);
+        free(started);
+        free_c(&C);
         return ORACLE_ENOMEM;
     }
     for (int t = 0; t < nthreads; t++) {
         jobs[t].n = n;
         jobs[t].mode = mode;
-        jobs[t].C64 = C64;
-        jobs[t].Cq = Cq;
+        jobs[t].C = &C;
         jobs[t].free_mask = free_mask;
         jobs[t].fix_val = fix_val;
-        jobs[t].nfree = nfree;
         jobs[t].lo = total / nthreads * t + (t < (int)(total % nthreads) ? t : total % nthreads);
         jobs[t].hi = jobs[t].lo + total / nthreads + (t < (int)(total % nthreads) ? 1 : 0);
     }
@@ -295,22 +320,24 @@ int oracle_tor(int n, const double *O, long ld, int mode, int nthreads,
     if (nthreads == 1) {
         run_job(&jobs[0]);
     } else {
-        for (int t = 0; t < nthreads; t++)
-            if (pthread_create(&th[t], NULL, run_job, &jobs[t]) != 0) {
+        for (int t = 0; t < nthreads; t++) {
+            if (pthread_create(&th[t], NULL, run_job, &jobs[t]) == 0)
+                started[t] = 1;
+            else
                 run_job(&jobs[t]);
-                th[t] = 0;
-            }
+        }
         for (int t = 0; t < nthreads; t++)
-            if (th[t])
+            if (started[t])
                 pthread_join(th[t], NULL);
     }
-    q_t sum = 0, sum_abs = 0;
+    q_t sum = 0, sum_abs = 0, sum_sq = 0;
     uint64_t count = 0;
     for (int t = 0; t < nthreads; t++) {
         if (jobs[t].status != ORACLE_OK)
             status = jobs[t].status;
         sum += jobs[t].sum;
         sum_abs += jobs[t].sum_abs;
+        sum_sq += jobs[t].sum_sq;
         count += jobs[t].count;
     }
     double hi = (double)sum;
@@ -319,58 +346,62 @@ int oracle_tor(int n, const double *O, long ld, int mode, int nthreads,
     out[1] = lo;
     out[2] = (double)sum_abs;
     out[3] = (double)count;
-    free(jobs); free(th); free(C64); free(Cq);
+    out[4] = (double)sum_sq;
+    free(jobs);
+    free(th);
+    free(started);
+    free_c(&C);
     return status;
 }
 
 /*
  * oracle_det: det((I - O)_Z) for one subset Z (bitmask over modes), by the same
- * fresh Cholesky.  out[0] = det (rounded to double), out[1] = the signed term
+ * fresh elimination.  out[0] = det (rounded to double), out[1] = the signed term
  * (-1)^(n-|Z|)/sqrt(det) rounded to double.
  */
 int oracle_det(int n, const double *O, long ld, uint64_t Z, int mode, double *out)
 {
-    if (n < 0 || n > 62 || !out || (n > 0 && (!O || ld < 2 * n)))
+    if (n < 0 || n > 62 || !out || (n > 0 && (!O || ld < 2 * n)) || !mode_ok(mode))
         return ORACLE_EINVAL;
     uint64_t full = (1ull << n) - 1;
     if (Z & ~full)
         return ORACLE_EINVAL;
-    int N = 2 * n;
     int idx[124];
     int m = subset_rows(n, Z, idx);
-    int sign_neg = ((n - m / 2) & 1);
-    int rc = ORACLE_OK;
     if (m == 0) {
+        const int neg = n & 1;
         out[0] = 1.0;
-        out[1] = sign_neg ? -1.0 : 1.0;
+        out[1] = neg ? -1.0 : 1.0;
         return ORACLE_OK;
     }
-    if (mode == ORACLE_F64) {
-        double *C = (double *)malloc(sizeof(double) * 2 * (size_t)N * N);
-        double *L = (double *)malloc(sizeof(double) * 2 * (size_t)m * m);
-        if (!C || !L) { free(C); free(L); return ORACLE_ENOMEM; }
-        make_c(n, O, ld, C, NULL);
-        double det;
-        rc = det_f64(C, N, idx, m, L, &det);
-        if (rc == ORACLE_OK) {
-            out[0] = det;
-            double td = 1.0 / sqrt(det);
-            out[1] = sign_neg ? -td : td;
-        }
-        free(C); free(L);
-    } else {
-        q_t *C = (q_t *)malloc(sizeof(q_t) * 2 * (size_t)N * N);
-        q_t *L = (q_t *)malloc(sizeof(q_t) * 2 * (size_t)m * m);
-        if (!C || !L) { free(C); free(L); return ORACLE_ENOMEM; }
-        make_c(n, O, ld, NULL, C);
-        q_t det;
-        rc = det_quad(C, N, idx, m, L, &det);
-        if (rc == ORACLE_OK) {
-            out[0] = (double)det;
-            q_t tq = 1 / sqrtq(det);
-            out[1] = (double)(sign_neg ? -tq : tq);
-        }
-        free(C); free(L);
+    cmat_t C;
+    if (make_c(n, O, ld, mode, &C) != ORACLE_OK)
+        return ORACLE_ENOMEM;
+    void *W = malloc(2 * scalar_size(mode) * (size_t)m * m);
+    if (!W) {
+        free_c(&C);
+        return ORACLE_ENOMEM;
     }
+    int rc;
+    if (mode == ORACLE_F64) {
+        double det;
+        rc = det_f64(C.f64, 2 * n, idx, m, (double *)W, &det);
+        out[0] = det;
+    } else if (mode == ORACLE_LD) {
+        ld_t det;
+        rc = det_ld(C.ld, 2 * n, idx, m, (ld_t *)W, &det);
+        out[0] = (double)det;
+    } else {
+        q_t det;
+        rc = det_quad(C.q, 2 * n, idx, m, (q_t *)W, &det);
+        out[0] = (double)det;
+    }
+    if (rc == ORACLE_OK) {
+        q_t t;
+        rc = subset_term(n, mode, &C, idx, m, W, &t);
+        out[1] = (double)t;
+    }
+    free(W);
+    free_c(&C);
     return rc;
 }

@@ -13,7 +13,10 @@
 * brute force of Eq. 2 in 40-digit mpmath (LU determinants, not Cholesky);
 * invariances: mode permutation (the reordering remark in Sec. 2), complex
   conjugation, per-mode phase rotation;
-* subtree restriction: the 2^k restricted sums add up to the full sum.
+* subtree restriction: the 2^k restricted sums add up to the full sum;
+* the reported sums of |t| and t^2 of a product state against their closed
+  forms prod (1 + a_i) and prod (1 + a_i^2), a_i = 1/sqrt(det(I - O_i));
+* the x87 extended mode against mpmath, the closed forms and __float128.
 
 The mutation tests at the end plant plausible mistakes in a copy of the
 oracle's C source (a flipped sign, a dropped conjugate, a dropped term, a
@@ -175,6 +178,46 @@ def test_product_state_fp64_larger_n():
     assert abs(res.value - want) <= bound, (res.value, want, bound)
 
 
+def test_product_state_sums_of_abs_and_squares():
+    # t_Z = (-1)^(n-|Z|) prod_{i in Z} a_i for a product state, so
+    # sum |t| = prod (1 + a_i) and sum t^2 = prod (1 + a_i^2)
+    rng = np.random.default_rng(21)
+    r = rng.uniform(0.3, 1.2, 9)
+    eta = 0.8
+    O = gen.product_state_O(r, eta, rng.uniform(0, 2 * np.pi, 9))
+    a = np.sqrt(1.0 + eta * (2.0 - eta) * np.sinh(r) ** 2)
+    for mode in (orc.F64, orc.LD, orc.QUAD):
+        res = orc.tor(O, mode=mode)
+        assert abs(res.sum_abs / np.prod(1 + a) - 1) <= 1e-12, mode
+        assert abs(res.sum_sq / np.prod(1 + a * a) - 1) <= 1e-12, mode
+        assert res.count == 1 << 9
+
+
+def test_extended_mode_pins():
+    # x87 extended precision (64-bit significand): exact zero for the vacuum,
+    # the product closed form, 40-digit mpmath, and __float128 at n = 14
+    # within a few units of 2^-64 times sqrt(sum t^2) (independent per-term
+    # roundings add in quadrature)
+    for n in (1, 4, 7):
+        assert orc.tor(gen.vacuum_O(n), mode=orc.LD).value == 0.0
+    r = np.linspace(0.4, 1.1, 6)
+    O = gen.product_state_O(r, 0.7, np.linspace(0, 2, 6))
+    want = _closed_product(r, 0.7)
+    assert abs(orc.tor(O, mode=orc.LD).value - want) <= 1e-11 * abs(want)
+    for seed, n in ((0, 3), (1, 4)):
+        O = gen.random_O(n, seed, 0.3, 1.2, 0.9)
+        want = float(_mp_tor(O))
+        got = orc.tor(O, mode=orc.LD).value
+        assert abs(got - want) <= 1e-15 * abs(want), (n, got, want)
+    O = gen.random_O(14, 2, 0.3, 1.2, 0.9)
+    q = orc.tor(O, mode=orc.QUAD)
+    e = orc.tor(O, mode=orc.LD)
+    f = orc.tor(O, mode=orc.F64)
+    spread = np.sqrt(q.sum_sq)
+    assert abs(e.value - q.value) <= 32 * 2.0 ** -64 * spread, (e.value, q.value)
+    assert abs(e.value - q.value) < abs(f.value - q.value)
+
+
 def test_permutation_conjugation_phase_invariance():
     n = 6
     O = gen.random_O(n, 11, 0.3, 1.2, 0.9)
@@ -250,14 +293,13 @@ def test_fp64_mode_within_error_model():
 # ---------------------------------------------------------------------------
 
 MUTANTS = {
-    "sign_ignores_n": ("int sign_neg = ((n - m / 2) & 1);\n        q_t t;",
-                       "int sign_neg = ((m / 2) & 1);\n        q_t t;"),
-    "no_conjugate": ("si -= ai * br - ar * bi;", "si -= ai * br + ar * bi;"),
+    "sign_ignores_n": ("const int neg = (n - m / 2) & 1;", "const int neg = (m / 2) & 1;"),
+    "no_conjugate": ("W[2 * ((long)i * m + j) + 1] -= li * br - lr * bi;",
+                     "W[2 * ((long)i * m + j) + 1] -= li * br + lr * bi;"),
     "drop_empty_subset": ("uint64_t Z = deposit(c, jb->free_mask) | jb->fix_val;",
                           "uint64_t Z = deposit(c, jb->free_mask) | jb->fix_val;\n        if (!Z) continue;"),
-    "short_inner_sum": ("for (int k = 0; k < j; k++) {\n                q_t ar",
-                        "for (int k = 0; k + 1 < j; k++) {\n                q_t ar"),
-    "det_not_squared": ("d *= s;\n        li[2 * i] = sqrtq(s);", "d *= sqrtq(s);\n        li[2 * i] = sqrtq(s);"),
+    "short_update": ("for (int j = k + 1; j <= i; j++) {", "for (int j = k + 1; j < i; j++) {"),
+    "det_not_squared": ("d *= p;", "d *= sqrt((double)p);"),
     "wrong_partner_row": ("idx[m++] = idx[t] + n;", "idx[m++] = (idx[t] + 1) % n + n;"),
 }
 
@@ -281,7 +323,7 @@ def _build_mutant(name, tmp):
     def tor(O, mode):
         O = np.ascontiguousarray(O, dtype=np.complex128)
         n = O.shape[0] // 2
-        out = (ctypes.c_double * 4)()
+        out = (ctypes.c_double * 5)()
         rc = lib.oracle_tor(n, O.ctypes.data if n else None, max(2 * n, 1), mode, 2, 0, 0, out)
         if rc != 0:
             raise orc.OracleError(str(rc))
