@@ -226,6 +226,9 @@ def main():
     torch.cuda.synchronize()
     path_flags = TOR_FORCE_COMPLEX if args.force_complex else 0
     dctx = Context(device=0, stream=stream, workspace=ws, flags=TOR_INPUT_DEVICE | path_flags)
+    # the library runs on `stream`; making it torch's current stream as well
+    # orders the device input's reads without a wait per call
+    torch.cuda.set_stream(stream)
     # the collector runs before the warm-up: a pause between warm-up and the
     # timed steps would let the GPU clocks fall again
     gc.collect()

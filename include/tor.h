@@ -111,7 +111,11 @@ typedef struct {
     int status;                /* TOR_OK or an error for this matrix                    */
     int path;                  /* 1 = real quadrature path, 2 = complex path,
                                   3 = real quadrature path with a double-double factor  */
-    float device_ms;           /* device time of the launch that produced it            */
+    float device_ms;           /* device time of the launch that produced it (served
+                                  requests: their share of the launches they ran in)    */
+    int launches;              /* launches of the recursive kernel that computed it: 1,
+                                  or for a served request the chunked launches it took
+                                  part in                                                */
 } tor_result;
 
 /* Defaults for every field (device 0, library stream and workspace, max_n 40). */
@@ -219,16 +223,21 @@ int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out);
  * kernel time.  Uses the context's workspace. */
 int tor_debug_fma_peak(tor_ctx *ctx, int iters, double *tflops, float *ms);
 
-/* Serving policy.  Each serving launch runs at most chunk_subsets subsets
- * (default 2^29, about 2.5 ms at n = 30 rates) taken from the admitted
- * requests: oldest_share of it (default 0.5) goes to the oldest request, the
- * rest to the requests with the least remaining work.  Before each such
- * launch, the requests with at most 2^24 subsets of work left (n <= 24) run
- * whole in a launch of their own, and their results can be polled before the
- * chunked launch starts.  max_queue bounds the
- * requests held (admitted or waiting); tor_submit beyond it returns
- * TOR_E_BUSY.  Applies from the next launch on. */
-int tor_serve_config(tor_ctx *ctx, long long chunk_subsets, double oldest_share, int max_queue);
+/* Serving policy.  Each chunked serving launch runs at most chunk_subsets
+ * subsets (default 2^29, about 2.5 ms at n = 30 rates) taken from the
+ * admitted requests: oldest_share of it (default 0.5) goes to the oldest
+ * request, the rest to the requests with the least remaining work, so a
+ * request larger than a chunk is split over several launches (root ranges
+ * of its subtree roots) while requests that arrive meanwhile join the next
+ * launch.  Before each chunked launch, the requests with at most
+ * express_subsets subsets of work left (default 2^24, n <= 24; 0 disables
+ * it) run whole in a launch of their own, and their results can be polled
+ * before the chunked launch starts.  max_queue bounds the requests held
+ * (admitted or waiting); tor_submit beyond it returns TOR_E_BUSY.  Applies
+ * from the scheduler's next round on.  Errors: TOR_E_INVAL (chunk_subsets
+ * < 1024, express_subsets < 0, oldest_share outside [0, 1], max_queue < 1). */
+int tor_serve_config(tor_ctx *ctx, long long chunk_subsets, long long express_subsets,
+                     double oldest_share, int max_queue);
 
 /* Autotuner.  For every n in [n_min, n_max] and each selected path
  * (TOR_TUNE_REAL: Gaussian-state matrices, TOR_TUNE_COMPLEX: general ones,

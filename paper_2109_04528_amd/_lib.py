@@ -72,13 +72,14 @@ class tor_result(ctypes.Structure):
         ("status", ctypes.c_int),
         ("path", ctypes.c_int),
         ("device_ms", ctypes.c_float),
+        ("launches", ctypes.c_int),
     ]
 
 
 # the same layout as a numpy record, to read an array of results at once
 _RESULT_DTYPE = np.dtype({
     "names": [f[0] for f in tor_result._fields_],
-    "formats": ["<f8", "<f8", "<f8", "<f8", "<u8", "<i4", "<i4", "<f4"],
+    "formats": ["<f8", "<f8", "<f8", "<f8", "<u8", "<i4", "<i4", "<f4", "<i4"],
     "offsets": [getattr(tor_result, f[0]).offset for f in tor_result._fields_],
     "itemsize": ctypes.sizeof(tor_result),
 })
@@ -144,7 +145,8 @@ def load(path: str = LIB_PATH):
     lib.tor_debug_math.restype = ctypes.c_int
     lib.tor_debug_fma_peak.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_float)]
     lib.tor_debug_fma_peak.restype = ctypes.c_int
-    lib.tor_serve_config.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_double, ctypes.c_int]
+    lib.tor_serve_config.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_longlong, ctypes.c_double,
+                                     ctypes.c_int]
     lib.tor_serve_config.restype = ctypes.c_int
     lib.tor_click_probs.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long, ctypes.c_int,
                                     P(ctypes.c_ulonglong), P(ctypes.c_double), ctypes.c_void_p]
@@ -180,6 +182,7 @@ class TorResult:
     status: int
     path: int
     device_ms: float
+    launches: int = 1
 
     @property
     def value(self) -> float:
@@ -192,7 +195,8 @@ class TorResult:
 
     @classmethod
     def from_c(cls, r: tor_result) -> "TorResult":
-        return cls(r.tor, r.tor_lo, r.sum_abs, r.err_est, int(r.subsets), r.status, r.path, r.device_ms)
+        return cls(r.tor, r.tor_lo, r.sum_abs, r.err_est, int(r.subsets), r.status, r.path, r.device_ms,
+                   r.launches)
 
 
 def _results(res, cnt: int) -> List["TorResult"]:
@@ -247,6 +251,9 @@ class Context:
         opt = tor_options()
         lib.tor_default_options(ctypes.byref(opt))
         opt.device = device
+        # a torch stream the library runs on (None: the library's own stream,
+        # or a raw handle torch knows nothing of)
+        self._torch_stream = stream if hasattr(stream, "wait_stream") else None
         if stream is not None:
             opt.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
         if workspace is not None:  # e.g. a torch uint8 tensor on the device
@@ -266,10 +273,24 @@ class Context:
         self._lib = lib
         self._device_in = bool(flags & TOR_INPUT_DEVICE)
 
+    def _after_torch_writes(self, O):
+        """Order the library's reads of a device tensor after the work torch
+        has queued on its current stream (which may still be writing O): the
+        library's stream waits for it on the device when it is a torch
+        stream, else the host waits for torch's stream to finish."""
+        import torch
+        cur = torch.cuda.current_stream(O.device)
+        if self._torch_stream is None:
+            cur.synchronize()
+        elif self._torch_stream != cur:
+            self._torch_stream.wait_stream(cur)
+
     def _in(self, O):
         """(pointer, n, ld, keep-alive) of a matrix argument."""
         if self._device_in:
             ptr, n, ld = _dev_c128(O)
+            if n:
+                self._after_torch_writes(O)
             return (ptr if n else None), n, ld, O
         A = _host_c128(O)
         n = A.shape[0] // 2
@@ -392,8 +413,8 @@ class Context:
             raise TorError(rc, "tor_drain")
 
     def serve_config(self, chunk_subsets: int = 1 << 29, oldest_share: float = 0.5,
-                     max_queue: int = 1 << 16) -> None:
-        rc = self._lib.tor_serve_config(self._h, chunk_subsets, oldest_share, max_queue)
+                     max_queue: int = 1 << 16, express_subsets: int = 1 << 24) -> None:
+        rc = self._lib.tor_serve_config(self._h, chunk_subsets, express_subsets, oldest_share, max_queue)
         if rc != TOR_OK:
             raise TorError(rc, "tor_serve_config")
 

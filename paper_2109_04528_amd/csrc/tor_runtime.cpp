@@ -74,6 +74,15 @@ struct Request {
     char *dC = nullptr;
     double *dSlots = nullptr;
     float device_ms = 0.f;
+    int launches = 0;  // serving launches that ran part of it
+};
+
+// Serving policy (tor_serve_config).  Written under the serving lock; the
+// scheduler takes a copy under the same lock before each round.
+struct ServeCfg {
+    long long chunk_subsets = 1ll << 29;   // work per chunked serving launch
+    long long express_subsets = 1ll << 24; // requests this small run ahead, whole (0: none)
+    double oldest_share = 0.5;             // of a chunk, guaranteed to the oldest request
 };
 
 struct TuneEntry {
@@ -113,9 +122,7 @@ struct tor_ctx {
     bool stop = false;
     int admitted = 0;
     int max_queue = 1 << 16;
-    long long chunk_subsets = 1ll << 29;  // work per serving launch
-    long long express_subsets = 1ll << 24; // requests this small run ahead, whole
-    double oldest_share = 0.5;            // of it, guaranteed to the oldest request
+    ServeCfg serve;  // guarded by smu
     char *pool = nullptr;
     size_t pool_bytes = 256ull << 20;
     std::map<size_t, size_t> pool_free;  // offset -> length
@@ -650,6 +657,7 @@ void fill_result(const Mat &st, int path, const double *r, float ms, tor_result 
     out->status = r[3] != 0.0 ? TOR_E_NOT_PD : !std::isfinite(r[0]) ? TOR_E_NUMERIC : TOR_OK;
     out->path = api_path(path);
     out->device_ms = ms;
+    out->launches = 1;
 }
 
 // Split depths for a launch of several matrices: roots of about equal work,
@@ -805,10 +813,10 @@ void pool_release(tor_ctx *ctx, size_t off, size_t len)
 
 // Split depth of a served request: roots of at most a quarter-wave share of
 // one launch's budget, so that no single root outlasts the launch it is in.
-int serve_k(const tor_ctx *ctx, const Request &r)
+int serve_k(const tor_ctx *ctx, const ServeCfg &cfg, const Request &r)
 {
     const int LA = std::max(r.N - path_R(r.path), 0);
-    const double per_root = std::max((double)ctx->chunk_subsets / (4.0 * launch_grid(ctx, r.path, r.N)), 1.0);
+    const double per_root = std::max((double)cfg.chunk_subsets / (4.0 * launch_grid(ctx, r.path, r.N)), 1.0);
     const int lg = (int)std::floor(std::log2(per_root));
     const int k = std::max(choose_k(ctx, r.N, r.path), r.N - lg);
     return std::max(0, std::min(k, std::min(LA, 20)));
@@ -832,15 +840,15 @@ size_t request_bytes(int n, unsigned sflags)
 
 // One scheduling round for one path: pick root ranges for a launch, run it,
 // retire the finished requests.  With express set, the launch takes only the
-// requests whose remaining work is at most ctx->express_subsets, whole.
+// requests whose remaining work is at most cfg.express_subsets, whole.
 // Called with ctx->mu held.
-int serve_round(tor_ctx *ctx, int path, std::vector<Request *> &active, std::vector<Request *> &finished,
-                bool express)
+int serve_round(tor_ctx *ctx, const ServeCfg &cfg, int path, std::vector<Request *> &active,
+                std::vector<Request *> &finished, bool express)
 {
     std::vector<Request *> cand;
     for (Request *r : active)
         if (r->path == path && r->next_root < r->nroots &&
-            (!express || (r->nroots - r->next_root) * r->root_work <= ctx->express_subsets))
+            (!express || (r->nroots - r->next_root) * r->root_work <= cfg.express_subsets))
             cand.push_back(r);
     if (cand.empty())
         return TOR_OK;
@@ -851,7 +859,7 @@ int serve_round(tor_ctx *ctx, int path, std::vector<Request *> &active, std::vec
     std::stable_sort(cand.begin(), cand.end(), [](Request *a, Request *b) {
         return (a->nroots - a->next_root) * a->root_work < (b->nroots - b->next_root) * b->root_work;
     });
-    long long budget = express ? (long long)1 << 62 : ctx->chunk_subsets;
+    long long budget = express ? (long long)1 << 62 : cfg.chunk_subsets;
     std::vector<ProblemDesc> descs;
     std::vector<Request *> used;
     auto take = [&](Request *r, long long share) {
@@ -869,7 +877,7 @@ int serve_round(tor_ctx *ctx, int path, std::vector<Request *> &active, std::vec
         r->next_root += n;
         budget -= n * r->root_work;
     };
-    take(oldest, (long long)(ctx->oldest_share * (double)budget));
+    take(oldest, (long long)(cfg.oldest_share * (double)budget));
     for (Request *r : cand) {
         if (budget <= 0)
             break;
@@ -887,8 +895,10 @@ int serve_round(tor_ctx *ctx, int path, std::vector<Request *> &active, std::vec
     std::vector<double> res;
     float ms = 0.f;
     int rc = run_launch(ctx, path, descs, red, 0, launch_grid(ctx, path, Nmax), &res, &ms);
-    for (Request *r : used)
+    for (Request *r : used) {
         r->device_ms += ms / (float)used.size();
+        ++r->launches;
+    }
     if (rc != TOR_OK) {
         for (Request *r : used) {
             r->res = tor_result{};
@@ -902,6 +912,7 @@ int serve_round(tor_ctx *ctx, int path, std::vector<Request *> &active, std::vec
     for (size_t j = 0; j < red.size(); j++) {
         Request *r = used[red[j]];
         fill_result(r->st, path, &res[4 * j], r->device_ms, &r->res);
+        r->res.launches = r->launches;
         finished.push_back(r);
     }
     return TOR_OK;
@@ -928,11 +939,13 @@ void serve_loop(tor_ctx *ctx)
     };
     for (;;) {
         std::vector<Request *> admit;
+        ServeCfg cfg;
         {
             std::unique_lock<std::mutex> lk(ctx->smu);
             ctx->scv.wait(lk, [&] { return ctx->stop || !ctx->pending.empty() || !active.empty(); });
             if (ctx->stop)
                 return;
+            cfg = ctx->serve;  // this round's policy
             // admission by device footprint, in arrival order
             const unsigned sfl = stage_flags(ctx->opt.flags);
             while (!ctx->pending.empty()) {
@@ -996,7 +1009,7 @@ void serve_loop(tor_ctx *ctx)
                 r->st = mats[j];
                 r->path = r->st.path;
                 r->N = r->st.N;
-                r->k = serve_k(ctx, *r);
+                r->k = serve_k(ctx, cfg, *r);
                 r->nroots = 1ll << r->k;
                 r->next_root = 0;
                 r->root_work = 1ll << (r->N - r->k);
@@ -1007,11 +1020,12 @@ void serve_loop(tor_ctx *ctx)
             // small requests first, in launches of their own, and their
             // results published before the chunked launch starts, so that
             // they wait for at most one large launch
-            for (int path : {PATH_REAL, PATH_CPLX, PATH_QUAD})
-                serve_round(ctx, path, active, finished, true);
+            if (cfg.express_subsets > 0)
+                for (int path : {PATH_REAL, PATH_CPLX, PATH_QUAD})
+                    serve_round(ctx, cfg, path, active, finished, true);
             publish(finished);
             for (int path : {PATH_REAL, PATH_CPLX, PATH_QUAD})
-                serve_round(ctx, path, active, finished, false);
+                serve_round(ctx, cfg, path, active, finished, false);
         }
         publish(finished);
     }
@@ -1614,7 +1628,9 @@ int tor_submit(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long
     r->raw.resize((size_t)n2 * n2 * 2);
     if (n > 0) {
         if (ctx->opt.flags & TOR_INPUT_DEVICE) {
-            hipError_t e = hipMemcpy2D(r->raw.data(), sizeof(c64) * n2, O, sizeof(c64) * (size_t)ld, sizeof(c64) * n2,
+            hipError_t e = hipSetDevice(ctx->device);
+            if (e == hipSuccess)
+                e = hipMemcpy2D(r->raw.data(), sizeof(c64) * n2, O, sizeof(c64) * (size_t)ld, sizeof(c64) * n2,
                                        n2, hipMemcpyDeviceToHost);
             if (e != hipSuccess) {
                 delete r;
@@ -1669,13 +1685,16 @@ int tor_drain(tor_ctx *ctx, int timeout_ms)
     return ctx->scv.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred) ? TOR_OK : TOR_E_TIMEOUT;
 }
 
-int tor_serve_config(tor_ctx *ctx, long long chunk_subsets, double oldest_share, int max_queue)
+int tor_serve_config(tor_ctx *ctx, long long chunk_subsets, long long express_subsets, double oldest_share,
+                     int max_queue)
 {
-    if (!ctx || chunk_subsets < 1024 || !(oldest_share >= 0.0 && oldest_share <= 1.0) || max_queue < 1)
+    if (!ctx || chunk_subsets < 1024 || express_subsets < 0 || !(oldest_share >= 0.0 && oldest_share <= 1.0) ||
+        max_queue < 1)
         return TOR_E_INVAL;
     std::lock_guard<std::mutex> g(ctx->smu);
-    ctx->chunk_subsets = chunk_subsets;
-    ctx->oldest_share = oldest_share;
+    ctx->serve.chunk_subsets = chunk_subsets;
+    ctx->serve.express_subsets = express_subsets;
+    ctx->serve.oldest_share = oldest_share;
     ctx->max_queue = max_queue;
     return TOR_OK;
 }

@@ -71,6 +71,33 @@ def test_device_input_eval_and_batch(ctxs):
     assert all(same(x, y) for x, y in zip(ra, rb))
 
 
+def test_device_input_written_just_before_the_call():
+    """A tensor torch is still writing when the call is made (a long matrix
+    product queued ahead of the copy into it): the binding orders the
+    library's reads after torch's queued work, on the library's own stream
+    (the host waits) and on a torch stream of the caller's (the stream waits
+    on the device).  A read that ran ahead would see zeros, the vacuum."""
+    import torch
+    from paper_2109_04528_amd import Context, TOR_INPUT_DEVICE
+    O = gen.random_O(12, 51, 0.3, 1.2, 0.9)
+    with Context(device=0) as h:
+        want = h.eval(O)
+    src = torch.from_numpy(O).pin_memory()
+    for kind in ("library stream", "torch stream"):
+        say(f"case device input written just before the call ({kind})")
+        s = torch.cuda.Stream(device="cuda:0") if kind == "torch stream" else None
+        with Context(device=0, flags=TOR_INPUT_DEVICE, stream=s) as d:
+            t = torch.zeros(O.shape, dtype=torch.complex128, device="cuda:0")
+            a = torch.full((4096, 4096), 1e-3, dtype=torch.float32, device="cuda:0")
+            torch.cuda.synchronize()
+            for _ in range(16):  # several milliseconds of queued work
+                a = a @ a
+            t.copy_(src, non_blocking=True)
+            r = d.eval(t)
+            torch.cuda.synchronize()
+        assert same(r, want), (kind, r.value, want.value)
+
+
 def test_convenience_function_takes_host_and_device_matrices():
     from paper_2109_04528_amd import tor
     O = gen.random_O(9, 43, 0.3, 1.2, 0.9)
