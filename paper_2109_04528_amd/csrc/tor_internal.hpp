@@ -116,9 +116,28 @@ struct StageDesc {
 };
 
 // sum_{i=1..s} 2i(i+1): scalars of all node sizes 1..s
-__host__ __device__ constexpr long long Gsum(long long s) { return 2 * s * (s + 1) * (s + 2) / 3; }
-// scalar offset of tier-A stack slot l (covers modes [l, N)), slots 1..N-R
-__host__ __device__ constexpr long long slot_off(int N, int l) { return Gsum(N - 1) - Gsum(N - l); }
+__host__ __device__ constexpr long long Gsum(long long s) { return s <= 0 ? 0 : 2 * s * (s + 1) * (s + 2) / 3; }
+
+// Per-wave stack of a matrix of N modes split at depth k, for a kernel that
+// finishes the last R modes in LDS and registers (LA = N - R tier-A levels):
+//  * the root node, eliminated in place: NSZ(N) scalars with the matrix's
+//    own array stride NB(N) (an include step only rewrites blocks of the
+//    modes that remain, each by the lane that reads it);
+//  * tier-A slots l = k+1 .. LA-1, slot l holding a node of N - l modes with
+//    its own stride NB(N - l);
+//  * the running determinants of the tier-A levels (LA + 1 real values).
+// Scalar offset of tier-A slot l (also of the determinants, at l = LA).
+__host__ __device__ constexpr long long tslot_off(int N, int k, int l)
+{
+    return NSZ(N) + (Gsum(N - k - 1) - Gsum(N - l));
+}
+// bytes of the stack for scalars of esz bytes and real values of rsz bytes
+__host__ __device__ constexpr long long stack_bytes(int N, int k, int R, int esz, int rsz)
+{
+    const int LA = N - R > 0 ? N - R : 0;
+    const long long slots = k < LA ? tslot_off(N, k, LA) : (long long)NSZ(N);
+    return esz * slots + (long long)rsz * (LA + 1);
+}
 
 // kernel configurations (modes handled per lane, levels expanded in LDS)
 // T: modes a lane finishes alone; B: levels between the tier-A leaf and the

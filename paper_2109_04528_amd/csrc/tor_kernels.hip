@@ -192,13 +192,19 @@ __device__ __forceinline__ void elim_block(const S *node, int nb, int m, int a, 
 // ---------------------------------------------------------------------------
 // one include step on global memory (tier A and the root path): src is a view
 // of s modes of a node with snb blocks per granule array, dst receives the
-// Schur complement of s-1 modes as a node of its own (NB(s-1) blocks per
-// array).  Every lane forms the pivot itself; lane l updates blocks l, l+64,
-// ...  dst (global, may be null) receives the whole child; lds (may be null)
-// receives its first nlds blocks (the tier-A leaf) as a node of nlds blocks.
+// Schur complement of s-1 modes as a node with dnb blocks per granule array.
+// Every lane forms the pivot itself; lane l updates blocks l, l+64, ...  dst
+// (global, may be null) receives the whole child; lds (may be null) receives
+// its first nlds blocks (the tier-A leaf) as a node of nlds blocks.
+//
+// dst may be src itself (the root path eliminates in place, with dnb = snb):
+// block (a, b) of the child is read and rewritten by the same lane, and the
+// pivot rows (blocks of mode s-1) are never written, so no lane reads a
+// block another lane has already replaced.  Block indices do not depend on
+// the node's size, so the same lane owns the same block at every step.
 template <class S>
-__device__ void elim_global(const S *__restrict__ src, int snb, S *__restrict__ dst, S *lds, int nlds, int s,
-                            int lane, RT<S> &pdet, int &bad)
+__device__ __forceinline__ void elim_global_body(const S *src, int snb, S *dst, int dnb, S *lds, int nlds, int s,
+                                                 int lane, RT<S> &pdet, int &bad)
 {
     const int m = s - 1;
     const Piv<S> pv = node_pivot(src, snb, m);
@@ -212,11 +218,27 @@ __device__ void elim_global(const S *__restrict__ src, int snb, S *__restrict__ 
         S o[4];
         elim_block(src, snb, m, a, b, bidx(a, b), pv, o);
         if (dst)
-            put_block(dst, NB(m), bi, o);
+            put_block(dst, dnb, bi, o);
         if (lds && bi < nlds)
             put_block(lds, nlds, bi, o);
     }
     __syncthreads();
+}
+
+// the same with src and dst distinct (tier A), so that loads of the next
+// blocks may move ahead of the stores of this one
+template <class S>
+__device__ void elim_global(const S *__restrict__ src, int snb, S *__restrict__ dst, int dnb, S *lds, int nlds, int s,
+                            int lane, RT<S> &pdet, int &bad)
+{
+    elim_global_body(src, snb, dst, dnb, lds, nlds, s, lane, pdet, bad);
+}
+
+// in place (dst == src, or src the read-only matrix): the root path
+template <class S>
+__device__ void elim_inplace(const S *src, int snb, S *dst, int dnb, int s, int lane, RT<S> &pdet, int &bad)
+{
+    elim_global_body(src, snb, dst, dnb, (S *)nullptr, 0, s, lane, pdet, bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -578,28 +600,27 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
         const long long root = P.root_begin + ((long long)item - P.item_begin);
         const int N = P.N, k = P.k, LA = N - R, D = LA - k;
         const S *C = reinterpret_cast<const S *>(P.C);
-        // running determinants of the tier-A levels on the current path, in
-        // the stack's slot of level LA: that slot never holds a node when the
-        // root has more than one leaf, and only then is it used
-        RT<S> *sdet = reinterpret_cast<RT<S> *>(wscr + slot_off(N, LA));
+        // the wave's stack (tslot_off): the root node, tier-A slots k+1 ..
+        // LA-1, and the running determinants of the tier-A levels on the
+        // current path (used only when the root has more than one leaf)
+        RT<S> *sdet = reinterpret_cast<RT<S> *>(wscr + tslot_off(N, k, LA));
         int bad = 0;
 
-        // root: decisions on modes 0..k-1 given by the bits of root
-        // (every stored node keeps its own block count as the array stride:
-        // the matrix NB(N), stack slot l a node of N-l modes, NB(N-l))
+        // root: decisions on modes 0..k-1 given by the bits of root.  The
+        // first include reads the matrix, the later ones rewrite the root
+        // node in place; it keeps the matrix's array stride NB(N) throughout
+        // (tier-A slot l holds a node of N-l modes with its own stride)
         const S *rsrc = C;
-        int rnb = NB(N);
+        const int rnb = NB(N);
         RT<S> rdet = rconst<RT<S>>(1.0);
         int rinc = 0;
         for (int l = 0; l < k; ++l) {
             if ((root >> l) & 1) {
-                S *dst = wscr + slot_off(N, l + 1);
                 RT<S> pd;
-                elim_global<S>(rsrc, rnb, dst, nullptr, 0, N - l, lane, pd, bad);
+                elim_inplace<S>(rsrc, rnb, wscr, rnb, N - l, lane, pd, bad);
                 rdet = rmul(rdet, pd);
                 ++rinc;
-                rsrc = dst;
-                rnb = NB(N - l - 1);
+                rsrc = wscr;
             }
         }
 
@@ -644,7 +665,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                     si = rinc;
                 } else {
                     const int sl = LA - (__builtin_ctzll(xr) + t + 1);
-                    s = wscr + slot_off(N, sl);
+                    s = wscr + tslot_off(N, k, sl);
                     snb = NB(N - sl);
                     sd = sdet[sl];
                     // includes on the path down to level sl: the root's and
@@ -654,9 +675,9 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                 // the deepest slot (level LA) is never the source of a later
                 // step: that child goes to LDS only; shallower ones also go to
                 // their stack slot
-                S *dst = (lvl + 1 < LA) ? wscr + slot_off(N, lvl + 1) : nullptr;
+                S *dst = (lvl + 1 < LA) ? wscr + tslot_off(N, k, lvl + 1) : nullptr;
                 RT<S> pd;
-                elim_global<S>(s, snb, dst, bufB, NB(R), N - lvl, lane, pd, bad);
+                elim_global<S>(s, snb, dst, NB(N - lvl - 1), bufB, NB(R), N - lvl, lane, pd, bad);
                 ldet = rmul(sd, pd);
                 linc = si + 1;
                 if (lane == 0)

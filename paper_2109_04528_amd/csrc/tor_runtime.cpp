@@ -470,23 +470,31 @@ int stage_sync(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, uns
 }
 
 
+// Bytes of one persistent wave's stack for a matrix of N modes split at
+// depth k (tslot_off): the root node, the tier-A slots, the determinants.
+long long wave_stack_bytes(int path, int N, int k)
+{
+    const int rsz = path == PATH_QUAD ? (int)sizeof(ddr) : (int)sizeof(double);
+    return (long long)align_up((size_t)stack_bytes(N, k, path_R(path), (int)path_esz(path), rsz), 256);
+}
+
 // Workspace bytes a launch needs after its matrices and slots: descriptors,
-// reduction descriptors, queue counter, results, per-wave tier-A stacks.
+// reduction descriptors, queue counter, results, per-wave stacks (stride:
+// the largest wave_stack_bytes of the launch's matrices).
 struct LaunchLayout {
     size_t b_probs, b_red, b_counter, b_res;
     long long stride;
     size_t total(int grid) const { return b_probs + b_red + b_counter + b_res + (size_t)stride * grid; }
 };
 
-LaunchLayout launch_layout(int path, int count, int nred, int Nmax)
+LaunchLayout launch_layout(int count, int nred, long long stride)
 {
-    const size_t esz = path_esz(path);
     LaunchLayout L;
     L.b_probs = align_up(sizeof(ProblemDesc) * std::max(count, 1), 256);
     L.b_red = align_up(sizeof(ProblemDesc) * std::max(nred, 1), 256);
     L.b_counter = 256;
     L.b_res = align_up(sizeof(double) * 4 * std::max(nred, 1), 256);
-    L.stride = (long long)align_up(esz * (size_t)std::max(Gsum(Nmax - 1) - Gsum(path_R(path) - 1), 1ll), 256);
+    L.stride = std::max(stride, 256ll);
     return L;
 }
 
@@ -501,18 +509,17 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
                size_t ws_off, int grid, std::vector<double> *results, float *ms)
 {
     const int count = (int)descs.size();
-    long long total = 0;
-    int Nmax = 0;
+    long long total = 0, stack = 0;
     for (auto &d : descs) {
         d.item_begin = total;
         total += d.nroots;
-        Nmax = std::max(Nmax, d.N);
+        stack = std::max(stack, wave_stack_bytes(path, d.N, d.k));
     }
     std::vector<ProblemDesc> red;
     for (int i : reduce)
         red.push_back(descs[i]);
     const int nred = (int)red.size();
-    const LaunchLayout Lo = launch_layout(path, count, nred, Nmax);
+    const LaunchLayout Lo = launch_layout(count, nred, stack);
     const size_t need = ws_off + Lo.total(grid);
     if (ws_off > 0 && need > ctx->ws_bytes)
         return TOR_E_NOMEM;  // the caller sizes the workspace first
@@ -590,17 +597,18 @@ int run_recursive(tor_ctx *ctx, int path, std::vector<Mat *> &mats, std::vector<
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mats[a]->N > mats[b]->N; });
     // workspace: slots, then what run_launch needs
     std::vector<size_t> s_off(count);
-    long long nslots = 0;
+    long long nslots = 0, stack = 0;
     int Nmax = 0;
     for (int s = 0; s < count; s++) {
         s_off[s] = base + sizeof(double) * 4 * (size_t)nslots;
         nslots += 1ll << ks[order[s]];
         Nmax = std::max(Nmax, mats[order[s]]->N);
+        stack = std::max(stack, wave_stack_bytes(path, mats[order[s]]->N, ks[order[s]]));
     }
     const size_t off = align_up(base + sizeof(double) * 4 * (size_t)nslots, 256);
     const int grid = launch_grid(ctx, path, Nmax);
     // size the workspace for everything, keeping the staged matrices below base
-    int rc = ensure_ws_keep(ctx, off + launch_layout(path, count, count, Nmax).total(grid), base);
+    int rc = ensure_ws_keep(ctx, off + launch_layout(count, count, stack).total(grid), base);
     if (rc != TOR_OK)
         return rc;
     std::vector<ProblemDesc> descs(count);
@@ -1132,7 +1140,8 @@ size_t tor_workspace_size(int max_n, int split_k, int max_inflight)
     const int cnt = std::max(max_inflight, 1);
     const long long items = (1ll << std::min(k, std::max(N - Rmin, 0))) * cnt;
     const size_t grid = 256 * MAX_FIT;
-    const size_t scr = align_up(sizeof(c64) * (size_t)std::max(Gsum(N - 1) - Gsum(Rmin - 1), 1ll), 256) * grid;
+    // the largest per-wave stack: 16-byte scalars, the smallest R, k = 0
+    const size_t scr = align_up((size_t)stack_bytes(N, 0, Rmin, 16, 16), 256) * grid;
     // staging: descriptors and status records, a raw copy of each input and its
     // staged form (16-byte scalars bound every path)
     const size_t n2 = 2 * (size_t)std::max(max_n, 1);
