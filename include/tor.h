@@ -66,6 +66,8 @@ extern "C" {
 #define TOR_E_DEVICE (-6)      /* no usable GPU, or a HIP runtime error             */
 #define TOR_E_TIMEOUT (-7)     /* a host-side deadline passed                       */
 #define TOR_E_UNKNOWN (-8)     /* tor_poll on a ticket this context never issued    */
+#define TOR_E_SCRATCH (-9)     /* tor_eval_static: the problem does not fit the
+                                  static scratch (TOR_STATIC_SCRATCH_BYTES)          */
 
 /* ---- options ------------------------------------------------------------- */
 #define TOR_ACCUM_DD 0   /* double-double accumulation of the signed terms (default) */
@@ -135,6 +137,26 @@ size_t tor_workspace_size(int max_n, int split_k, int max_inflight);
 
 /* Torontonian of one 2n x 2n matrix (Eq. 2), recursive GPU path. */
 int tor_eval(tor_ctx *ctx, int n, const double *O, long ld, tor_result *out);
+
+/* For callers that cannot allocate device or pinned memory -- code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * same evaluation as tor_eval (same kernels, same split, the same value
+ * bit for bit), using only a device array the library declares statically,
+ * TOR_STATIC_SCRATCH_BYTES (128 MiB) per GPU, held from the first context
+ * created on that GPU until the process ends.  It calls no hipMalloc,
+ * hipFree, hipHostMalloc or host heap allocation, and uses neither the
+ * context's workspace nor its pinned buffers, only its stream and events.
+ * O is a host pointer (copied into the array) or, with TOR_INPUT_DEVICE,
+ * device memory read in place.  The array holds the staged matrix, the
+ * root slots and the per-wave stacks of one call at a time: every path fits
+ * for n <= 30; beyond that the call returns TOR_E_SCRATCH when the launch's
+ * stacks do not fit (the real quadrature path fits up to n = 34).  Calls on
+ * one GPU share its array and keep the last call's contents; the library
+ * serialises them with a per-device lock (calls that overlapped would race
+ * on the array).  Errors: those of tor_eval, TOR_E_SCRATCH, and
+ * TOR_E_DEVICE when the array's address could not be resolved. */
+#define TOR_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+int tor_eval_static(tor_ctx *ctx, int n, const double *O, long ld, tor_result *out);
 
 /* Torontonians of count matrices of possibly different n in ONE persistent
  * launch: one work queue over (matrix, subtree root) items, largest n first.

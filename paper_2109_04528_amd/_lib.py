@@ -26,6 +26,7 @@ TOR_E_NOMEM = -5
 TOR_E_DEVICE = -6
 TOR_E_TIMEOUT = -7
 TOR_E_UNKNOWN = -8
+TOR_E_SCRATCH = -9
 
 TOR_ACCUM_DD = 0
 TOR_ACCUM_FP64 = 1
@@ -40,7 +41,7 @@ EXPORTS = [
     "tor_default_options", "tor_create", "tor_destroy", "tor_workspace_size", "tor_eval",
     "tor_eval_batch", "tor_eval_plain", "tor_eval_partials", "tor_submit", "tor_poll",
     "tor_drain", "tor_debug_math", "tor_debug_fma_peak", "tor_strerror", "tor_autotune", "tor_tune_save", "tor_tune_load",
-    "tor_serve_config", "tor_click_probs", "tor_eval_removal",
+    "tor_serve_config", "tor_click_probs", "tor_eval_removal", "tor_eval_static",
 ]
 
 TOR_TUNE_REAL = 0x1
@@ -125,6 +126,8 @@ def load(path: str = LIB_PATH):
     lib.tor_workspace_size.restype = ctypes.c_size_t
     lib.tor_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long, P(tor_result)]
     lib.tor_eval.restype = ctypes.c_int
+    lib.tor_eval_static.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long, P(tor_result)]
+    lib.tor_eval_static.restype = ctypes.c_int
     lib.tor_eval_batch.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_void_p),
                                    P(ctypes.c_long), P(tor_result)]
     lib.tor_eval_batch.restype = ctypes.c_int
@@ -319,6 +322,16 @@ class Context:
         rc = self._lib.tor_eval(self._h, n, ptr, ld, ctypes.byref(r))
         if check and rc != TOR_OK:
             raise TorError(rc, "tor_eval")
+        return TorResult.from_c(r)
+
+    def eval_static(self, O, check: bool = True) -> TorResult:
+        """tor_eval without any allocation (the library's static device
+        array; see tor_eval_static in include/tor.h)."""
+        ptr, n, ld, _keep = self._in(O)
+        r = tor_result()
+        rc = self._lib.tor_eval_static(self._h, n, ptr, ld, ctypes.byref(r))
+        if check and rc != TOR_OK:
+            raise TorError(rc, "tor_eval_static")
         return TorResult.from_c(r)
 
     def eval_batch(self, Os: Sequence, check: bool = True) -> List[TorResult]:

@@ -1097,6 +1097,154 @@ int tune_one(tor_ctx *ctx, int path, int n, TuneEntry &best)
     return TOR_OK;
 }
 
+// ---- the allocation-free evaluation (tor_eval_static) -----------------------
+// A file-scope device array: every GPU the library runs on holds its own copy,
+// at its own address, once a context has been created on it, until the
+// process ends.  Host code never uses the array's name as an address (on the
+// host it only stands for the symbol): tor_create resolves the device
+// address with hipGetSymbolAddress, with that device current, and keeps it
+// per device; kernels receive that address as an argument.
+__device__ __align__(256) char scratch[TOR_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+struct StaticScratch {
+    std::mutex mu;          // one tor_eval_static at a time on a device
+    char *ptr = nullptr;    // the device address of `scratch` on that device
+    bool resolved = false;
+    hipError_t err = hipSuccess;
+};
+StaticScratch g_static[kMaxDevices];
+std::mutex g_static_init;
+
+// Resolve the array's address on `device` (the current device) once.
+void resolve_static(int device)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return;
+    std::lock_guard<std::mutex> g(g_static_init);
+    StaticScratch &ss = g_static[device];
+    if (ss.resolved)
+        return;
+    void *p = nullptr;
+    ss.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    ss.ptr = ss.err == hipSuccess ? (char *)p : nullptr;
+    ss.resolved = true;
+}
+
+// Byte layout of one tor_eval_static call in the device array: the staging
+// descriptor and record, the launch descriptor, queue counter and result,
+// then (from kStaticData on) the host input's copy, the staged form, the
+// root slots and the per-wave stacks.
+constexpr size_t kStaticDesc = 0, kStaticInfo = 256, kStaticProb = 512, kStaticCounter = 1024,
+                 kStaticRes = 1280, kStaticData = 4096;
+
+int eval_static(tor_ctx *ctx, char *base, int n, const double *O, long ld, tor_result *out)
+{
+    const bool dev_in = (ctx->opt.flags & TOR_INPUT_DEVICE) != 0;
+    const unsigned sfl = stage_flags(ctx->opt.flags);
+    const int n2 = 2 * n;
+    size_t at = kStaticData;
+    char *dRaw = nullptr;
+    if (!dev_in && n > 0) {
+        dRaw = base + at;
+        at += align_up(sizeof(c64) * (size_t)n2 * n2, 256);
+    }
+    char *dForm = base + at;
+    at += align_up(staged_bytes(n, sfl, CPLX_R), 256);
+    if (at > TOR_STATIC_SCRATCH_BYTES)
+        return TOR_E_SCRATCH;
+    StageDesc *dDesc = (StageDesc *)(base + kStaticDesc);
+    StageInfo *dInfo = (StageInfo *)(base + kStaticInfo);
+    ProblemDesc *dProb = (ProblemDesc *)(base + kStaticProb);
+    unsigned long long *dCounter = (unsigned long long *)(base + kStaticCounter);
+    double *dRes = (double *)(base + kStaticRes);
+
+    // staging: the host matrix (compact rows) and the descriptor go up from
+    // host memory the caller or this frame owns, both alive until the
+    // synchronisations below
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess && dRaw)
+        e = hipMemcpy2DAsync(dRaw, sizeof(c64) * n2, O, sizeof(c64) * (size_t)ld, sizeof(c64) * n2, n2,
+                             hipMemcpyHostToDevice, ctx->stream);
+    StageDesc d{};
+    d.O = dRaw ? (const double *)dRaw : O;
+    d.ld = dRaw ? n2 : ld;
+    d.sel = nullptr;
+    d.n = n;
+    d.M = n;
+    d.flags = sfl;
+    d.min_cplx = CPLX_R;
+    d.out = dForm;
+    d.info = dInfo;
+    StageInfo info{};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dDesc, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_stage(dDesc, 1, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&info, dInfo, sizeof(info), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    if (info.status != 0) {
+        *out = tor_result{};
+        out->status = TOR_E_INVAL;
+        return TOR_E_INVAL;
+    }
+    Mat m;
+    m.n = n;
+    m.N = info.N;
+    m.path = info.path;
+    const int path = info.path, N = info.N;
+    const int k = choose_k(ctx, N, path);
+    const long long nroots = 1ll << k;
+    double *dSlots = (double *)(base + at);
+    at += align_up(sizeof(double) * 4 * (size_t)nroots, 256);
+    const long long stride = wave_stack_bytes(path, N, k);
+    const int grid = (int)std::min<long long>(launch_grid(ctx, path, N), nroots);
+    if (at + (size_t)stride * grid > TOR_STATIC_SCRATCH_BYTES)
+        return TOR_E_SCRATCH;
+    ProblemDesc pd{};
+    pd.C = dForm;
+    pd.slots = dSlots;
+    pd.N = N;
+    pd.k = k;
+    pd.root_begin = 0;
+    pd.item_begin = 0;
+    pd.nroots = nroots;
+    MainParams mp{};
+    mp.probs = dProb;
+    mp.nprob = 1;
+    mp.total_items = nroots;
+    mp.counter = dCounter;
+    mp.scratch = base + at;
+    mp.scratch_stride = stride;
+    const bool dd = ctx->opt.accum != TOR_ACCUM_FP64 || path == PATH_QUAD;
+    double h[4] = {0, 0, 0, 0};
+    e = hipMemcpyAsync(dProb, &pd, sizeof(pd), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)  // the queue head starts at zero: a fill kernel, no memset
+        e = launch_zero(dCounter, 1, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev0, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_main(path, dd, mp, grid, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev1, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_reduce(dProb, 1, dRes, dd, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h, dRes, sizeof(h), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    fill_result(m, path, h, ms, out);
+    return out->status;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1124,6 +1272,7 @@ const char *tor_strerror(int code)
     case TOR_E_DEVICE: return "device error or no usable GPU";
     case TOR_E_TIMEOUT: return "timed out";
     case TOR_E_UNKNOWN: return "unknown ticket";
+    case TOR_E_SCRATCH: return "the problem exceeds the static scratch of tor_eval_static";
     default: return "unrecognised status code";
     }
 }
@@ -1219,6 +1368,7 @@ int tor_create(tor_ctx **out, const tor_options *opt)
         tor_destroy(ctx);
         return TOR_E_DEVICE;
     }
+    resolve_static(o.device);  // the device is current
     ctx->worker = std::thread(serve_loop, ctx);
     *out = ctx;
     return TOR_OK;
@@ -1259,6 +1409,18 @@ void tor_destroy(tor_ctx *ctx)
     for (auto &kv : ctx->live)
         delete kv.second;
     delete ctx;
+}
+
+int tor_eval_static(tor_ctx *ctx, int n, const double *O, long ld, tor_result *out)
+{
+    if (!ctx || !out || !args_ok(ctx, n, O, ld))
+        return TOR_E_INVAL;
+    if (ctx->device < 0 || ctx->device >= kMaxDevices || !g_static[ctx->device].ptr)
+        return TOR_E_DEVICE;
+    StaticScratch &ss = g_static[ctx->device];
+    std::lock_guard<std::mutex> g(ctx->mu);
+    std::lock_guard<std::mutex> gs(ss.mu);
+    return eval_static(ctx, ss.ptr, n, O, ld, out);
 }
 
 int tor_eval(tor_ctx *ctx, int n, const double *O, long ld, tor_result *out)

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror_covers_codes():
     lib = _lib.load()
-    for code in range(-8, 2):
+    for code in range(-9, 2):
         s = lib.tor_strerror(code).decode()
         assert s and s != "unrecognised status code", code
     assert lib.tor_strerror(-99).decode() == "unrecognised status code"
