@@ -37,8 +37,12 @@
  * sum |t| (the cancellation R = sum |t| / |Tor|) and sum t^2, whose square
  * root scales the spread of independent per-term rounding errors.
  *
- * Subsets are split over POSIX threads in contiguous ranges; the per-thread
- * partial sums are combined in thread order.
+ * Subsets are split over POSIX threads in interleaved chunks of 4096 masks
+ * (masks with high modes included cost more, so contiguous ranges would
+ * leave one thread with most of the work); the per-thread partial sums are
+ * combined in thread order.  FP64 and extended terms are multiples of 2^-52
+ * (2^-63) of magnitude >= 1 for the inputs here, so their __float128 sums are
+ * exact and independent of this split.
  *
  * A restriction (fix_mask, fix_val) limits the sum to subsets Z with
  * (Z & fix_mask) == fix_val, i.e. one subtree of the include/exclude tree.
@@ -167,11 +171,14 @@ static size_t scalar_size(int mode)
 
 /* ---- threaded sum ---------------------------------------------------------- */
 
+#define CHUNK 4096
+
 typedef struct {
     int n, mode;
     const cmat_t *C;
     uint64_t free_mask, fix_val;
-    uint64_t lo, hi; /* range of free-bit counters */
+    uint64_t total;       /* free-bit counters 0 .. total-1 */
+    int tid, nthreads;    /* this thread takes chunks tid, tid + nthreads, ... */
     q_t sum, sum_abs, sum_sq;
     uint64_t count;
     int status;
@@ -203,18 +210,22 @@ static void *run_job(void *arg)
         return NULL;
     }
     q_t sum = 0, sum_abs = 0, sum_sq = 0;
-    for (uint64_t c = jb->lo; c < jb->hi; c++) {
-        uint64_t Z = deposit(c, jb->free_mask) | jb->fix_val;
-        int m = subset_rows(n, Z, idx);
-        q_t t;
-        if (subset_term(n, jb->mode, jb->C, idx, m, W, &t) != ORACLE_OK) {
-            jb->status = ORACLE_ENOTPD;
-            break;
+    for (uint64_t c0 = (uint64_t)jb->tid * CHUNK; c0 < jb->total && jb->status == ORACLE_OK;
+         c0 += (uint64_t)jb->nthreads * CHUNK) {
+        const uint64_t c1 = c0 + CHUNK < jb->total ? c0 + CHUNK : jb->total;
+        for (uint64_t c = c0; c < c1; c++) {
+            uint64_t Z = deposit(c, jb->free_mask) | jb->fix_val;
+            int m = subset_rows(n, Z, idx);
+            q_t t;
+            if (subset_term(n, jb->mode, jb->C, idx, m, W, &t) != ORACLE_OK) {
+                jb->status = ORACLE_ENOTPD;
+                break;
+            }
+            sum += t;
+            sum_abs += (t < 0 ? -t : t);
+            sum_sq += t * t;
+            jb->count++;
         }
-        sum += t;
-        sum_abs += (t < 0 ? -t : t);
-        sum_sq += t * t;
-        jb->count++;
     }
     jb->sum = sum;
     jb->sum_abs = sum_abs;
@@ -295,8 +306,9 @@ int oracle_tor(int n, const double *O, long ld, int mode, int nthreads,
         long p = sysconf(_SC_NPROCESSORS_ONLN);
         nthreads = p > 0 ? (int)p : 1;
     }
-    if ((uint64_t)nthreads > total)
-        nthreads = (int)total;
+    const uint64_t nchunks = (total + CHUNK - 1) / CHUNK;
+    if ((uint64_t)nthreads > nchunks)
+        nthreads = (int)nchunks;
     job_t *jobs = (job_t *)calloc((size_t)nthreads, sizeof(job_t));
     pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
     int *started = (int *)calloc((size_t)nthreads, sizeof(int));
@@ -313,8 +325,9 @@ int oracle_tor(int n, const double *O, long ld, int mode, int nthreads,
         jobs[t].C = &C;
         jobs[t].free_mask = free_mask;
         jobs[t].fix_val = fix_val;
-        jobs[t].lo = total / nthreads * t + (t < (int)(total % nthreads) ? t : total % nthreads);
-        jobs[t].hi = jobs[t].lo + total / nthreads + (t < (int)(total % nthreads) ? 1 : 0);
+        jobs[t].total = total;
+        jobs[t].tid = t;
+        jobs[t].nthreads = nthreads;
     }
     int status = ORACLE_OK;
     if (nthreads == 1) {
