@@ -156,6 +156,57 @@ __device__ __forceinline__ void put_block(S *node, int nb, int bi, const S *o)
     }
 }
 
+// the same accesses through global-address-space pointers (tier A and the
+// root path read and write the wave's stack and the matrix in global memory;
+// a generic pointer would make them flat accesses)
+typedef double dv2 __attribute__((ext_vector_type(2)));
+template <class S>
+__device__ __forceinline__ void get_block_g(const S *node, int nb, int bi, S *v)
+{
+    typedef const __attribute__((address_space(1))) dv2 GG;
+    constexpr int G = EPG((int)sizeof(S));
+#pragma unroll
+    for (int g = 0; g < 4 / G; ++g) {
+        const dv2 raw = *(GG *)(node + gpos((int)sizeof(S), nb, bi, g * G));
+        Gran<S> q;
+        __builtin_memcpy(&q, &raw, 16);
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            v[g * G + j] = q.e[j];
+    }
+}
+template <class S>
+__device__ __forceinline__ void put_block_g(S *node, int nb, int bi, const S *o)
+{
+    typedef __attribute__((address_space(1))) dv2 GG;
+    constexpr int G = EPG((int)sizeof(S));
+#pragma unroll
+    for (int g = 0; g < 4 / G; ++g) {
+        Gran<S> q;
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            q.e[j] = o[g * G + j];
+        dv2 raw;
+        __builtin_memcpy(&raw, &q, 16);
+        *(GG *)(node + gpos((int)sizeof(S), nb, bi, g * G)) = raw;
+    }
+}
+__device__ __forceinline__ double ld_g(const double *p) { return *(const __attribute__((address_space(1))) double *)p; }
+template <class S>
+__device__ __forceinline__ S ld_g(const S *p)
+{
+    const dv2 raw = *(const __attribute__((address_space(1))) dv2 *)p;
+    S v;
+    __builtin_memcpy(&v, &raw, 16);
+    return v;
+}
+template <class S>
+__device__ __forceinline__ Piv<S> node_pivot_g(const S *node, int nb, int m)
+{
+    const int bi = bidx(m, m);
+    return pivot(re(ld_g(&blk(node, nb, bi, 0))), ld_g(&blk(node, nb, bi, 2)), re(ld_g(&blk(node, nb, bi, 3))));
+}
+
 template <class S>
 __device__ __forceinline__ Piv<S> node_pivot(const S *node, int nb, int m)
 {
@@ -163,14 +214,20 @@ __device__ __forceinline__ Piv<S> node_pivot(const S *node, int nb, int m)
     return pivot(re(blk(node, nb, bi, 0)), blk(node, nb, bi, 2), re(blk(node, nb, bi, 3)));
 }
 
-template <class S>
+template <class S, bool GLOBAL = false>
 __device__ __forceinline__ void elim_block(const S *node, int nb, int m, int a, int b, int ih, const Piv<S> &pv,
                                            S *o)
 {
     S A[4], Bk[4], H[4];
-    get_block(node, nb, bidx(m, a), A);
-    get_block(node, nb, bidx(m, b), Bk);
-    get_block(node, nb, ih, H);
+    if constexpr (GLOBAL) {
+        get_block_g(node, nb, bidx(m, a), A);
+        get_block_g(node, nb, bidx(m, b), Bk);
+        get_block_g(node, nb, ih, H);
+    } else {
+        get_block(node, nb, bidx(m, a), A);
+        get_block(node, nb, bidx(m, b), Bk);
+        get_block(node, nb, ih, H);
+    }
     const S ra0 = A[0], ra1 = A[1];
     const S qa0 = sub_mul(A[2], ra0, pv.ba), qa1 = sub_mul(A[3], ra1, pv.ba);
     const S rb0 = Bk[0], rb1 = Bk[1];
@@ -207,7 +264,7 @@ __device__ __forceinline__ void elim_global_body(const S *src, int snb, S *dst, 
                                                  int lane, RT<S> &pdet, int &bad)
 {
     const int m = s - 1;
-    const Piv<S> pv = node_pivot(src, snb, m);
+    const Piv<S> pv = node_pivot_g(src, snb, m);
     pdet = pv.pdet;
     if (!is_pos(pv.pdet) || !is_pos(pv.inv_a))
         bad = 1;
@@ -216,9 +273,9 @@ __device__ __forceinline__ void elim_global_body(const S *src, int snb, S *dst, 
         int a, b;
         block_ab(bi, a, b);
         S o[4];
-        elim_block(src, snb, m, a, b, bidx(a, b), pv, o);
+        elim_block<S, true>(src, snb, m, a, b, bidx(a, b), pv, o);
         if (dst)
-            put_block(dst, dnb, bi, o);
+            put_block_g(dst, dnb, bi, o);
         if (lds && bi < nlds)
             put_block(lds, nlds, bi, o);
     }
@@ -644,7 +701,7 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                 constexpr int GA = EPG((int)sizeof(S)) * NB(R);  // scalars per granule array
                 for (int e = lane; e < NSZ(R); e += 64) {
                     const int g = e / GA;
-                    bufB[e] = rsrc[g * EPG((int)sizeof(S)) * rnb + (e - g * GA)];
+                    bufB[e] = ld_g(&rsrc[g * EPG((int)sizeof(S)) * rnb + (e - g * GA)]);
                 }
                 ldet = rdet;
                 linc = rinc;
