@@ -107,8 +107,9 @@ typedef struct {
     double tor;                /* Torontonian, high part                                */
     double tor_lo;             /* low part of the double-double value                   */
     double sum_abs;            /* sum of |term|; R = sum_abs / |tor| is the cancellation */
-    double err_est;            /* estimated relative error from term rounding (FP64, or
-                                  2^-104 with TOR_FACTOR_DD)                            */
+    double err_est;            /* typical relative error from the rounding of the
+                                  terms: 2 u R / sqrt(2^n), u = 2^-53 (FP64 factor) or
+                                  2^-102 (TOR_FACTOR_DD)                                */
     unsigned long long subsets;/* 2^n                                                   */
     int status;                /* TOR_OK or an error for this matrix                    */
     int path;                  /* 1 = real quadrature path, 2 = complex path,

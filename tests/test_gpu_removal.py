@@ -1,6 +1,7 @@
 """The paper's removal-order kernel (tor_eval_removal, Algorithm 2) against
-the oracle: both sides round every term once in FP64 and sum exactly, so the
-FP64 term bound of test_gpu_parity applies."""
+the oracle: both sides round every term once and sum exactly, so the
+tolerance of tests/bounds.py applies (FP64 on the GPU, the oracle's own
+precision on the other side)."""
 import json
 import os
 import sys
@@ -8,11 +9,11 @@ import sys
 import numpy as np
 import pytest
 
+import bounds
 from oracle import oracle as orc
 from paper_2109_04528_amd import inputs as gen
 
 pytestmark = pytest.mark.gpu
-U = 2.0 ** -53
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLD = json.load(open(os.path.join(HERE, "golden", "oracle_values.json")))
 
@@ -20,18 +21,6 @@ GOLD = json.load(open(os.path.join(HERE, "golden", "oracle_values.json")))
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def kappa(O):
-    C = np.eye(O.shape[0]) - O
-    C = np.tril(C) + np.tril(C, -1).conj().T
-    w = np.linalg.eigvalsh(C)
-    return float(w[-1] / w[0])
-
-
-def bound(O, sum_abs):
-    n = O.shape[0] // 2
-    return 8.0 * max(n, 9) * kappa(O) * U * sum_abs
 
 
 @pytest.fixture(scope="module")
@@ -54,7 +43,7 @@ def test_removal_vs_oracle(ctx, label, O):
     say(f"case removal {label}")
     r = ctx.eval_removal(O)
     q = orc.tor(O, mode=orc.QUAD)
-    b = bound(O, q.sum_abs)
+    b = bounds.sum_bound(q.sum_sq, bounds.U64, bounds.UQ)
     say(f"  gpu={r.value!r} oracle={q.value!r} diff={abs(r.value - q.value):.3e} bound={b:.3e} ms={r.device_ms:.2f}")
     assert r.status == 0
     assert abs(r.value - q.value) <= b
@@ -69,13 +58,11 @@ def test_removal_golden(ctx, name):
     say(f"case removal golden {name}")
     r = ctx.eval_removal(O)
     want = g["tor_hi"] + g["tor_lo"]
-    b = bound(O, g["sum_abs"])
-    # an FP64 oracle value carries the same kind of error as the GPU's
-    if g["oracle_mode"] == "f64":
-        b *= 2
+    b = bounds.sum_bound(g["sum_sq"], bounds.U64, bounds.UNIT_OF_MODE[g["oracle_mode"]])
     say(f"  gpu={r.value!r} oracle={want!r} rel={abs(r.value - want) / abs(want):.3e} "
         f"bound_rel={b / abs(want):.3e} ms={r.device_ms:.2f}")
     assert r.status == 0
+    assert b <= 1e-2 * abs(want)
     assert abs(r.value - want) <= b
 
 

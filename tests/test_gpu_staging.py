@@ -175,6 +175,8 @@ def test_structure_tolerance(ctxs):
     big[n + 1, n + 3] += 1e-9
     rt, rb = h.eval(tiny), h.eval(big)
     assert rt.path == 1 and rb.path == 2
+    # the GPU evaluates the perturbed matrix, the oracle the original: the
+    # worst-case term bound also covers the first-order effect of 1e-18
     q = orc.tor(O, mode=orc.QUAD)
     assert abs(rt.value - q.value) <= 8.0 * n * kappa(O) * U * q.sum_abs
 
