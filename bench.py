@@ -170,6 +170,52 @@ def serve_stream(ctx, reqs, seed, rate_hz):
             "mean_ms": 1e3 * sum(lat) / len(lat), "max_ms": 1e3 * lat[-1]}
 
 
+GOLDEN = "tests/golden/oracle_values.json"
+
+
+def precision_report(stream, ws):
+    """Relative errors of the FP64 and the double-double factor paths against
+    the stored oracle values (tests/golden/oracle_values.json: __float128 at
+    n = 10, 16, 20, x87 extended at n = 24 and 30), with R, each result's
+    err_est and the tolerance the tests use (6 standard deviations of
+    4 sqrt(u_gpu^2 + u_oracle^2) sqrt(sum t^2)).  At n = 24 and 30 the
+    double-double figure is bounded by the extended reference's own rounding
+    (about 2^-64 sqrt(sum t^2))."""
+    import numpy as np
+    from paper_2109_04528_amd import TOR_FACTOR_DD, Context, inputs
+    gold = json.load(open(os.path.join(ROOT, GOLDEN)))
+    unit = {"quad": 2.0 ** -113, "ld": 2.0 ** -64, "f64": 2.0 ** -53}
+    rows = []
+    with Context(device=0, stream=stream, workspace=ws) as fc, \
+            Context(device=0, stream=stream, workspace=ws, flags=TOR_FACTOR_DD) as qc:
+        for name in sorted(gold):
+            g = gold[name]
+            if g["oracle_mode"] not in ("quad", "ld"):
+                continue
+            O = inputs.random_O(g["n"], g["seed"], g["r_lo"], g["r_hi"], g["eta"])
+            if inputs.sha256(O) != g["sha256"]:
+                raise RuntimeError(f"{name}: generator output differs from the stored input")
+            want = g["tor_hi"] + g["tor_lo"]
+            rf, rq = fc.eval(O), qc.eval(O)
+            dq = (rq.tor - g["tor_hi"]) + (rq.tor_lo - g["tor_lo"])
+            sq = math.sqrt(g["sum_sq"])
+            rows.append({"case": name, "n": g["n"], "reference": g["oracle_mode"], "R": g["sum_abs"] / abs(want),
+                         "fp64_rel_error": abs(rf.value - want) / abs(want), "fp64_err_est": rf.err_est,
+                         "fp64_bound_rel": 24 * math.hypot(2.0 ** -53, unit[g["oracle_mode"]]) * sq / abs(want),
+                         "dd_rel_error": abs(dq) / abs(want), "dd_err_est": rq.err_est,
+                         "dd_bound_rel": 24 * math.hypot(2.0 ** -100, unit[g["oracle_mode"]]) * sq / abs(want),
+                         "dd_kernel_ms": rq.device_ms})
+    by_n = {}
+    for row in rows:
+        by_n.setdefault(row["n"], []).append(row)
+    summary = {str(k): {"cases": len(v), "reference": v[0]["reference"],
+                        "fp64_rel_error_max": max(x["fp64_rel_error"] for x in v),
+                        "fp64_rel_error_median": float(np.median([x["fp64_rel_error"] for x in v])),
+                        "dd_rel_error_max": max(x["dd_rel_error"] for x in v),
+                        "R_max": max(x["R"] for x in v)} for k, v in sorted(by_n.items())}
+    return {"source": GOLDEN, "summary_by_n": summary, "cases": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +234,9 @@ def main():
                     help="click-pattern probabilities of one 32-mode state (0: skip)")
     ap.add_argument("--quad", type=int, default=1,
                     help="also time the same n=30 Torontonian with the double-double factor")
+    ap.add_argument("--precision", type=int, default=1,
+                    help="errors of the FP64 and double-double paths against the stored oracle values")
+    ap.add_argument("--compare-seeds", type=int, default=8, help="seeds of the n=24 method comparison")
     ap.add_argument("--profile-traffic", action="store_true",
                     help="one n=30 Torontonian and one 256 MiB device copy, for the HBM counters")
     ap.add_argument("--force-complex", action="store_true",
@@ -328,23 +377,33 @@ def main():
 
     compare = None
     if args.compare:
+        # the pair workload, seeds 0..7: the append form (real and complex),
+        # the paper's removal order and a fresh factorisation per subset
+        # (complex, as the removal order is), kernel times
         from paper_2109_04528_amd.flops import removal_flops
-        O24 = inputs.random_O(24, 0, 0.5, 1.0, 0.7)
-        ctx.eval(O24)
-        ra = ctx.eval(O24)
-        ctx.eval_removal(O24)
-        rr = ctx.eval_removal(O24)
+        rows = []
         with Context(device=0, stream=stream, workspace=ws, flags=TOR_FORCE_COMPLEX) as cc:
-            cc.eval(O24)
-            rc_ = cc.eval(O24)
-            rp = cc.eval_plain(O24)  # complex, as the removal order is
-        compare = {"workload": "n=24, r~U[0.5,1], eta=0.7, seed 0 (2^24 subsets), kernel times",
-                   "append_real_ms": ra.device_ms, "append_complex_ms": rc_.device_ms,
-                   "removal_order_ms": rr.device_ms, "plain_ms": rp.device_ms,
-                   "removal_tflops": removal_flops(24) / (rr.device_ms * 1e-3) / 1e12,
-                   "removal_over_plain": rp.device_ms / rr.device_ms,
-                   "append_complex_over_removal": rr.device_ms / rc_.device_ms,
-                   "append_real_over_removal": rr.device_ms / ra.device_ms}
+            for seed in range(args.compare_seeds):
+                O24 = inputs.random_O(24, seed, 0.5, 1.0, 0.7)
+                ctx.eval(O24)
+                ra = ctx.eval(O24)
+                ctx.eval_removal(O24)
+                rr = ctx.eval_removal(O24)
+                cc.eval(O24)
+                rc_ = cc.eval(O24)
+                rp = cc.eval_plain(O24)
+                rows.append({"seed": seed, "append_real_ms": ra.device_ms, "append_complex_ms": rc_.device_ms,
+                             "removal_order_ms": rr.device_ms, "plain_ms": rp.device_ms})
+        med = {k: float(np.median([row[k] for row in rows]))
+               for k in ("append_real_ms", "append_complex_ms", "removal_order_ms", "plain_ms")}
+        compare = {"workload": f"n=24, r~U[0.5,1], eta=0.7, seeds 0..{args.compare_seeds - 1} (2^24 subsets each), "
+                               "kernel times, medians over the seeds",
+                   **med, "per_seed": rows,
+                   "removal_tflops": removal_flops(24) / (med["removal_order_ms"] * 1e-3) / 1e12,
+                   "removal_over_plain": med["plain_ms"] / med["removal_order_ms"],
+                   "append_complex_over_removal": med["removal_order_ms"] / med["append_complex_ms"],
+                   "append_real_over_removal": med["removal_order_ms"] / med["append_real_ms"],
+                   "append_real_over_plain": med["plain_ms"] / med["append_real_ms"]}
         print("bench: method comparison done", file=sys.stderr, flush=True)
 
     quad = None
@@ -354,13 +413,21 @@ def main():
             qc.eval(O)
             qms = [qc.eval(O).device_ms for _ in range(3)]
             rq = qc.eval(O)
+        qms_med = float(np.median(qms))
         # the FP64 result's actual error, measured against the double-double one
-        quad = {"n": n, "kernel_ms": float(np.median(qms)),
-                "subset_dets_per_s": (1 << n) / (float(np.median(qms)) * 1e-3),
+        quad = {"n": n, "kernel_ms": qms_med, "tor_per_s": 1e3 / qms_med,
+                "subset_dets_per_s": (1 << n) / (qms_med * 1e-3),
+                "alg_dd_ops_per_s": tor_flops(n, real=True) / (qms_med * 1e-3),
                 "tor_hi": rq.tor, "tor_lo": rq.tor_lo, "err_est": rq.err_est,
                 "fp64_path_rel_error": abs(r.value - rq.value) / abs(rq.value),
-                "factor": "double-double (TOR_FACTOR_DD), real quadrature form"}
+                "factor": "double-double (TOR_FACTOR_DD), real quadrature form; alg_dd_ops_per_s counts "
+                          "the FP64 path's algorithmic operations, each done in double-double"}
         print("bench: double-double factor done", file=sys.stderr, flush=True)
+
+    precision = None
+    if args.precision:
+        precision = precision_report(stream, ws)
+        print("bench: precision report done", file=sys.stderr, flush=True)
 
     click = None
     if args.click > 0:
@@ -432,6 +499,7 @@ def main():
         "batch": batch,
         "n34": big,
         "quad": quad,
+        "precision": precision,
         "click": click,
         "compare_n24": compare,
         "serving": serve,
