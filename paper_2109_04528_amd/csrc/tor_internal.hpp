@@ -120,9 +120,11 @@ __host__ __device__ constexpr long long Gsum(long long s) { return s <= 0 ? 0 : 
 
 // Per-wave stack of a matrix of N modes split at depth k, for a kernel that
 // finishes the last R modes in LDS and registers (LA = N - R tier-A levels):
-//  * the root node, eliminated in place: NSZ(N) scalars with the matrix's
-//    own array stride NB(N) (an include step only rewrites blocks of the
-//    modes that remain, each by the lane that reads it);
+//  * the root node, NSZ(N) scalars: the final root node of N-k modes with
+//    its own stride NB(N-k) when the root path ran in LDS, or the node
+//    eliminated in place with the matrix's stride NB(N) (an include step
+//    only rewrites blocks of the modes that remain, each by the lane that
+//    reads it);
 //  * tier-A slots l = k+1 .. LA-1, slot l holding a node of N - l modes with
 //    its own stride NB(N - l);
 //  * the running determinants of the tier-A levels (LA + 1 real values).

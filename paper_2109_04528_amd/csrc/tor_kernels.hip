@@ -298,6 +298,53 @@ __device__ void elim_inplace(const S *src, int snb, S *dst, int dnb, int s, int 
     elim_global_body(src, snb, dst, dnb, (S *)nullptr, 0, s, lane, pdet, bad);
 }
 
+// the root path in LDS: one include step in place on a node of s modes with
+// nb blocks per granule array (each lane rewrites only blocks it reads, and
+// never a pivot row, as in elim_inplace)
+template <class S>
+__device__ __forceinline__ void elim_lds(S *node, int nb, int s, int lane, RT<S> &pdet, int &bad)
+{
+    const int m = s - 1;
+    const Piv<S> pv = node_pivot(node, nb, m);
+    pdet = pv.pdet;
+    if (!is_pos(pv.pdet) || !is_pos(pv.inv_a))
+        bad = 1;
+    for (int bi = lane; bi < NB(m); bi += 64) {
+        int a, b;
+        block_ab(bi, a, b);
+        S o[4];
+        elim_block<S, false>(node, nb, m, a, b, bidx(a, b), pv, o);
+        put_block(node, nb, bi, o);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void st_g(double *p, double v) { *(__attribute__((address_space(1))) double *)p = v; }
+template <class S>
+__device__ __forceinline__ void st_g(S *p, S v)
+{
+    dv2 raw;
+    __builtin_memcpy(&raw, &v, 16);
+    *(__attribute__((address_space(1))) dv2 *)p = raw;
+}
+
+// the first s modes of a node with snb blocks per granule array, copied into
+// a node with dnb (global source or destination as flagged)
+template <class S, bool SRC_G, bool DST_G>
+__device__ __forceinline__ void copy_node(const S *src, int snb, S *dst, int dnb, int s, int lane)
+{
+    constexpr int G = EPG((int)sizeof(S));
+    const int ga = G * NB(s);  // scalars of one granule array
+    for (int e = lane; e < NSZ(s); e += 64) {
+        const int g = e / ga, r = e - g * ga;
+        const S v = SRC_G ? ld_g(&src[g * G * snb + r]) : src[g * G * snb + r];
+        if constexpr (DST_G)
+            st_g(&dst[g * G * dnb + r], v);
+        else
+            dst[g * G * dnb + r] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // View t of the tier-B tables: for the node of level jl with id i (bit
 // jl-1-m of i = decision on the m-th mode below the tier-A leaf, 1 =
@@ -622,7 +669,8 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
     constexpr int R = T + B;
     constexpr int BL = B - L;                // levels expanded in LDS
     constexpr int NN_MAX = 1 << (BL - 1);    // include nodes of the last LDS level
-    __shared__ S bufB[NodePlacement<R, BL, (int)sizeof(S), L>{}.off[1 << BL] / (int)sizeof(S)];
+    constexpr int kBufScalars = NodePlacement<R, BL, (int)sizeof(S), L>{}.off[1 << BL] / (int)sizeof(S);
+    __shared__ S bufB[kBufScalars];
     __shared__ S nBa[NN_MAX];
     __shared__ RT<S> nInv[2 * NN_MAX];
     __shared__ RT<S> ndet[1 << BL];
@@ -663,21 +711,44 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
         RT<S> *sdet = reinterpret_cast<RT<S> *>(wscr + tslot_off(N, k, LA));
         int bad = 0;
 
-        // root: decisions on modes 0..k-1 given by the bits of root.  The
-        // first include reads the matrix, the later ones rewrite the root
-        // node in place; it keeps the matrix's array stride NB(N) throughout
-        // (tier-A slot l holds a node of N-l modes with its own stride)
+        // root: decisions on modes 0..k-1 given by the bits of root.  When
+        // the node at the first included level fits the LDS buffer (free
+        // until the first leaf), it is copied there, every include
+        // eliminates in place in LDS, and only the final root node (N-k
+        // modes, stride NB(N-k)) is written to the wave's stack.  Otherwise
+        // the first include reads the matrix and the later ones rewrite the
+        // root node in place in the stack with the matrix's stride NB(N).
         const S *rsrc = C;
-        const int rnb = NB(N);
+        int rnb = NB(N);
         RT<S> rdet = rconst<RT<S>>(1.0);
         int rinc = 0;
-        for (int l = 0; l < k; ++l) {
-            if ((root >> l) & 1) {
-                RT<S> pd;
-                elim_inplace<S>(rsrc, rnb, wscr, rnb, N - l, lane, pd, bad);
-                rdet = rmul(rdet, pd);
-                ++rinc;
-                rsrc = wscr;
+        const unsigned long long rbits = (unsigned long long)root & ((1ull << k) - 1);
+        const int l0 = rbits ? __builtin_ctzll(rbits) : k;  // first included level
+        if (rbits && NSZ(N - l0) <= kBufScalars) {
+            const int nb0 = NB(N - l0);
+            copy_node<S, true, false>(C, NB(N), bufB, nb0, N - l0, lane);
+            __syncthreads();
+            for (int l = l0; l < k; ++l) {
+                if ((rbits >> l) & 1) {
+                    RT<S> pd;
+                    elim_lds<S>(bufB, nb0, N - l, lane, pd, bad);
+                    rdet = rmul(rdet, pd);
+                    ++rinc;
+                }
+            }
+            copy_node<S, false, true>(bufB, nb0, wscr, NB(N - k), N - k, lane);
+            __syncthreads();
+            rsrc = wscr;
+            rnb = NB(N - k);
+        } else {
+            for (int l = 0; l < k; ++l) {
+                if ((rbits >> l) & 1) {
+                    RT<S> pd;
+                    elim_inplace<S>(rsrc, rnb, wscr, rnb, N - l, lane, pd, bad);
+                    rdet = rmul(rdet, pd);
+                    ++rinc;
+                    rsrc = wscr;
+                }
             }
         }
 
