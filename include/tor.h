@@ -60,7 +60,8 @@ extern "C" {
 #define TOR_E_NOT_PD (-2)      /* I - O is not Hermitian positive definite (a
                                   tested pivot <= 0 or NaN)                         */
 #define TOR_E_NUMERIC (-3)     /* a non-finite result with every tested pivot
-                                  positive                                          */
+                                  positive, still so after its failed roots ran
+                                  once more (see tor_eval)                          */
 #define TOR_E_BUSY (-4)        /* admission refused: serving queue is full          */
 #define TOR_E_NOMEM (-5)       /* device or host allocation failed                  */
 #define TOR_E_DEVICE (-6)      /* no usable GPU, or a HIP runtime error             */
@@ -117,8 +118,8 @@ typedef struct {
     float device_ms;           /* device time of the launch that produced it (served
                                   requests: their share of the launches they ran in)    */
     int launches;              /* launches of the recursive kernel that computed it: 1,
-                                  or for a served request the chunked launches it took
-                                  part in                                                */
+                                  2 when failed roots ran once more (tor_eval), or for a
+                                  served request the chunked launches it took part in  */
 } tor_result;
 
 /* Defaults for every field (device 0, library stream and workspace, max_n 40). */
@@ -136,7 +137,16 @@ void tor_destroy(tor_ctx *ctx);
  * with up to max_inflight concurrent serving requests. */
 size_t tor_workspace_size(int max_n, int split_k, int max_inflight);
 
-/* Torontonian of one 2n x 2n matrix (Eq. 2), recursive GPU path. */
+/* Torontonian of one 2n x 2n matrix (Eq. 2), recursive GPU path.  Each of
+ * the 2^k subtree roots writes its partial sum to a slot of its own, which a
+ * later run of the same root overwrites.  A root whose partial sum comes out
+ * non-finite while every pivot it tested was positive (a numeric failure, not
+ * a property of the input) is therefore run once more: tor_eval, tor_eval_batch,
+ * tor_eval_partials and tor_click_probs relaunch the range of failed roots of
+ * each such matrix, then reduce its slots again in the same fixed order, so a
+ * recovered result is bit for bit the result of a clean run and reports
+ * launches = 2.  A root that fails again gives TOR_E_NUMERIC.  Serving and
+ * tor_eval_static report TOR_E_NUMERIC without a second run. */
 int tor_eval(tor_ctx *ctx, int n, const double *O, long ld, tor_result *out);
 
 /* For callers that cannot allocate device or pinned memory -- code under HIP
@@ -245,6 +255,16 @@ int tor_debug_math(tor_ctx *ctx, int count, const double *x, double *out);
  * *tflops receives 2 * 16 * iters * lanes / time; *ms (may be NULL) the
  * kernel time.  Uses the context's workspace. */
 int tor_debug_fma_peak(tor_ctx *ctx, int iters, double *tflops, float *ms);
+
+/* Test aid for the recovery described at tor_eval: in the next synchronous
+ * evaluation on this context (tor_eval, tor_eval_batch, tor_eval_partials,
+ * tor_click_probs), subtree root `root` of its first matrix reports a
+ * numeric failure in its first `runs` launches (runs = 1: the re-run
+ * recovers it; runs = 2: the result is TOR_E_NUMERIC; runs = 0 or root < 0
+ * clears the request).  A root at or beyond that matrix's 2^k roots is
+ * ignored.  The request is used up by that one evaluation.  Errors:
+ * TOR_E_INVAL (null ctx, runs outside 0..2). */
+int tor_debug_fail_root(tor_ctx *ctx, long long root, int runs);
 
 /* Serving policy.  Each chunked serving launch runs at most chunk_subsets
  * subsets (default 2^29, about 2.5 ms at n = 30 rates) taken from the

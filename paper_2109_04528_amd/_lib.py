@@ -41,7 +41,7 @@ EXPORTS = [
     "tor_default_options", "tor_create", "tor_destroy", "tor_workspace_size", "tor_eval",
     "tor_eval_batch", "tor_eval_plain", "tor_eval_partials", "tor_submit", "tor_poll",
     "tor_drain", "tor_debug_math", "tor_debug_fma_peak", "tor_strerror", "tor_autotune", "tor_tune_save", "tor_tune_load",
-    "tor_serve_config", "tor_click_probs", "tor_eval_removal", "tor_eval_static",
+    "tor_serve_config", "tor_click_probs", "tor_eval_removal", "tor_eval_static", "tor_debug_fail_root",
 ]
 
 TOR_TUNE_REAL = 0x1
@@ -148,6 +148,8 @@ def load(path: str = LIB_PATH):
     lib.tor_debug_math.restype = ctypes.c_int
     lib.tor_debug_fma_peak.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_float)]
     lib.tor_debug_fma_peak.restype = ctypes.c_int
+    lib.tor_debug_fail_root.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int]
+    lib.tor_debug_fail_root.restype = ctypes.c_int
     lib.tor_serve_config.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_longlong, ctypes.c_double,
                                      ctypes.c_int]
     lib.tor_serve_config.restype = ctypes.c_int
@@ -463,6 +465,13 @@ class Context:
         if rc != TOR_OK:
             raise TorError(rc, "tor_debug_fma_peak")
         return tf.value, ms.value
+
+    def debug_fail_root(self, root: int, runs: int = 1):
+        """The next synchronous evaluation's first matrix: root `root` reports
+        a numeric failure in its first `runs` launches (tor_debug_fail_root)."""
+        rc = self._lib.tor_debug_fail_root(self._h, int(root), int(runs))
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_debug_fail_root")
 
 
 def workspace_size(max_n: int, split_k: int = 0, max_inflight: int = 1) -> int:

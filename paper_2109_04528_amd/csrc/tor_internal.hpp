@@ -61,7 +61,14 @@ struct MainParams {
     unsigned long long *counter;  // queue head, zero before the launch
     char *scratch;                // per-wave stack of the upper include levels
     long long scratch_stride;     // bytes per wave
+    long long fail_item1;         // debug: 1 + the queue item whose root reports a
+                                  // numeric failure (0: none)
 };
+// root slot flag (fourth double): a tested pivot failed (I - O is not
+// positive definite), or the root's sum is not finite (a numeric failure,
+// which the host may re-run); the per-matrix reduction keeps the largest
+constexpr double SLOT_NOT_PD = 1.0;
+constexpr double SLOT_NUMERIC = 0.5;
 
 struct PlainParams {
     const void *C;                // packed reversed matrix of N modes

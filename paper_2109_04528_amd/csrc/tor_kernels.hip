@@ -830,11 +830,14 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
         }
         const int anybad = __any(bad);
         if (lane == 0) {
+            // slots are overwritten, never accumulated, so running a root
+            // again (the host's recovery from a numeric failure) is idempotent
+            const bool forced = (long long)item + 1 == prm.fail_item1;
             double *sl = P.slots + 4 * root;
-            sl[0] = h;
+            sl[0] = forced ? __builtin_nan("") : h;
             sl[1] = l;
             sl[2] = ab;
-            sl[3] = anybad ? 1.0 : 0.0;
+            sl[3] = anybad ? SLOT_NOT_PD : (forced || !__builtin_isfinite(h)) ? SLOT_NUMERIC : 0.0;
         }
     }
 }

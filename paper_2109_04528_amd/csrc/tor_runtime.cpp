@@ -123,6 +123,11 @@ struct tor_ctx {
     int admitted = 0;
     int max_queue = 1 << 16;
     ServeCfg serve;  // guarded by smu
+    // debug (tor_debug_fail_root): root dbg_root of the next synchronous
+    // evaluation's first matrix reports a numeric failure in its first
+    // dbg_runs launches
+    long long dbg_root = -1;
+    int dbg_runs = 0;
     char *pool = nullptr;
     size_t pool_bytes = 256ull << 20;
     std::map<size_t, size_t> pool_free;  // offset -> length
@@ -506,7 +511,7 @@ LaunchLayout launch_layout(int count, int nred, long long stride)
 // hold data the descriptors point to, and the caller has already sized the
 // workspace (a reallocation here would move that data).
 int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const std::vector<int> &reduce,
-               size_t ws_off, int grid, std::vector<double> *results, float *ms)
+               size_t ws_off, int grid, std::vector<double> *results, float *ms, long long fail_item1 = 0)
 {
     const int count = (int)descs.size();
     long long total = 0, stack = 0;
@@ -556,6 +561,7 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     mp.counter = dCounter;
     mp.scratch = dScr;
     mp.scratch_stride = stride;
+    mp.fail_item1 = fail_item1;
     // the double-double factor always sums in double-double
     const bool dd = ctx->opt.accum != TOR_ACCUM_FP64 || path == PATH_QUAD;
     if (e == hipSuccess)
@@ -588,7 +594,8 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
 // the workspace from byte base on.  results: 4 doubles per matrix (input
 // order).
 int run_recursive(tor_ctx *ctx, int path, std::vector<Mat *> &mats, std::vector<int> &ks,
-                  std::vector<double> &results, float *ms, std::vector<double> *slots_out, size_t base)
+                  std::vector<double> &results, float *ms, std::vector<double> *slots_out, size_t base,
+                  std::vector<int> *launches)
 {
     const int count = (int)mats.size();
     std::vector<int> order(count);
@@ -624,10 +631,77 @@ int run_recursive(tor_ctx *ctx, int path, std::vector<Mat *> &mats, std::vector<
         d.nroots = 1ll << d.k;
         red[s] = s;
     }
+    // debug: the queue item of root dbg_root of the first input matrix
+    int dbg_s = 0;
+    while (order[dbg_s] != 0)
+        ++dbg_s;
+    long long dbg_item1 = 0;
+    const bool use_dbg = launches != nullptr;  // evaluations only, not the autotuner
+    if (use_dbg && ctx->dbg_runs > 0 && ctx->dbg_root >= 0 && ctx->dbg_root < descs[dbg_s].nroots) {
+        for (int s = 0; s < dbg_s; s++)
+            dbg_item1 += descs[s].nroots;
+        dbg_item1 += ctx->dbg_root + 1;
+    }
+    const long long dbg_root = ctx->dbg_root;
+    int dbg_runs = dbg_item1 ? ctx->dbg_runs : 0;
+    if (use_dbg)
+        ctx->dbg_runs = 0;
     std::vector<double> res;
-    rc = run_launch(ctx, path, descs, red, off, grid, &res, ms);
+    rc = run_launch(ctx, path, descs, red, off, grid, &res, ms, dbg_item1);
     if (rc != TOR_OK)
         return rc;
+    --dbg_runs;
+    std::vector<int> runs(count, 1);
+    // Recovery: a matrix whose roots report numeric failures and no failed
+    // pivot runs the range of its failed roots once more.  Root slots are
+    // overwritten, not accumulated, so a root that runs again (or a good one
+    // inside the range) leaves exactly the value a clean launch leaves, and
+    // the reduction sums the slots in the same fixed order.
+    std::vector<int> redo;
+    for (int s = 0; s < count; s++)
+        if (res[4 * (size_t)s + 3] == SLOT_NUMERIC)
+            redo.push_back(s);
+    if (!redo.empty()) {
+        std::vector<double> hs(4 * (size_t)nslots);
+        hipError_t e = hipMemcpy(hs.data(), ctx->ws + s_off[0], sizeof(double) * 4 * nslots, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return hip_status(e);
+        std::vector<ProblemDesc> rd;
+        std::vector<int> rred;
+        long long item1 = 0, items = 0;
+        for (int s : redo) {
+            const long long first = (long long)(s_off[s] - s_off[0]) / (4 * (long long)sizeof(double));
+            long long lo = -1, hi = -1;
+            for (long long r = 0; r < descs[s].nroots; r++)
+                if (hs[4 * (first + r) + 3] == SLOT_NUMERIC) {
+                    if (lo < 0)
+                        lo = r;
+                    hi = r;
+                }
+            ProblemDesc d = descs[s];
+            d.root_begin = lo;
+            d.nroots = hi - lo + 1;
+            if (s == dbg_s && dbg_runs > 0 && dbg_root >= lo && dbg_root <= hi)
+                item1 = items + (dbg_root - lo) + 1;
+            items += d.nroots;
+            rred.push_back((int)rd.size());
+            rd.push_back(d);
+        }
+        std::vector<double> res2;
+        rc = run_launch(ctx, path, rd, rred, off, grid, &res2, nullptr, item1);
+        if (rc != TOR_OK)
+            return rc;
+        for (size_t i = 0; i < redo.size(); i++) {
+            for (int j = 0; j < 4; j++)
+                res[4 * (size_t)redo[i] + j] = res2[4 * i + j];
+            ++runs[redo[i]];
+        }
+    }
+    if (launches) {
+        launches->assign(count, 1);
+        for (int s = 0; s < count; s++)
+            (*launches)[order[s]] = runs[s];
+    }
     results.assign(4 * (size_t)count, 0.0);
     for (int s = 0; s < count; s++)
         for (int j = 0; j < 4; j++)
@@ -665,7 +739,7 @@ void fill_result(const Mat &st, int path, const double *r, float ms, tor_result 
     out->subsets = 1ull << st.n;
     // a pivot that is not positive in some subset: I - O is not positive
     // definite (the all-include subset is I - O itself)
-    out->status = r[3] != 0.0 ? TOR_E_NOT_PD : !std::isfinite(r[0]) ? TOR_E_NUMERIC : TOR_OK;
+    out->status = r[3] >= SLOT_NOT_PD ? TOR_E_NOT_PD : (r[3] > 0.0 || !std::isfinite(r[0])) ? TOR_E_NUMERIC : TOR_OK;
     out->path = api_path(path);
     out->device_ms = ms;
     out->launches = 1;
@@ -716,12 +790,14 @@ int run_staged(tor_ctx *ctx, std::vector<Mat *> &mats, const std::vector<int> &i
         if (fixed_k < 0)
             batch_ks(ctx, path, grp, ks);
         std::vector<double> res;
+        std::vector<int> runs;
         float ms = 0.f;
-        int rc = run_recursive(ctx, path, grp, ks, res, &ms, slots_out, base);
+        int rc = run_recursive(ctx, path, grp, ks, res, &ms, slots_out, base, &runs);
         if (rc != TOR_OK)
             return rc;
         for (size_t j = 0; j < grp.size(); j++) {
             fill_result(*grp[j], path, &res[4 * j], ms, &out[gidx[j]]);
+            out[gidx[j]].launches = runs[j];
             if (out[gidx[j]].status != TOR_OK && first_err == TOR_OK)
                 first_err = out[gidx[j]].status;
         }
@@ -1086,7 +1162,7 @@ int tune_one(tor_ctx *ctx, int path, int n, TuneEntry &best)
                 ctx->tune[path][std::min(N, MAX_N)] = TuneEntry{true, k, w, 0.f};
                 std::vector<double> res;
                 float ms_ = 0.f;
-                rc = run_recursive(ctx, path, ms, ks, res, &ms_, nullptr, base);
+                rc = run_recursive(ctx, path, ms, ks, res, &ms_, nullptr, base, nullptr);
                 ctx->tune[path][std::min(N, MAX_N)] = save;
                 if (rc != TOR_OK)
                     return rc;
@@ -1786,6 +1862,16 @@ int tor_debug_fma_peak(tor_ctx *ctx, int iters, double *tflops, float *ms_out)
 }
 
 // ---- serving ---------------------------------------------------------------
+
+int tor_debug_fail_root(tor_ctx *ctx, long long root, int runs)
+{
+    if (!ctx || runs < 0 || runs > 2)
+        return TOR_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->dbg_root = root;
+    ctx->dbg_runs = root < 0 ? 0 : runs;
+    return TOR_OK;
+}
 
 int tor_submit(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long *ticket)
 {
