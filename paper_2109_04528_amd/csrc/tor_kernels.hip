@@ -214,6 +214,32 @@ __device__ __forceinline__ Piv<S> node_pivot(const S *node, int nb, int m)
     return pivot(re(blk(node, nb, bi, 0)), blk(node, nb, bi, 2), re(blk(node, nb, bi, 3)));
 }
 
+// the update of block (a, b) from its row blocks A = (m, a), Bk = (m, b)
+template <class S>
+__device__ __forceinline__ void elim_math(const S *A, const S *Bk, const S *H, bool diag, const Piv<S> &pv, S *o)
+{
+    const S ra0 = A[0], ra1 = A[1];
+    const S qa0 = sub_mul(A[2], ra0, pv.ba), qa1 = sub_mul(A[3], ra1, pv.ba);
+    const S rb0 = Bk[0], rb1 = Bk[1];
+    const S qb0 = sub_mul(Bk[2], rb0, pv.ba), qb1 = sub_mul(Bk[3], rb1, pv.ba);
+    const S ua0 = scale(ra0, pv.inv_a), ua1 = scale(ra1, pv.inv_a);
+    const S va0 = scale(qa0, pv.inv_g), va1 = scale(qa1, pv.inv_g);
+    o[0] = upd(H[0], ua0, rb0, va0, qb0);
+    o[1] = upd(H[1], ua0, rb1, va0, qb1);
+    o[2] = upd(H[2], ua1, rb0, va1, qb0);
+    o[3] = upd(H[3], ua1, rb1, va1, qb1);
+    // diagonal block: real diagonal, conjugate upper entry.  Nothing reads
+    // the upper entry of a diagonal block (pivots read entries 0, 2, 3, the
+    // lanes read the lower triangle), so real scalars leave it as computed.
+    if constexpr (std::is_same<S, c64>::value) {
+        if (diag) {
+            o[0] = fix_diag(o[0]);
+            o[3] = fix_diag(o[3]);
+            o[1] = conj_of(o[2]);
+        }
+    }
+}
+
 template <class S, bool GLOBAL = false>
 __device__ __forceinline__ void elim_block(const S *node, int nb, int m, int a, int b, int ih, const Piv<S> &pv,
                                            S *o)
@@ -228,21 +254,7 @@ __device__ __forceinline__ void elim_block(const S *node, int nb, int m, int a, 
         get_block(node, nb, bidx(m, b), Bk);
         get_block(node, nb, ih, H);
     }
-    const S ra0 = A[0], ra1 = A[1];
-    const S qa0 = sub_mul(A[2], ra0, pv.ba), qa1 = sub_mul(A[3], ra1, pv.ba);
-    const S rb0 = Bk[0], rb1 = Bk[1];
-    const S qb0 = sub_mul(Bk[2], rb0, pv.ba), qb1 = sub_mul(Bk[3], rb1, pv.ba);
-    const S ua0 = scale(ra0, pv.inv_a), ua1 = scale(ra1, pv.inv_a);
-    const S va0 = scale(qa0, pv.inv_g), va1 = scale(qa1, pv.inv_g);
-    o[0] = upd(H[0], ua0, rb0, va0, qb0);
-    o[1] = upd(H[1], ua0, rb1, va0, qb1);
-    o[2] = upd(H[2], ua1, rb0, va1, qb0);
-    o[3] = upd(H[3], ua1, rb1, va1, qb1);
-    if (a == b) {  // diagonal block: real diagonal, conjugate upper entry
-        o[0] = fix_diag(o[0]);
-        o[3] = fix_diag(o[3]);
-        o[1] = conj_of(o[2]);
-    }
+    elim_math(A, Bk, H, a == b, pv, o);
 }
 
 
@@ -282,13 +294,62 @@ __device__ __forceinline__ void elim_global_body(const S *src, int snb, S *dst, 
     __syncthreads();
 }
 
-// the same with src and dst distinct (tier A), so that loads of the next
-// blocks may move ahead of the stores of this one
+// the same with src and dst distinct (tier A).  A step of at most 128
+// blocks (every step that makes a tier-A leaf, and the deeper stack levels)
+// issues the loads of the pivot and of both of each lane's blocks before any
+// arithmetic, so it waits for L2 once instead of once for the pivot and once
+// per pass; larger steps take the loop above.
 template <class S>
 __device__ void elim_global(const S *__restrict__ src, int snb, S *__restrict__ dst, int dnb, S *lds, int nlds, int s,
                             int lane, RT<S> &pdet, int &bad)
 {
-    elim_global_body(src, snb, dst, dnb, lds, nlds, s, lane, pdet, bad);
+    const int m = s - 1;
+    const int nbo = dst ? NB(m) : nlds;
+    if (nbo > 128) {
+        elim_global_body(src, snb, dst, dnb, lds, nlds, s, lane, pdet, bad);
+        return;
+    }
+    const int bi0 = lane, bi1 = lane + 64;
+    const bool h0 = bi0 < nbo, h1 = bi1 < nbo;
+    int a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+    block_ab(bi0, a0, b0);
+    block_ab(bi1, a1, b1);
+    S A0[4], B0[4], H0[4], A1[4], B1[4], H1[4];
+    const int dbi = bidx(m, m);
+    const RT<S> al = re(ld_g(&blk(src, snb, dbi, 0)));
+    const S be = ld_g(&blk(src, snb, dbi, 2));
+    const RT<S> ga = re(ld_g(&blk(src, snb, dbi, 3)));
+    if (h0) {
+        get_block_g(src, snb, bidx(m, a0), A0);
+        get_block_g(src, snb, bidx(m, b0), B0);
+        get_block_g(src, snb, bidx(a0, b0), H0);
+    }
+    if (h1) {
+        get_block_g(src, snb, bidx(m, a1), A1);
+        get_block_g(src, snb, bidx(m, b1), B1);
+        get_block_g(src, snb, bidx(a1, b1), H1);
+    }
+    const Piv<S> pv = pivot(al, be, ga);
+    pdet = pv.pdet;
+    if (!is_pos(pv.pdet) || !is_pos(pv.inv_a))
+        bad = 1;
+    if (h0) {
+        S o[4];
+        elim_math(A0, B0, H0, a0 == b0, pv, o);
+        if (dst)
+            put_block_g(dst, dnb, bi0, o);
+        if (lds && bi0 < nlds)
+            put_block(lds, nlds, bi0, o);
+    }
+    if (h1) {
+        S o[4];
+        elim_math(A1, B1, H1, a1 == b1, pv, o);
+        if (dst)
+            put_block_g(dst, dnb, bi1, o);
+        if (lds && bi1 < nlds)
+            put_block(lds, nlds, bi1, o);
+    }
+    __syncthreads();
 }
 
 // in place (dst == src, or src the read-only matrix): the root path
@@ -396,12 +457,13 @@ __device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcNB, u
         int poff, pnb, pdet, coff, cnb, cdet;
         view_entry<R, B, esz, L>(t, poff, pnb, pdet);
         view_entry<R, B, esz, L>((1 << J) + 2 * i, coff, cnb, cdet);
-        nodeRec[t] = (unsigned long long)poff | ((unsigned long long)pnb << 16) | ((unsigned long long)coff << 32);
+        nodeRec[t] = (unsigned long long)(poff * esz) | ((unsigned long long)(16 * pnb) << 16) |
+                     ((unsigned long long)(coff * esz) << 32);
     }
     for (int bi = lane; bi < NB(R - 1); bi += 64) {
         int a, b;
         block_ab(bi, a, b);
-        blkRec[bi] = (uint32_t)(bidx(a, b) | (a << 16) | (b << 24));
+        blkRec[bi] = (uint32_t)(16 * bidx(a, b) | (16 * a) << 16 | (16 * b) << 24);
     }
 }
 
@@ -412,8 +474,8 @@ struct TierB {
     const uint16_t *srcOff; // per view: offset of its stored node
     const uint8_t *srcNB;   // per view: blocks per granule array of that node
     const uint8_t *srcDet;  // per view: determinant slot (0xff: tier-A leaf)
-    const unsigned long long *nodeRec;  // per include node: parent offset | nb << 16 | own offset << 32
-    const uint32_t *blkRec;             // block index -> bidx(a, b) | a << 16 | b << 24
+    const unsigned long long *nodeRec;  // per include node, bytes: parent | its granule array stride << 16 | own << 32
+    const uint32_t *blkRec;             // block index, bytes: 16 bidx(a, b) | 16 a << 16 | 16 b << 24
     RT<S> *nInv;            // per include node of a level: 1/alpha, 1/gamma1
     S *nBa;                 // per include node of a level: beta/alpha
     RT<S> *ndet;            // per include node: running determinant
@@ -439,24 +501,61 @@ __device__ __forceinline__ void tierB_level(const TierB<S> &tb, RT<S> leafDet, i
             bad = 1;
     }
     __syncthreads();
-#pragma unroll 2
-    for (int it0 = 0; it0 < NN * NBO; it0 += 64) {
-        const int it = it0 + lane;
-        if (it < NN * NBO) {
-            const int i = it / NBO, bi = it - i * NBO;
-            const unsigned long long rec = tb.nodeRec[NN - 1 + i];
-            const uint32_t br = tb.blkRec[bi];
-            const S *par = tb.buf + (int)(rec & 0xffffu);
-            const int pnb = (int)((rec >> 16) & 0xffu);
-            Piv<S> pq;
-            pq.inv_a = tb.nInv[2 * i];
-            pq.inv_g = tb.nInv[2 * i + 1];
-            pq.ba = tb.nBa[i];
-            S o[4];
-            elim_block(par, pnb, m, (int)((br >> 16) & 0xffu), (int)(br >> 24), (int)(br & 0xffffu), pq, o);
-            // the include child i of level J is view 2i+1 of that level
-            put_block(tb.buf + (int)(rec >> 32), NBO, bi, o);
+    // granule g of the block at byte offset o of a node at byte offset p
+    // with arrays st bytes apart: buf + p + g st + o
+    char *const lb = reinterpret_cast<char *>(tb.buf);
+    constexpr int GPB = 4 / EPG((int)sizeof(S));  // granules per block
+    auto pass = [&](int it) {
+        const int i = (int)((unsigned)it / NBO), bi = it - i * NBO;
+        const unsigned long long rec = tb.nodeRec[NN - 1 + i];
+        const uint32_t br = tb.blkRec[bi];
+        const int par = (int)(rec & 0xffffu), st = (int)((rec >> 16) & 0xffffu), cof = (int)(rec >> 32);
+        const int a16 = (int)((br >> 16) & 0xffu), b16 = (int)(br >> 24), h16 = (int)(br & 0xffffu);
+        Piv<S> pq;
+        pq.inv_a = tb.nInv[2 * i];
+        pq.inv_g = tb.nInv[2 * i + 1];
+        pq.ba = tb.nBa[i];
+        S A[4], Bk[4], H[4], o[4];
+        const char *pa = lb + par + a16 + 16 * NB(m), *pb = lb + par + b16 + 16 * NB(m), *ph = lb + par + h16;
+#pragma unroll
+        for (int g = 0; g < GPB; ++g) {
+            const Gran<S> qa = *reinterpret_cast<const Gran<S> *>(pa + g * st);
+            const Gran<S> qb = *reinterpret_cast<const Gran<S> *>(pb + g * st);
+            const Gran<S> qh = *reinterpret_cast<const Gran<S> *>(ph + g * st);
+#pragma unroll
+            for (int j = 0; j < EPG((int)sizeof(S)); ++j) {
+                A[g * EPG((int)sizeof(S)) + j] = qa.e[j];
+                Bk[g * EPG((int)sizeof(S)) + j] = qb.e[j];
+                H[g * EPG((int)sizeof(S)) + j] = qh.e[j];
+            }
         }
+        elim_math(A, Bk, H, a16 == b16, pq, o);
+        // the include child i of level J is view 2i+1 of that level
+        char *pc = lb + cof + 16 * bi;
+#pragma unroll
+        for (int g = 0; g < GPB; ++g) {
+            Gran<S> q;
+#pragma unroll
+            for (int j = 0; j < EPG((int)sizeof(S)); ++j)
+                q.e[j] = o[g * EPG((int)sizeof(S)) + j];
+            *reinterpret_cast<Gran<S> *>(pc + g * 16 * NBO) = q;
+        }
+    };
+    constexpr int TOT = NN * NBO, FULL = TOT / 64;
+    // real path: an empty asm hides that the lane index is the same in every
+    // leaf, so the passes' node and block indices are recomputed per leaf
+    // instead of being held in registers across the whole leaf loop (10
+    // registers less, which the one-wait tier-A step uses; the complex path
+    // has them to spare)
+    int ln = lane;
+    if constexpr (std::is_same<S, double>::value)
+        __asm__ volatile("" : "+v"(ln));
+#pragma unroll 2
+    for (int it0 = 0; it0 < 64 * FULL; it0 += 64)
+        pass(it0 + ln);
+    if constexpr (TOT % 64 != 0) {
+        if (64 * FULL + ln < TOT)
+            pass(64 * FULL + ln);
     }
     __syncthreads();
 }
@@ -759,9 +858,8 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
             // is the same in every leaf, so what the tiers derive from it
             // (block and node indices, table entries) is recomputed in each
             // leaf instead of being held in registers across the whole loop.
-            // That brings the kernel to 256 registers, two waves per SIMD;
-            // the FP64 kernels already fit and run faster with the values
-            // held.
+            // That brings the kernel to 256 registers, two waves per SIMD
+            // (the real FP64 kernel does the same for tier B only).
             int lane = threadIdx.x;
             if constexpr (std::is_same<S, ddr>::value)
                 __asm__ volatile("" : "+v"(lane));
