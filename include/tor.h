@@ -130,7 +130,10 @@ void tor_default_options(tor_options *opt);
  * aligned to 256 bytes), TOR_E_DEVICE (no GPU), TOR_E_NOMEM. */
 int tor_create(tor_ctx **out, const tor_options *opt);
 
-/* Wait for in-flight work, then free every device and host resource. */
+/* Stop the serving scheduler after the launch it has on the GPU, cancel the
+ * served requests that have not completed (their tickets are released), wait
+ * for the context's stream, then free every device and host resource.  A
+ * request must not be polled after its context is destroyed. */
 void tor_destroy(tor_ctx *ctx);
 
 /* Device bytes a caller-provided workspace needs for matrices up to max_n
