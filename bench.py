@@ -232,6 +232,8 @@ def main():
                     help="the n=24 pair workload by the append form, the paper's removal order and plain")
     ap.add_argument("--click", type=int, default=1024,
                     help="click-pattern probabilities of one 32-mode state (0: skip)")
+    ap.add_argument("--click-all", type=int, default=1,
+                    help="every click pattern of a 16- and a 24-mode state at once")
     ap.add_argument("--quad", type=int, default=1,
                     help="also time the same n=30 Torontonian with the double-double factor")
     ap.add_argument("--precision", type=int, default=1,
@@ -447,6 +449,32 @@ def main():
                  "kernel_ms": max(r.device_ms for r in cres), "min_prob": float(probs.min())}
         print("bench: click probabilities done", file=sys.stderr, flush=True)
 
+    click_all = None
+    if args.click_all:
+        # every pattern of one state at once (tor_click_all), against the same
+        # patterns one by one (tor_click_probs) where that is still feasible;
+        # states r ~ U[.5, 1], eta = .7
+        click_all = {}
+        for M, direct in ((16, True), (24, False)):
+            Oa = inputs.random_O(M, 11, 0.5, 1.0, 0.7)
+            ctx.click_all(Oa)
+            t0 = time.perf_counter()
+            pa, _, ra = ctx.click_all(Oa)
+            t1 = time.perf_counter()
+            row = {"modes": M, "patterns": 1 << M, "seconds": t1 - t0, "device_ms": ra.device_ms,
+                   "subset_dets": 1 << M, "subset_dets_one_by_one": 3 ** M,
+                   "sum_of_probs": math.fsum(pa)}
+            if direct:
+                ctx.click_probs(Oa, range(256))
+                t0 = time.perf_counter()
+                pd, _ = ctx.click_probs(Oa, range(1 << M))
+                t1 = time.perf_counter()
+                row["one_by_one_seconds"] = t1 - t0
+                row["speedup"] = row["one_by_one_seconds"] / row["seconds"]
+                row["max_prob_difference"] = float(np.max(np.abs(pa - pd)))
+            click_all[f"M{M}"] = row
+        print("bench: every click pattern done", file=sys.stderr, flush=True)
+
     serve = None
     if args.serve > 0:
         reqs = serve_requests(args.serve, 5)
@@ -501,6 +529,7 @@ def main():
         "quad": quad,
         "precision": precision,
         "click": click,
+        "click_all": click_all,
         "compare_n24": compare,
         "serving": serve,
         "cpu_baseline": cpu,

@@ -228,6 +228,31 @@ int tor_eval_partials(tor_ctx *ctx, int n, const double *O, long ld, int k_max,
 int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count,
                     const unsigned long long *patterns, double *probs, tor_result *results);
 
+/* Click probabilities of every pattern of one Gaussian state at once, with
+ * the work shared across patterns (Sec. 1, Eq. 1-2): every O_S draws its
+ * terms from the same subset determinants of I - O, so one launch of the
+ * recursive kernel over the whole M-mode state forms each of the 2^M terms
+ * once, every prefix factor shared by all patterns, and stores it in device
+ * memory; an exact double-double subset-sum transform over the subset lattice
+ * then gives every Tor(O_S).  That is 2^M determinants and M passes over 2^M
+ * sums, against 3^M determinants for the patterns one by one.  Pattern S is
+ * indexed by its bitmask (bit q = mode q clicked).  probs (2^M doubles, may
+ * be NULL) receives p(S) = Tor(O_S) sqrt(det(I - O)); tor_hi and tor_lo
+ * (2^M doubles each, may be NULL) receive Tor(O_S) as a double-double; out
+ * (may be NULL) the record of the whole state (Tor(O), its sum of |t|, the
+ * device time of both steps).  All are host memory.  O is as for
+ * tor_click_probs.  The terms are those of the FP64 real quadrature path, and
+ * each Tor(O_S) is their exact sum while its partial sums stay below 2^53
+ * (every term is a multiple of 2^-52).  Device workspace: about 24 * 2^N + 24 *
+ * 2^M bytes beyond what tor_eval of the state needs, N = max(M, 11).
+ * Errors: TOR_E_INVAL (M > TOR_CLICK_ALL_MAX_M or > max_n, a null O, no
+ * output, a context with TOR_FORCE_COMPLEX or TOR_FACTOR_DD, or an O without
+ * the block structure of a Gaussian state), TOR_E_NOT_PD, TOR_E_NUMERIC (a
+ * non-finite term; no re-run), TOR_E_NOMEM. */
+#define TOR_CLICK_ALL_MAX_M 30
+int tor_click_all(tor_ctx *ctx, int M, const double *O, long ld, double *probs, double *tor_hi, double *tor_lo,
+                  tor_result *out);
+
 /* Serving: enqueue one Torontonian request.  O is copied before return and
  * staged on the device when the request is admitted; a staging error
  * (TOR_E_INVAL), TOR_E_NOT_PD, or TOR_E_NOMEM when the device pool of the
@@ -268,6 +293,12 @@ int tor_debug_fma_peak(tor_ctx *ctx, int iters, double *tflops, float *ms);
  * ignored.  The request is used up by that one evaluation.  Errors:
  * TOR_E_INVAL (null ctx, runs outside 0..2). */
 int tor_debug_fail_root(tor_ctx *ctx, long long root, int runs);
+
+/* Test aid: the subset-sum transform of tor_click_all on its own.  For the
+ * 2^nbits host doubles t (1 <= nbits <= 26), g_hi and g_lo (host, 2^nbits
+ * each) receive g[S] = sum over Z subset of S of t[Z] as double-doubles.
+ * Errors: TOR_E_INVAL (null pointers, nbits out of range), TOR_E_NOMEM. */
+int tor_debug_zeta(tor_ctx *ctx, int nbits, const double *t, double *g_hi, double *g_lo);
 
 /* Serving policy.  Each chunked serving launch runs at most chunk_subsets
  * subsets (default 2^29, about 2.5 ms at n = 30 rates) taken from the

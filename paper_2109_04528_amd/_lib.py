@@ -42,6 +42,7 @@ EXPORTS = [
     "tor_eval_batch", "tor_eval_plain", "tor_eval_partials", "tor_submit", "tor_poll",
     "tor_drain", "tor_debug_math", "tor_debug_fma_peak", "tor_strerror", "tor_autotune", "tor_tune_save", "tor_tune_load",
     "tor_serve_config", "tor_click_probs", "tor_eval_removal", "tor_eval_static", "tor_debug_fail_root",
+    "tor_click_all", "tor_debug_zeta",
 ]
 
 TOR_TUNE_REAL = 0x1
@@ -156,6 +157,12 @@ def load(path: str = LIB_PATH):
     lib.tor_click_probs.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long, ctypes.c_int,
                                     P(ctypes.c_ulonglong), P(ctypes.c_double), ctypes.c_void_p]
     lib.tor_click_probs.restype = ctypes.c_int
+    DP = P(ctypes.c_double)
+    lib.tor_click_all.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long, DP, DP, DP,
+                                  ctypes.c_void_p]
+    lib.tor_click_all.restype = ctypes.c_int
+    lib.tor_debug_zeta.argtypes = [ctypes.c_void_p, ctypes.c_int, DP, DP, DP]
+    lib.tor_debug_zeta.restype = ctypes.c_int
     lib.tor_eval_removal.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_long, P(tor_result)]
     lib.tor_eval_removal.restype = ctypes.c_int
     lib.tor_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint]
@@ -404,6 +411,44 @@ class Context:
         if check and rc != TOR_OK:
             raise TorError(rc, "tor_click_probs")
         return probs[:cnt], [TorResult.from_c(res[i]) for i in range(cnt)]
+
+    def click_all(self, O, probs: bool = True, tor: bool = False, check: bool = True):
+        """Click probabilities of every pattern of the M-mode state at once
+        (tor_click_all): p[S] for every bitmask S < 2^M, the subset
+        determinants shared by all patterns.  Returns (probs or None,
+        (tor_hi, tor_lo) or None, TorResult of the whole state)."""
+        ptr, M, ld, _keep = self._in(O)
+        n = 1 << M
+        dp = ctypes.POINTER(ctypes.c_double)
+        p = np.empty(n, dtype=np.float64) if probs else None
+        th = np.empty(n, dtype=np.float64) if tor else None
+        tl = np.empty(n, dtype=np.float64) if tor else None
+        r = tor_result()
+        nul = ctypes.cast(None, dp)
+        rc = self._lib.tor_click_all(self._h, M, ptr, ld,
+                                     p.ctypes.data_as(dp) if probs else nul,
+                                     th.ctypes.data_as(dp) if tor else nul,
+                                     tl.ctypes.data_as(dp) if tor else nul,
+                                     ctypes.cast(ctypes.byref(r), ctypes.c_void_p))
+        if check and rc != TOR_OK:
+            raise TorError(rc, "tor_click_all")
+        return p, ((th, tl) if tor else None), TorResult.from_c(r)
+
+    def debug_zeta(self, t):
+        """The subset-sum transform of click_all on 2^nbits host doubles:
+        (g_hi, g_lo) with g[S] = sum over Z subset of S of t[Z]."""
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        nbits = int(t.size).bit_length() - 1
+        if t.size != 1 << nbits:
+            raise ValueError("the number of terms must be a power of two")
+        gh = np.empty_like(t)
+        gl = np.empty_like(t)
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = self._lib.tor_debug_zeta(self._h, nbits, t.ctypes.data_as(dp), gh.ctypes.data_as(dp),
+                                      gl.ctypes.data_as(dp))
+        if rc != TOR_OK:
+            raise TorError(rc, "tor_debug_zeta")
+        return gh, gl
 
     def submit(self, O) -> int:
         ptr, n, ld, _keep = self._in(O)

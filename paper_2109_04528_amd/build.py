@@ -1,8 +1,8 @@
 """Build libtor.so (the HIP kernels and the C ABI) for gfx950, in-tree.
 
-``python -m paper_2109_04528_amd.build`` compiles ``csrc/tor_kernels.hip``,
-``csrc/tor_stage.hip``, ``csrc/tor_probe.hip`` and ``csrc/tor_runtime.cpp``
-with hipcc into ``paper_2109_04528_amd/libtor.so``.
+``python -m paper_2109_04528_amd.build`` compiles the HIP sources in
+``csrc/`` (the recursive, comparison, staging, subset-sum and probe kernels)
+and ``csrc/tor_runtime.cpp`` with hipcc into ``paper_2109_04528_amd/libtor.so``.
 Packed-FP32 instructions are disabled; no fast-math (the double-double
 accumulation relies on IEEE rounding and no reassociation).
 """
@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtor.so")
 ARCH = os.environ.get("TOR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["tor_kernels.hip", "tor_compare.hip", "tor_stage.hip", "tor_probe.hip", "tor_runtime.cpp"]
+SOURCES = ["tor_kernels.hip", "tor_compare.hip", "tor_stage.hip", "tor_zeta.hip", "tor_probe.hip", "tor_runtime.cpp"]
 
 
 def hipcc() -> str:

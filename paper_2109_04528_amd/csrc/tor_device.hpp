@@ -306,6 +306,7 @@ __device__ __forceinline__ Piv<ddr> pivot(ddr a, ddr b, ddr g)
 struct AccDD {
     static constexpr bool kDD = true;  // reduce as double-double
     double hi = 0.0, lo = 0.0, abs_sum = 0.0, frame = 1.0;
+    __device__ __forceinline__ void begin_leaf(double *) {}
     __device__ __forceinline__ void two_sum(double t)
     {
         double s = hi + t;
@@ -314,13 +315,13 @@ struct AccDD {
         hi = s;
         lo += e;
     }
-    template <int SG>
+    template <int SG, int TB = 0>
     __device__ __forceinline__ void add(double r)
     {
         two_sum(SG * r);
         abs_sum += r;
     }
-    template <int SG>
+    template <int SG, int TB = 0>
     __device__ __forceinline__ void add_pair(double r0, double r1)
     {
         const double s = r1 - r0;
@@ -343,13 +344,14 @@ struct AccDD {
 struct AccF64 {
     static constexpr bool kDD = false;
     double hi = 0.0, lo = 0.0, abs_sum = 0.0, frame = 1.0;
-    template <int SG>
+    __device__ __forceinline__ void begin_leaf(double *) {}
+    template <int SG, int TB = 0>
     __device__ __forceinline__ void add(double r)
     {
         hi += SG * r;
         abs_sum += r;
     }
-    template <int SG>
+    template <int SG, int TB = 0>
     __device__ __forceinline__ void add_pair(double r0, double r1)
     {
         hi += -SG * r0;
@@ -363,24 +365,53 @@ struct AccF64 {
     }
 };
 
+// every term stored instead of summed (all click patterns at once): the lane's
+// 2^T terms of one tier-A leaf go to out[TB], TB the subset below the lane's
+// node (bit M-1 of TB = the decision when M modes are left), each with its
+// full sign (-1)^(#excluded); only the sum of |t| is kept
+struct AccStore {
+    static constexpr bool kDD = false;
+    static constexpr double hi = 0.0, lo = 0.0;
+    double abs_sum = 0.0, frame = 1.0;
+    double *out = nullptr;
+    __device__ __forceinline__ void begin_leaf(double *p) { out = p; }
+    template <int SG, int TB = 0>
+    __device__ __forceinline__ void add(double r)
+    {
+        *(__attribute__((address_space(1))) double *)(out + TB) = SG * frame * r;
+        abs_sum += r;
+    }
+    template <int SG, int TB = 0>
+    __device__ __forceinline__ void add_pair(double r0, double r1)
+    {
+        static_assert((TB & 1) == 0, "the last mode's pair is two neighbouring subsets");
+        typedef double v2 __attribute__((ext_vector_type(2)));
+        const v2 v = {-SG * frame * r0, SG * frame * r1};
+        *(__attribute__((address_space(1))) v2 *)(out + TB) = v;
+        abs_sum += r0 + r1;
+    }
+    __device__ __forceinline__ void set_frame(double f) { frame = f; }
+};
+
 // double-double sum of double-double terms (the higher-precision mode); the
 // pair of the last mode is formed as a double-double difference first
 struct AccQ {
     static constexpr bool kDD = true;
     double hi = 0.0, lo = 0.0, abs_sum = 0.0, frame = 1.0;
+    __device__ __forceinline__ void begin_leaf(double *) {}
     __device__ __forceinline__ void acc(double th, double tl)
     {
         const ddr s = dd_add(ddr{hi, lo}, ddr{th, tl});
         hi = s.hi;
         lo = s.lo;
     }
-    template <int SG>
+    template <int SG, int TB = 0>
     __device__ __forceinline__ void add(ddr r)
     {
         acc(SG * r.hi, SG * r.lo);
         abs_sum += r.hi;
     }
-    template <int SG>
+    template <int SG, int TB = 0>
     __device__ __forceinline__ void add_pair(ddr r0, ddr r1)
     {
         const ddr d = dd_add(r1, dd_neg(r0));

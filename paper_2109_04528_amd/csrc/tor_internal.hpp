@@ -63,6 +63,9 @@ struct MainParams {
     long long scratch_stride;     // bytes per wave
     long long fail_item1;         // debug: 1 + the queue item whose root reports a
                                   // numeric failure (0: none)
+    double *terms;                // every-term launch (one matrix, all roots): the
+                                  // signed term of each subset, indexed by subset
+                                  // (bit N-1-l = decision at level l); else null
 };
 // root slot flag (fourth double): a tested pivot failed (I - O is not
 // positive definite), or the root's sum is not finite (a numeric failure,
@@ -174,6 +177,17 @@ constexpr int MAX_FIT = 8;  // persistent one-wave workgroups per CU, at most
 
 // host-side launchers (defined in tor_kernels.hip unless noted)
 hipError_t launch_main(int path, bool dd, const MainParams &p, int grid, hipStream_t s);
+// the real-path kernel that stores every term (p.terms) instead of summing
+hipError_t launch_main_store(const MainParams &p, int grid, hipStream_t s);
+int main_store_occupancy();
+// exact double-double subset sums g[S] = sum over Z subset of S of t[Z], for
+// the 2^nbits terms t (tor_zeta.hip)
+hipError_t launch_zeta(const double *t, ddr *g, int nbits, hipStream_t s);
+// per click pattern S of M modes (bit i = API mode i) of a staged form of N
+// modes: Tor(O_S) = (-1)^(N-|S|) g[S reversed over N bits], and optionally
+// p(S) = Tor(O_S) sqrt(det(I - O)) (tor_zeta.hip)
+hipError_t launch_click_out(const ddr *g, int N, int M, const double *sqrt_det, double *probs, double *tor_hi,
+                            double *tor_lo, hipStream_t s);
 hipError_t launch_reduce(const ProblemDesc *probs, int nprob, double *results, bool dd, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, int count, hipStream_t s);
 hipError_t launch_plain(const PlainParams &p, bool real, int grid, hipStream_t s);

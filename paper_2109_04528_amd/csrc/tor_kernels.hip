@@ -598,20 +598,20 @@ __device__ __forceinline__ void elim_regs(const S *h, const Piv<S> &pq, S *hn)
 // all 2^M subsets below a register-resident node of M modes.  SG is the sign
 // (-1)^(#excluded) of its subsets relative to the lane's frame (see the
 // accumulators); det is the running determinant.
-template <class S, int M, int SG, class Acc>
+template <class S, int M, int SG, class Acc, int TB = 0>
 __device__ __forceinline__ void tail(const S *h, RT<S> det, Acc &acc, int &bad)
 {
     if constexpr (M == 0) {
-        acc.template add<SG>(rsqrt_nr(det));
+        acc.template add<SG, TB>(rsqrt_nr(det));
     } else if constexpr (M == 1) {
         // exclude (sign -SG) and include (sign SG) of the last mode
         const RT<S> a = re(h[0]);
         const S b = h[1];
         const RT<S> g = re(h[2]);
         const RT<S> pd = det_last(a, b, g);  // det of the last 2x2 block
-        acc.template add_pair<SG>(rsqrt_nr(det), rsqrt_nr(rmul(det, pd)));
+        acc.template add_pair<SG, TB>(rsqrt_nr(det), rsqrt_nr(rmul(det, pd)));
     } else {
-        tail<S, M - 1, -SG, Acc>(h, det, acc, bad);  // exclude the next mode
+        tail<S, M - 1, -SG, Acc, TB>(h, det, acc, bad);  // exclude the next mode
         constexpr int p = 2 * M - 2;
         const RT<S> a = re(h[pidx(p, p)]);
         const S b = h[pidx(p + 1, p)];
@@ -619,7 +619,7 @@ __device__ __forceinline__ void tail(const S *h, RT<S> det, Acc &acc, int &bad)
         const Piv<S> pq = pivot(a, b, g);
         S hn[E(M - 1)];
         elim_regs<S, M>(h, pq, hn);
-        tail<S, M - 1, SG, Acc>(hn, rmul(det, pq.pdet), acc, bad);
+        tail<S, M - 1, SG, Acc, TB | (1 << (M - 1))>(hn, rmul(det, pq.pdet), acc, bad);
     }
 }
 
@@ -910,6 +910,15 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                     sdet[lvl + 1] = ldet;
             }
             __syncthreads();
+            if constexpr (std::is_same<Acc, AccStore>::value) {
+                // subset index of the lane's first term: bit N-1-l is the
+                // decision at level l, so the root's k bits reversed on top,
+                // then the leaf index x (tier A, level LA-1 lowest), then the
+                // lane (tier B's view bits and tier C's two lane levels), then
+                // the T bits of the tail
+                const unsigned long long rrev = k ? __builtin_bitreverse64((unsigned long long)root) >> (64 - k) : 0ull;
+                acc.begin_leaf(prm.terms + ((rrev << (N - k)) | ((unsigned long long)x << R) | ((unsigned long long)lane << T)));
+            }
             tierB<S, R, 1, BL + 1>(tb, ldet, lane, bad);
             tierC<S, T, B, L, Acc>(tb, ldet, linc, N, lane, acc, bad, root == (1ll << k) - 1 && x == nleaf - 1);
             __syncthreads();
@@ -1012,6 +1021,20 @@ __global__ void tor_zero(unsigned long long *p, int count)
 }
 
 // ---------------------------------------------------------------------------
+hipError_t launch_main_store(const MainParams &p, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((tor_main<double, REAL_T, REAL_B, REAL_L, AccStore>), dim3(grid), dim3(64), 0, s, p);
+    return hipGetLastError();
+}
+
+int main_store_occupancy()
+{
+    int n = 0;
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tor_main<double, REAL_T, REAL_B, REAL_L, AccStore>, 64, 0);
+    return e == hipSuccess ? n : 0;
+}
+
 hipError_t launch_main(int path, bool dd, const MainParams &p, int grid, hipStream_t s)
 {
     if (path == PATH_QUAD) {

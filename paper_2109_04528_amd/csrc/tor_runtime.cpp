@@ -511,7 +511,8 @@ LaunchLayout launch_layout(int count, int nred, long long stride)
 // hold data the descriptors point to, and the caller has already sized the
 // workspace (a reallocation here would move that data).
 int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const std::vector<int> &reduce,
-               size_t ws_off, int grid, std::vector<double> *results, float *ms, long long fail_item1 = 0)
+               size_t ws_off, int grid, std::vector<double> *results, float *ms, long long fail_item1 = 0,
+               double *terms = nullptr)
 {
     const int count = (int)descs.size();
     long long total = 0, stack = 0;
@@ -562,6 +563,7 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     mp.scratch = dScr;
     mp.scratch_stride = stride;
     mp.fail_item1 = fail_item1;
+    mp.terms = terms;
     // the double-double factor always sums in double-double
     const bool dd = ctx->opt.accum != TOR_ACCUM_FP64 || path == PATH_QUAD;
     if (e == hipSuccess)
@@ -569,7 +571,8 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     // no more persistent waves than queue items: a launch of few roots (a
     // small matrix) does not pay for starting the whole grid
     if (e == hipSuccess && total > 0)
-        e = launch_main(path, dd, mp, (int)std::min<long long>(grid, total), ctx->stream);
+        e = terms ? launch_main_store(mp, (int)std::min<long long>(grid, total), ctx->stream)
+                  : launch_main(path, dd, mp, (int)std::min<long long>(grid, total), ctx->stream);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev1, ctx->stream);  // device_ms: the main kernel alone
     const double *hres = (const double *)ctx->hdown;
@@ -1671,6 +1674,180 @@ int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count, co
             results[i] = res[i];
     }
     return first_err;
+}
+
+int tor_click_all(tor_ctx *ctx, int M, const double *O, long ld, double *probs, double *tor_hi, double *tor_lo,
+                  tor_result *out)
+{
+    if (!ctx || M < 0 || M > TOR_CLICK_ALL_MAX_M || M > ctx->opt.max_n || (M > 0 && (!O || ld < 2L * M)) ||
+        (!probs && !tor_hi && !tor_lo && !out))
+        return TOR_E_INVAL;
+    // the terms are stored by the FP64 kernel of the real quadrature form
+    if (ctx->opt.flags & (TOR_FORCE_COMPLEX | TOR_FACTOR_DD))
+        return TOR_E_INVAL;
+    if (M == 0) {  // the empty pattern of a 0-mode state: Tor = 1, p = 1
+        if (probs)
+            probs[0] = 1.0;
+        if (tor_hi)
+            tor_hi[0] = 1.0;
+        if (tor_lo)
+            tor_lo[0] = 0.0;
+        if (out) {
+            std::memset(out, 0, sizeof(*out));
+            out->tor = 1.0;
+            out->sum_abs = 1.0;
+            out->subsets = 1;
+            out->path = api_path(PATH_REAL);
+        }
+        return TOR_OK;
+    }
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const int m2 = 2 * M;
+    const bool dev = (ctx->opt.flags & TOR_INPUT_DEVICE) != 0;
+    const size_t bO = dev ? 0 : align_up(sizeof(c64) * (size_t)m2 * m2, 256);
+    const size_t bScr = align_up(sizeof(c64) * (size_t)m2 * m2, 256);
+    const size_t base = bO + bScr + 256;
+    std::vector<StageIn> in(1);
+    in[0].n = M;
+    in[0].M = M;
+    const unsigned sfl = stage_flags(ctx->opt.flags);
+    int rc = ensure_ws_keep(ctx, base + stage_layout(in, true, sfl, CPLX_R).total, 0);
+    if (rc != TOR_OK)
+        return rc;
+    hipError_t e = hipSetDevice(ctx->device);
+    const double *dO = O;
+    long dld = ld;
+    if (e == hipSuccess && !dev) {
+        e = hipMemcpy2DAsync(ctx->ws, sizeof(c64) * m2, O, sizeof(c64) * (size_t)ld, sizeof(c64) * m2, m2,
+                             hipMemcpyHostToDevice, ctx->stream);
+        dO = (const double *)ctx->ws;
+        dld = m2;
+    }
+    double *dDet = (double *)(ctx->ws + bO + bScr);
+    if (e == hipSuccess)
+        e = launch_sqrt_det(dO, dld, M, (c64 *)(ctx->ws + bO), dDet, ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    in[0].O = dO;
+    in[0].ld = dld;
+    std::vector<Mat> mats;
+    size_t end = 0, down = 0;
+    rc = stage_enqueue(ctx, in, true, sfl, CPLX_R, base, mats, &end, &down);
+    if (rc != TOR_OK)
+        return rc;
+    const size_t det_at = align_up(down, 16);
+    if (det_at + 2 * sizeof(double) > ctx->hdown_bytes)
+        return TOR_E_NOMEM;
+    double *hDet = (double *)(ctx->hdown + det_at);
+    e = hipMemcpyAsync(hDet, dDet, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    stage_collect(ctx, mats);
+    if (hDet[1] != 0.0 || !(hDet[0] > 0.0))
+        return TOR_E_NOT_PD;
+    if (mats[0].status != TOR_OK)
+        return mats[0].status;
+    if (mats[0].path != PATH_REAL)
+        return TOR_E_INVAL;  // O lacks the Gaussian-state block structure
+    const int N = mats[0].N;
+    const int k = choose_k(ctx, N, PATH_REAL);
+    // after the staged matrix: root slots, the 2^N terms, their subset sums,
+    // the device outputs, then what run_launch needs
+    const long long nS = 1ll << N, nP = 1ll << M;
+    const size_t oSlots = align_up(end, 256);
+    const size_t oTerms = align_up(oSlots + sizeof(double) * 4 * ((size_t)1 << k), 256);
+    const size_t oG = align_up(oTerms + sizeof(double) * (size_t)nS, 256);
+    const size_t oOut = align_up(oG + sizeof(ddr) * (size_t)nS, 256);
+    const size_t off = align_up(oOut + 3 * sizeof(double) * (size_t)nP, 256);
+    const long long stack = wave_stack_bytes(PATH_REAL, N, k);
+    const int fit = std::max(1, std::min(main_store_occupancy(), ctx->fit[PATH_REAL]));
+    const int grid = ctx->num_cu * fit;
+    rc = ensure_ws_keep(ctx, off + launch_layout(1, 1, stack).total(grid), end);
+    if (rc != TOR_OK)
+        return rc;
+    double *dTerms = (double *)(ctx->ws + oTerms);
+    ddr *dG = (ddr *)(ctx->ws + oG);
+    double *dP = (double *)(ctx->ws + oOut), *dH = dP + nP, *dL = dH + nP;
+    dDet = (double *)(ctx->ws + bO + bScr);  // the workspace may have moved
+    std::vector<ProblemDesc> descs(1);
+    ProblemDesc &d = descs[0];
+    d.C = mat_ptr(ctx, mats[0]);
+    d.slots = (double *)(ctx->ws + oSlots);
+    d.N = N;
+    d.k = k;
+    d.root_begin = 0;
+    d.nroots = 1ll << k;
+    std::vector<double> res;
+    float ms_main = 0.f, ms_zeta = 0.f;
+    rc = run_launch(ctx, PATH_REAL, descs, std::vector<int>{0}, off, grid, &res, &ms_main, 0, dTerms);
+    if (rc != TOR_OK)
+        return rc;
+    if (res[3] >= SLOT_NOT_PD)
+        return TOR_E_NOT_PD;
+    if (res[3] > 0.0)
+        return TOR_E_NUMERIC;
+    e = hipEventRecord(ctx->ev0, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_zeta(dTerms, dG, N, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_click_out(dG, N, M, dDet, probs ? dP : nullptr, tor_hi || out ? dH : nullptr,
+                             tor_lo || out ? dL : nullptr, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev1, ctx->stream);
+    if (e == hipSuccess && probs)
+        e = hipMemcpyAsync(probs, dP, sizeof(double) * nP, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess && tor_hi)
+        e = hipMemcpyAsync(tor_hi, dH, sizeof(double) * nP, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess && tor_lo)
+        e = hipMemcpyAsync(tor_lo, dL, sizeof(double) * nP, hipMemcpyDeviceToHost, ctx->stream);
+    double full[2] = {0.0, 0.0};
+    if (e == hipSuccess && out)
+        e = hipMemcpyAsync(&full[0], dH + (nP - 1), sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess && out)
+        e = hipMemcpyAsync(&full[1], dL + (nP - 1), sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    (void)hipEventElapsedTime(&ms_zeta, ctx->ev0, ctx->ev1);
+    if (out) {
+        // the result of the whole state (every mode clicks), with the sum of
+        // |t| over all subsets and the device time of both steps
+        const double r[4] = {full[0], full[1], res[2], 0.0};
+        fill_result(mats[0], PATH_REAL, r, ms_main + ms_zeta, out);
+    }
+    return TOR_OK;
+}
+
+int tor_debug_zeta(tor_ctx *ctx, int nbits, const double *t, double *g_hi, double *g_lo)
+{
+    if (!ctx || nbits < 1 || nbits > 26 || !t || !g_hi || !g_lo)
+        return TOR_E_INVAL;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const size_t n = (size_t)1 << nbits;
+    const size_t oG = align_up(sizeof(double) * n, 256);
+    int rc = ensure_ws(ctx, oG + sizeof(ddr) * n);
+    if (rc != TOR_OK)
+        return rc;
+    std::vector<ddr> h(n);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->ws, t, sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_zeta((const double *)ctx->ws, (ddr *)(ctx->ws + oG), nbits, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), ctx->ws + oG, sizeof(ddr) * n, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return hip_status(e);
+    for (size_t i = 0; i < n; i++) {
+        g_hi[i] = h[i].hi;
+        g_lo[i] = h[i].lo;
+    }
+    return TOR_OK;
 }
 
 int tor_eval_plain(tor_ctx *ctx, int n, const double *O, long ld, unsigned long long mask_begin,

@@ -1,0 +1,160 @@
+// tor_zeta.hip -- click probabilities of every pattern of one state at once.
+//
+// The probability that threshold detectors click exactly on the modes S of a
+// Gaussian state is p(S) = Tor(O_S) sqrt(det(I - O)) (Sec. 1), and Tor(O_S)
+// is Eq. 2 for the principal submatrix O_S: a signed sum of
+// 1/sqrt(det (I - O)_Z) over the subsets Z of S.  Every pattern therefore
+// draws its terms from the same 2^M subset determinants of I - O.  One launch
+// of the recursive kernel over the whole state stores each signed term
+//     t[Z] = (-1)^(N-|Z|) / sqrt(det (I - O)_Z)
+// (N the modes of the staged form, index bit N-1-l = the decision at level l,
+// which is mode l), so every prefix factor of the state is formed once for all
+// patterns.  The subset sums
+//     g[S] = sum over Z subset of S of t[Z]
+// (the zeta transform over the subset lattice) then give every pattern at
+// once: Tor(O_S) = (-1)^(N-|S|) g[S].  That is 2^M determinants and M passes
+// of additions over 2^M entries, against 3^M determinants for the patterns
+// one by one.
+//
+// The transform adds along one index bit at a time (g[S] += g[S without bit b]
+// for every S with bit b set).  The low ZB bits run in LDS, one block of 2^ZB
+// entries per workgroup; the higher bits in global passes of 4 bits, each
+// thread holding the 16 entries that differ only in those bits.
+//
+// Exactness: every term is a double of magnitude at least 1 (det <= 1), so a
+// multiple of 2^-52, and the additions are double-double sums built from
+// Knuth's TwoSum alone.  While a partial sum stays below 2^53 in magnitude,
+// every intermediate quantity is a multiple of 2^-52 that fits its double, so
+// every g[S] is the exact sum of its terms, whatever the order.
+#include "tor_internal.hpp"
+
+namespace tor {
+
+namespace {
+
+constexpr int ZB = 10;  // index bits transformed in LDS (blocks of 1024 entries)
+constexpr int ZT = 256; // threads per LDS block
+constexpr int ZG = 4;   // index bits per global pass
+
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// a + b in double-double from error-free sums only (see the file comment)
+__device__ __forceinline__ void dd_acc(double &ah, double &al, double bh, double bl)
+{
+    double s, e, t, f;
+    two_sum(ah, bh, s, e);
+    two_sum(al, bl, t, f);
+    e += t;
+    two_sum(s, e, s, e);
+    e += f;
+    two_sum(s, e, ah, al);
+}
+
+// bits 0 .. nb-1 of a block of 2^nb entries (nb <= ZB), terms in, double-double out
+__global__ void __launch_bounds__(ZT) tor_zeta_lds(const double *t, ddr *g, int nb)
+{
+    __shared__ double hs[1 << ZB], ls[1 << ZB];
+    const int size = 1 << nb;
+    const long long base = (long long)blockIdx.x << nb;
+    for (int i = threadIdx.x; i < size; i += ZT) {
+        hs[i] = t[base + i];
+        ls[i] = 0.0;
+    }
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+        const int low = (1 << b) - 1;
+        for (int p = threadIdx.x; p < size / 2; p += ZT) {
+            const int i1 = ((p & ~low) << 1) | (1 << b) | (p & low);  // the p-th index with bit b set
+            const int i0 = i1 ^ (1 << b);
+            double h = hs[i1], l = ls[i1];
+            dd_acc(h, l, hs[i0], ls[i0]);
+            hs[i1] = h;
+            ls[i1] = l;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < size; i += ZT)
+        g[base + i] = ddr{hs[i], ls[i]};
+}
+
+// bits b0 .. b0+nb-1 (nb <= ZG) over all 2^nbits entries: thread q holds the
+// 2^nb entries whose index has q's bits below b0 and above b0+nb-1
+__global__ void __launch_bounds__(256) tor_zeta_bits(ddr *g, int nbits, int b0, int nb)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (1ll << (nbits - nb)))
+        return;
+    const long long lowm = (1ll << b0) - 1;
+    const long long base = (q & lowm) | ((q & ~lowm) << nb);
+    double h[1 << ZG], l[1 << ZG];
+#pragma unroll
+    for (int j = 0; j < (1 << ZG); ++j)
+        if (j < (1 << nb)) {
+            const ddr v = g[base + ((long long)j << b0)];
+            h[j] = v.hi;
+            l[j] = v.lo;
+        }
+#pragma unroll
+    for (int b = 0; b < ZG; ++b)
+        if (b < nb) {
+#pragma unroll
+            for (int j = 0; j < (1 << ZG); ++j)
+                if (j < (1 << nb) && ((j >> b) & 1))
+                    dd_acc(h[j], l[j], h[j ^ (1 << b)], l[j ^ (1 << b)]);
+        }
+#pragma unroll
+    for (int j = 0; j < (1 << ZG); ++j)
+        if (j < (1 << nb))
+            g[base + ((long long)j << b0)] = ddr{h[j], l[j]};
+}
+
+// one thread per pattern S < 2^M: S's bit i (mode i, decided at level i) is
+// index bit N-1-i
+__global__ void __launch_bounds__(256) tor_click_out(const ddr *g, int N, int M, const double *sqrt_det,
+                                                      double *probs, double *tor_hi, double *tor_lo)
+{
+    const long long S = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (S >= (1ll << M))
+        return;
+    const unsigned long long idx = __builtin_bitreverse64((unsigned long long)S) >> (64 - N);
+    const ddr v = g[idx];
+    const double sg = ((N - __popcll((unsigned long long)S)) & 1) ? -1.0 : 1.0;
+    if (tor_hi)
+        tor_hi[S] = sg * v.hi;
+    if (tor_lo)
+        tor_lo[S] = sg * v.lo;
+    if (probs)
+        probs[S] = sg * (v.hi + v.lo) * sqrt_det[0];
+}
+
+}  // namespace
+
+hipError_t launch_zeta(const double *t, ddr *g, int nbits, hipStream_t s)
+{
+    const int nb = nbits < ZB ? nbits : ZB;
+    hipLaunchKernelGGL(tor_zeta_lds, dim3((unsigned)(1ll << (nbits - nb))), dim3(ZT), 0, s, t, g, nb);
+    hipError_t e = hipGetLastError();
+    for (int b0 = nb; e == hipSuccess && b0 < nbits; b0 += ZG) {
+        const int w = nbits - b0 < ZG ? nbits - b0 : ZG;
+        const long long threads = 1ll << (nbits - w);
+        hipLaunchKernelGGL(tor_zeta_bits, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, g, nbits, b0, w);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t launch_click_out(const ddr *g, int N, int M, const double *sqrt_det, double *probs, double *tor_hi,
+                            double *tor_lo, hipStream_t s)
+{
+    const long long n = 1ll << M;
+    hipLaunchKernelGGL(tor_click_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, N, M, sqrt_det, probs,
+                       tor_hi, tor_lo);
+    return hipGetLastError();
+}
+
+}  // namespace tor

@@ -1,0 +1,198 @@
+"""Click probabilities of every pattern at once (tor_click_all), GPU.
+
+One launch of the recursive kernel stores the signed term of every subset of
+the state's modes; an exact double-double subset-sum transform then gives
+Tor(O_S) for every pattern S.  Pins:
+  * the transform alone against exact integer arithmetic (every term a
+    multiple of 2^-52, so the sums are exact);
+  * the whole state's Tor bit for bit against tor_eval: each term is the same
+    sequence of pivots in both (the same arithmetic whichever tier takes a
+    level), and both sums are exact;
+  * every pattern against tor_click_probs, which stages each O_S on its own
+    (its terms differ in the last mode's 2x2 determinant, which the last level
+    of a tree forms directly; so at the statistical bound);
+  * a product state's closed form p(S) = prod_{i in S} (1 - 1/a_i)
+    prod_{i not in S} 1/a_i, a_i = 1/sqrt(det (I - O)_i), in 50-digit
+    arithmetic from the input's own entries;
+  * the __float128 oracle per pattern, and the normalisation sum_S p(S) = 1.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import bounds
+from oracle import oracle as orc
+from paper_2109_04528_amd import inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2109_04528_amd import Context
+    c = Context(device=0)
+    yield c
+    c.close()
+
+
+def state(M, seed):
+    return gen.random_O(M, seed, 0.5, 1.0, 0.7)
+
+
+def sqrt_det(O):
+    return math.sqrt(np.linalg.det(np.eye(O.shape[0]) - O).real)
+
+
+def exact_zeta(t):
+    """Subset sums in integers of 2^-52 (object arrays of Python ints)."""
+    a = np.array([int(x * 2.0 ** 52) for x in t], dtype=object)
+    nb = a.size.bit_length() - 1
+    for b in range(nb):
+        v = a.reshape(-1, 2, 1 << b)
+        v[:, 1, :] += v[:, 0, :]
+    return a
+
+
+@pytest.mark.parametrize("nbits", [1, 4, 10, 11, 13, 16])
+def test_subset_sum_transform_is_exact(ctx, nbits):
+    rng = np.random.default_rng(nbits)
+    n = 1 << nbits
+    # doubles of magnitude 1 .. 2^20 with full significands, both signs
+    t = rng.choice([-1.0, 1.0], n) * np.ldexp(1.0 + rng.random(n), rng.integers(0, 20, n))
+    say(f"case zeta nbits={nbits}")
+    gh, gl = ctx.debug_zeta(t)
+    want = exact_zeta(t)
+    got = np.array([int(h * 2.0 ** 52) + int(l * 2.0 ** 52) for h, l in zip(gh, gl)], dtype=object)
+    assert np.all(got == want)
+    assert np.all(np.abs(gl) <= np.spacing(np.abs(gh)) / 2)
+
+
+@pytest.mark.parametrize("M", [8, 12, 20])
+def test_whole_state_equals_eval_bitwise(ctx, M):
+    O = state(M, 40 + M)
+    say(f"case click_all whole state M={M}")
+    probs, (th, tl), r = ctx.click_all(O, tor=True)
+    e = ctx.eval(O)
+    full = (1 << M) - 1
+    say(f"  click_all={r.tor!r},{r.tor_lo!r} eval={e.tor!r},{e.tor_lo!r} ms={r.device_ms:.2f}")
+    assert r.status == 0 and r.path == 1
+    assert (r.tor, r.tor_lo) == (e.tor, e.tor_lo)
+    assert (th[full], tl[full]) == (e.tor, e.tor_lo)
+    assert r.sum_abs == e.sum_abs
+
+
+def test_every_pattern_against_click_probs(ctx):
+    M = 12
+    O = state(M, 52)
+    say("case click_all vs click_probs M=12 (4096 patterns)")
+    probs, (th, tl), _ = ctx.click_all(O, tor=True)
+    p2, res = ctx.click_probs(O, range(1 << M))
+    assert all(r.status == 0 for r in res)
+    same, worst = 0, 0.0
+    for S, r in enumerate(res):
+        d = abs((th[S] - r.tor) + (tl[S] - r.tor_lo))
+        same += d == 0.0
+        modes = [i for i in range(M) if (S >> i) & 1]
+        q = orc.tor(gen.click_submatrix(O, modes), mode=orc.F64)
+        tol = bounds.sum_bound(q.sum_sq, bounds.U64, bounds.U64)
+        worst = max(worst, d / tol)
+        assert d <= tol
+    say(f"  patterns bit-identical: {same} of {1 << M}; worst difference / bound = {worst:.3f}")
+    # the patterns without the last mode share every term with the whole state
+    assert same >= 1 << (M - 1)
+
+
+def test_product_state_closed_form(ctx):
+    """p(S) = prod_{i in S} (a_i - 1) / prod_i a_i; the terms t_Z = prod_{i in Z}
+    a_i of pattern S have sum t^2 = prod_{i in S} (1 + a_i^2), which sets the
+    FP64 floor of each Tor(O_S)."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    M = 10
+    rng = np.random.default_rng(8)
+    O = gen.product_state_O(rng.uniform(0.3, 1.2, M), 0.8, rng.uniform(0, 2 * np.pi, M))
+    say("case click_all product state M=10")
+    probs, (th, tl), _ = ctx.click_all(O, tor=True)
+    a = []
+    for i in range(M):
+        c11 = 1 - mp.mpf(float(O[i, i].real))
+        c22 = 1 - mp.mpf(float(O[i + M, i + M].real))
+        c21 = mp.mpc(-float(O[i + M, i].real), -float(O[i + M, i].imag))
+        a.append(1 / mp.sqrt(c11 * c22 - abs(c21) ** 2))
+    vac = mp.mpf(1)
+    for ai in a:
+        vac /= ai  # p(no click) = sqrt(det(I - O))
+    worst, rels = 0.0, []
+    for S in range(1 << M):
+        tor, ssq = mp.mpf(1), mp.mpf(1)
+        for i in range(M):
+            if (S >> i) & 1:
+                tor *= a[i] - 1
+                ssq *= 1 + a[i] ** 2
+        tol = bounds.sum_bound(float(ssq), bounds.U64, 0.0)
+        d = float(abs((mp.mpf(th[S]) + mp.mpf(tl[S])) - tor))
+        worst = max(worst, d / tol)
+        rels.append(d / float(abs(tor)))
+        assert d <= tol
+        assert abs(probs[S] - float(tor * vac)) <= tol * float(vac) + 4e-16 * float(abs(tor * vac))
+    say(f"  worst difference / bound = {worst:.3f}; median relative error {np.median(rels):.2e}")
+    assert np.median(rels) <= 1e-12
+
+
+def test_patterns_against_oracle(ctx):
+    M = 8
+    O = state(M, 53)
+    say("case click_all vs __float128 oracle M=8 (256 patterns)")
+    probs, (th, tl), _ = ctx.click_all(O, tor=True)
+    sq = sqrt_det(O)
+    worst = 0.0
+    for S in range(1 << M):
+        modes = [i for i in range(M) if (S >> i) & 1]
+        q = orc.tor(gen.click_submatrix(O, modes), mode=orc.QUAD)
+        tol = bounds.sum_bound(q.sum_sq, bounds.U64, bounds.UQ)
+        d = abs((th[S] - q.hi) + (tl[S] - q.lo))
+        worst = max(worst, d / tol)
+        assert d <= tol
+        assert abs(probs[S] - q.value * sq) <= tol * sq + 4e-16 * abs(q.value * sq)
+    say(f"  worst difference / bound = {worst:.3f}")
+
+
+def test_probabilities_sum_to_one(ctx):
+    M = 16
+    O = state(M, 54)
+    say("case click_all sum rule M=16")
+    probs, _, r = ctx.click_all(O)
+    s = math.fsum(probs)
+    say(f"  sum={s!r} min={probs.min():.3e} ms={r.device_ms:.2f}")
+    assert abs(s - 1.0) <= 1e-12
+    assert probs.min() >= -1e-12
+
+
+def test_click_all_errors(ctx):
+    from paper_2109_04528_amd import (TOR_E_INVAL, TOR_E_NOT_PD, TOR_FACTOR_DD, TOR_FORCE_COMPLEX, Context,
+                                      TorError)
+    bad = np.eye(12, dtype=np.complex128) * 1.5
+    with pytest.raises(TorError) as ei:
+        ctx.click_all(bad)
+    assert ei.value.code == TOR_E_NOT_PD
+    rng = np.random.default_rng(3)
+    A = rng.normal(size=(16, 16)) + 1j * rng.normal(size=(16, 16))
+    H = A @ A.conj().T
+    herm = 0.5 * H / np.linalg.eigvalsh(H).max()  # Hermitian, no Gaussian-state structure
+    with pytest.raises(TorError) as ei:
+        ctx.click_all(herm)
+    assert ei.value.code == TOR_E_INVAL
+    for flags in (TOR_FORCE_COMPLEX, TOR_FACTOR_DD):
+        with Context(device=0, flags=flags) as c:
+            with pytest.raises(TorError) as ei:
+                c.click_all(state(6, 1))
+            assert ei.value.code == TOR_E_INVAL
+    probs, (th, tl), r = ctx.click_all(np.zeros((0, 0), dtype=np.complex128), tor=True)
+    assert probs.tolist() == [1.0] and th.tolist() == [1.0] and r.tor == 1.0

@@ -73,7 +73,9 @@ def test_n40_fp64_subtrees_against_oracle():
     assert k == 20 and res.status == 0
     hi, lo = dd_sum(parts)
     assert abs((hi + lo) - res.value) <= 1e-12 * res.sum_abs
-    for root in [0x55555, 0xFFFFF]:
+    # roots whose first included mode leaves a node of more than 34 modes run
+    # their root path in global memory, the others in LDS: both are sampled
+    for root in [0x55555, 0xFFFFF, 0x55540, 0x80000]:
         q = orc.tor(O, mode=orc.F64, fix_mask=(1 << k) - 1, fix_val=root)
         got = parts[root, 0] + parts[root, 1]
         b = bounds.sum_bound(q.sum_sq, bounds.U64, bounds.U64)
@@ -92,7 +94,7 @@ def test_n41_staged_from_global_memory():
     assert k == 21 and res.status == 0 and res.path == 1
     hi, lo = dd_sum(parts)
     assert abs((hi + lo) - res.value) <= 1e-12 * res.sum_abs
-    for root in [0x0F0F0F, 0x1FFFFF]:
+    for root in [0x0F0F0F, 0x1FFFFF, 0x0F0F00]:
         q = orc.tor(O, mode=orc.F64, fix_mask=(1 << k) - 1, fix_val=root)
         got = parts[root, 0] + parts[root, 1]
         b = bounds.sum_bound(q.sum_sq, bounds.U64, bounds.U64)
