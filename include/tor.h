@@ -89,6 +89,9 @@ extern "C" {
  * The input itself is FP64; I - O and the real form are formed from it in
  * double-double (exactly, or rounded to 2^-106).  About 9x the FP64 time. */
 #define TOR_FACTOR_DD 0x8u
+/* tor_click_all writes probs, tor_hi and tor_lo to device memory: the
+ * caller's device pointers, on the context's device, ordered on its stream */
+#define TOR_OUTPUT_DEVICE 0x10u
 
 typedef struct tor_ctx tor_ctx;
 
@@ -240,13 +243,14 @@ int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count,
  * be NULL) receives p(S) = Tor(O_S) sqrt(det(I - O)); tor_hi and tor_lo
  * (2^M doubles each, may be NULL) receive Tor(O_S) as a double-double; out
  * (may be NULL) the record of the whole state (Tor(O), its sum of |t|, the
- * device time of both steps).  All are host memory.  O is as for
- * tor_click_probs.  The terms are those of the FP64 real quadrature path, and
+ * device time of both steps).  tor_hi and tor_lo are both given or both NULL.
+ * The outputs are host memory, or device memory with TOR_OUTPUT_DEVICE (out
+ * stays a host record).  O is as for tor_click_probs.  The terms are those of the FP64 real quadrature path, and
  * each Tor(O_S) is their exact sum while its partial sums stay below 2^53
  * (every term is a multiple of 2^-52).  Device workspace: about 24 * 2^N + 24 *
  * 2^M bytes beyond what tor_eval of the state needs, N = max(M, 11).
  * Errors: TOR_E_INVAL (M > TOR_CLICK_ALL_MAX_M or > max_n, a null O, no
- * output, a context with TOR_FORCE_COMPLEX or TOR_FACTOR_DD, or an O without
+ * output, only one of tor_hi and tor_lo, a context with TOR_FORCE_COMPLEX or TOR_FACTOR_DD, or an O without
  * the block structure of a Gaussian state), TOR_E_NOT_PD, TOR_E_NUMERIC (a
  * non-finite term; no re-run), TOR_E_NOMEM. */
 #define TOR_CLICK_ALL_MAX_M 30

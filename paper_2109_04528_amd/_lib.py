@@ -35,6 +35,7 @@ TOR_INPUT_DEVICE = 0x1
 TOR_CHECK_HERMITIAN = 0x2
 TOR_FORCE_COMPLEX = 0x4
 TOR_FACTOR_DD = 0x8
+TOR_OUTPUT_DEVICE = 0x10
 
 # every symbol include/tor.h declares
 EXPORTS = [
@@ -284,6 +285,8 @@ class Context:
         self._h = h
         self._lib = lib
         self._device_in = bool(flags & TOR_INPUT_DEVICE)
+        self._flags = flags
+        self._device = device
 
     def _after_torch_writes(self, O):
         """Order the library's reads of a device tensor after the work torch
@@ -420,15 +423,31 @@ class Context:
         ptr, M, ld, _keep = self._in(O)
         n = 1 << M
         dp = ctypes.POINTER(ctypes.c_double)
-        p = np.empty(n, dtype=np.float64) if probs else None
-        th = np.empty(n, dtype=np.float64) if tor else None
-        tl = np.empty(n, dtype=np.float64) if tor else None
+        if self._flags & TOR_OUTPUT_DEVICE:
+            # torch tensors on the context's device, written on its stream
+            import torch
+            dev = torch.device("cuda", self._device)
+            mk = lambda: torch.empty(n, dtype=torch.float64, device=dev)
+            at = lambda a: ctypes.cast(ctypes.c_void_p(a.data_ptr()), dp)
+            # the new tensors' memory may still be read by work torch has
+            # queued: order the library's writes after it
+            cur = torch.cuda.current_stream(dev)
+            if self._torch_stream is None:
+                cur.synchronize()
+            elif self._torch_stream != cur:
+                self._torch_stream.wait_stream(cur)
+        else:
+            mk = lambda: np.empty(n, dtype=np.float64)
+            at = lambda a: a.ctypes.data_as(dp)
+        p = mk() if probs else None
+        th = mk() if tor else None
+        tl = mk() if tor else None
         r = tor_result()
         nul = ctypes.cast(None, dp)
         rc = self._lib.tor_click_all(self._h, M, ptr, ld,
-                                     p.ctypes.data_as(dp) if probs else nul,
-                                     th.ctypes.data_as(dp) if tor else nul,
-                                     tl.ctypes.data_as(dp) if tor else nul,
+                                     at(p) if probs else nul,
+                                     at(th) if tor else nul,
+                                     at(tl) if tor else nul,
                                      ctypes.cast(ctypes.byref(r), ctypes.c_void_p))
         if check and rc != TOR_OK:
             raise TorError(rc, "tor_click_all")

@@ -1680,18 +1680,35 @@ int tor_click_all(tor_ctx *ctx, int M, const double *O, long ld, double *probs, 
                   tor_result *out)
 {
     if (!ctx || M < 0 || M > TOR_CLICK_ALL_MAX_M || M > ctx->opt.max_n || (M > 0 && (!O || ld < 2L * M)) ||
-        (!probs && !tor_hi && !tor_lo && !out))
+        (!probs && !tor_hi && !out) || (!tor_hi != !tor_lo))
         return TOR_E_INVAL;
+    const bool dev_out = (ctx->opt.flags & TOR_OUTPUT_DEVICE) != 0;
     // the terms are stored by the FP64 kernel of the real quadrature form
     if (ctx->opt.flags & (TOR_FORCE_COMPLEX | TOR_FACTOR_DD))
         return TOR_E_INVAL;
     if (M == 0) {  // the empty pattern of a 0-mode state: Tor = 1, p = 1
-        if (probs)
-            probs[0] = 1.0;
-        if (tor_hi)
-            tor_hi[0] = 1.0;
-        if (tor_lo)
-            tor_lo[0] = 0.0;
+        const double one[2] = {1.0, 0.0};
+        if (dev_out && (probs || tor_hi)) {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            hipError_t e = hipSetDevice(ctx->device);
+            if (e == hipSuccess && probs)
+                e = hipMemcpyAsync(probs, &one[0], sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+            if (e == hipSuccess && tor_hi)
+                e = hipMemcpyAsync(tor_hi, &one[0], sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+            if (e == hipSuccess && tor_lo)
+                e = hipMemcpyAsync(tor_lo, &one[1], sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess)
+                return hip_status(e);
+        } else {
+            if (probs)
+                probs[0] = 1.0;
+            if (tor_hi)
+                tor_hi[0] = 1.0;
+            if (tor_lo)
+                tor_lo[0] = 0.0;
+        }
         if (out) {
             std::memset(out, 0, sizeof(*out));
             out->tor = 1.0;
@@ -1791,22 +1808,27 @@ int tor_click_all(tor_ctx *ctx, int M, const double *O, long ld, double *probs, 
     e = hipEventRecord(ctx->ev0, ctx->stream);
     if (e == hipSuccess)
         e = launch_zeta(dTerms, dG, N, ctx->stream);
+    // where the kernel writes: the caller's device arrays, or the workspace
+    // (then copied to the caller's host arrays); the whole state's Tor for
+    // out is read from wherever tor_hi and tor_lo go
+    double *pP = probs ? (dev_out ? probs : dP) : nullptr;
+    double *pH = tor_hi ? (dev_out ? tor_hi : dH) : (out ? dH : nullptr);
+    double *pL = tor_lo ? (dev_out ? tor_lo : dL) : (out ? dL : nullptr);
     if (e == hipSuccess)
-        e = launch_click_out(dG, N, M, dDet, probs ? dP : nullptr, tor_hi || out ? dH : nullptr,
-                             tor_lo || out ? dL : nullptr, ctx->stream);
+        e = launch_click_out(dG, N, M, dDet, pP, pH, pL, ctx->stream);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev1, ctx->stream);
-    if (e == hipSuccess && probs)
+    if (e == hipSuccess && probs && !dev_out)
         e = hipMemcpyAsync(probs, dP, sizeof(double) * nP, hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess && tor_hi)
+    if (e == hipSuccess && tor_hi && !dev_out)
         e = hipMemcpyAsync(tor_hi, dH, sizeof(double) * nP, hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess && tor_lo)
+    if (e == hipSuccess && tor_lo && !dev_out)
         e = hipMemcpyAsync(tor_lo, dL, sizeof(double) * nP, hipMemcpyDeviceToHost, ctx->stream);
     double full[2] = {0.0, 0.0};
     if (e == hipSuccess && out)
-        e = hipMemcpyAsync(&full[0], dH + (nP - 1), sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+        e = hipMemcpyAsync(&full[0], pH + (nP - 1), sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess && out)
-        e = hipMemcpyAsync(&full[1], dL + (nP - 1), sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+        e = hipMemcpyAsync(&full[1], pL + (nP - 1), sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess)

@@ -196,3 +196,21 @@ def test_click_all_errors(ctx):
             assert ei.value.code == TOR_E_INVAL
     probs, (th, tl), r = ctx.click_all(np.zeros((0, 0), dtype=np.complex128), tor=True)
     assert probs.tolist() == [1.0] and th.tolist() == [1.0] and r.tor == 1.0
+
+
+def test_device_outputs_equal_host_outputs(ctx):
+    import torch
+    from paper_2109_04528_amd import TOR_INPUT_DEVICE, TOR_OUTPUT_DEVICE, Context
+    M = 14
+    O = state(M, 55)
+    say("case click_all device input and outputs M=14")
+    probs, (th, tl), r = ctx.click_all(O, tor=True)
+    Od = torch.from_numpy(O).to("cuda:0")
+    with Context(device=0, flags=TOR_INPUT_DEVICE | TOR_OUTPUT_DEVICE) as c:
+        pd, (hd, ld), rd = c.click_all(Od, tor=True)
+        assert pd.is_cuda and hd.is_cuda
+        assert np.array_equal(pd.cpu().numpy(), probs)
+        assert np.array_equal(hd.cpu().numpy(), th) and np.array_equal(ld.cpu().numpy(), tl)
+        assert (rd.tor, rd.tor_lo) == (r.tor, r.tor_lo)
+        p0, _, _ = c.click_all(torch.zeros((0, 0), dtype=torch.complex128, device="cuda:0"))
+        assert p0.cpu().tolist() == [1.0]
