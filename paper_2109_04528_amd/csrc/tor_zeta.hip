@@ -113,8 +113,52 @@ __global__ void __launch_bounds__(256) tor_zeta_bits(ddr *g, int nbits, int b0, 
             g[base + ((long long)j << b0)] = ddr{h[j], l[j]};
 }
 
-// one thread per pattern S < 2^M: S's bit i (mode i, decided at level i) is
-// index bit N-1-i
+// one pattern's outputs from its subset sum v
+__device__ __forceinline__ void put_pattern(long long S, int N, ddr v, double sq, double *probs, double *tor_hi,
+                                            double *tor_lo)
+{
+    const double sg = ((N - __popcll((unsigned long long)S)) & 1) ? -1.0 : 1.0;
+    if (tor_hi)
+        tor_hi[S] = sg * v.hi;
+    if (tor_lo)
+        tor_lo[S] = sg * v.lo;
+    if (probs)
+        probs[S] = sg * (v.hi + v.lo) * sq;
+}
+
+// Pattern S's sum sits at index bitreverse_N(S) (S's bit i is mode i, the
+// decision at level i, index bit N-1-i).  Without padding modes (M = N) the
+// permutation runs in tiles: a workgroup fixes the middle N-2A index bits,
+// reads the 2^A x 2^A entries of its top and bottom A bits in runs of 2^A
+// neighbours, and writes them out again in runs of 2^A neighbours of S
+// through LDS (the top A bits of S are the bottom A bits of the index
+// reversed, and the other way round).
+constexpr int TA = 5;
+__global__ void __launch_bounds__(256) tor_click_out_tiled(const ddr *g, int N, const double *sqrt_det, double *probs,
+                                                            double *tor_hi, double *tor_lo)
+{
+    __shared__ double th[1 << TA][(1 << TA) + 1], tl[1 << TA][(1 << TA) + 1];
+    const long long mid = blockIdx.x;
+    const int nm = N - 2 * TA;
+    for (int q = threadIdx.x; q < (1 << (2 * TA)); q += 256) {
+        const int h = q >> TA, l = q & ((1 << TA) - 1);
+        const ddr v = g[((long long)h << (N - TA)) | (mid << TA) | l];
+        th[h][l] = v.hi;
+        tl[h][l] = v.lo;
+    }
+    __syncthreads();
+    const long long rmid = nm > 0 ? (long long)(__builtin_bitreverse64((unsigned long long)mid) >> (64 - nm)) : 0;
+    const double sq = sqrt_det[0];
+    for (int q = threadIdx.x; q < (1 << (2 * TA)); q += 256) {
+        const int rl = q >> TA, rh = q & ((1 << TA) - 1);
+        const int h = (int)(__builtin_bitreverse32((unsigned)rh) >> (32 - TA));
+        const int l = (int)(__builtin_bitreverse32((unsigned)rl) >> (32 - TA));
+        const long long S = ((long long)rl << (N - TA)) | (rmid << TA) | rh;
+        put_pattern(S, N, ddr{th[h][l], tl[h][l]}, sq, probs, tor_hi, tor_lo);
+    }
+}
+
+// one thread per pattern S < 2^M (any M <= N): a gather, for the padded forms
 __global__ void __launch_bounds__(256) tor_click_out(const ddr *g, int N, int M, const double *sqrt_det,
                                                       double *probs, double *tor_hi, double *tor_lo)
 {
@@ -122,14 +166,7 @@ __global__ void __launch_bounds__(256) tor_click_out(const ddr *g, int N, int M,
     if (S >= (1ll << M))
         return;
     const unsigned long long idx = __builtin_bitreverse64((unsigned long long)S) >> (64 - N);
-    const ddr v = g[idx];
-    const double sg = ((N - __popcll((unsigned long long)S)) & 1) ? -1.0 : 1.0;
-    if (tor_hi)
-        tor_hi[S] = sg * v.hi;
-    if (tor_lo)
-        tor_lo[S] = sg * v.lo;
-    if (probs)
-        probs[S] = sg * (v.hi + v.lo) * sqrt_det[0];
+    put_pattern(S, N, g[idx], sqrt_det[0], probs, tor_hi, tor_lo);
 }
 
 }  // namespace
@@ -151,6 +188,11 @@ hipError_t launch_zeta(const double *t, ddr *g, int nbits, hipStream_t s)
 hipError_t launch_click_out(const ddr *g, int N, int M, const double *sqrt_det, double *probs, double *tor_hi,
                             double *tor_lo, hipStream_t s)
 {
+    if (M == N && N >= 2 * TA) {
+        hipLaunchKernelGGL(tor_click_out_tiled, dim3((unsigned)(1ll << (N - 2 * TA))), dim3(256), 0, s, g, N, sqrt_det,
+                           probs, tor_hi, tor_lo);
+        return hipGetLastError();
+    }
     const long long n = 1ll << M;
     hipLaunchKernelGGL(tor_click_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, N, M, sqrt_det, probs,
                        tor_hi, tor_lo);
