@@ -247,7 +247,8 @@ int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count,
  * The outputs are host memory, or device memory with TOR_OUTPUT_DEVICE (out
  * stays a host record).  O is as for tor_click_probs.  The terms are those of the FP64 real quadrature path, and
  * each Tor(O_S) is their exact sum while its partial sums stay below 2^53
- * (every term is a multiple of 2^-52).  Device workspace: about 24 * 2^N + 24 *
+ * (for a Gaussian state every subset determinant of I - O is at most 1, so
+ * every term is a double of magnitude at least 1, a multiple of 2^-52).  Device workspace: about 24 * 2^N + 24 *
  * 2^M bytes beyond what tor_eval of the state needs, N = max(M, 11).
  * Errors: TOR_E_INVAL (M > TOR_CLICK_ALL_MAX_M or > max_n, a null O, no
  * output, only one of tor_hi and tor_lo, a context with TOR_FORCE_COMPLEX or TOR_FACTOR_DD, or an O without

@@ -21,9 +21,12 @@
 // entries per workgroup; the higher bits in global passes of 4 bits, each
 // thread holding the 16 entries that differ only in those bits.
 //
-// Exactness: every term is a double of magnitude at least 1 (det <= 1), so a
-// multiple of 2^-52, and the additions are double-double sums built from
-// Knuth's TwoSum alone.  While a partial sum stays below 2^53 in magnitude,
+// Exactness: for a Gaussian state every subset determinant is at most 1
+// (sqrt(det(I - O)) / sqrt(det (I - O)_Z) is the probability that no mode
+// outside Z clicks, at least the probability sqrt(det(I - O)) that none
+// does), so every term is a double of magnitude at least 1, a multiple of
+// 2^-52, and the additions are double-double sums built from Knuth's TwoSum
+// alone.  While a partial sum stays below 2^53 in magnitude,
 // every intermediate quantity is a multiple of 2^-52 that fits its double, so
 // every g[S] is the exact sum of its terms, whatever the order.
 #include "tor_internal.hpp"
