@@ -28,3 +28,22 @@ def test_structured_O_moves_tor_by_rounding_only():
         d = (q.hi - qa.hi) + (q.lo - qa.lo)
         assert q.cancellation > 1e4
         assert abs(d) <= 1e-14 * abs(q.value)
+
+
+def test_gaussian_state_subset_determinants_lie_between_det_and_one():
+    """For the O of a Gaussian state, sqrt(det(I - O)) / sqrt(det (I - O)_Z) is
+    the probability that no mode outside Z clicks, so det(I - O) <= det (I -
+    O)_Z <= 1 for every mode subset Z although I - O has eigenvalues above 1:
+    every term of Eq. 2 is at least 1 in magnitude, which makes the
+    double-double sums of the library exact."""
+    import itertools
+    for n, seed, lo, hi, eta in [(9, 0, 0.3, 1.2, 0.9), (8, 1, 0.5, 1.0, 0.7), (7, 2, 1.5, 2.0, 1.0)]:
+        O = gen.random_O(n, seed, lo, hi, eta)
+        C = np.eye(2 * n) - O
+        assert np.linalg.eigvalsh(C).max() > 1.2  # not a contraction
+        full = np.linalg.det(C).real
+        for k in range(n + 1):
+            for Z in itertools.combinations(range(n), k):
+                idx = list(Z) + [z + n for z in Z]
+                d = np.linalg.det(C[np.ix_(idx, idx)]).real if Z else 1.0
+                assert full * (1 - 1e-12) <= d <= 1 + 1e-12
