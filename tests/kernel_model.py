@@ -92,16 +92,27 @@ def eliminate(src: np.ndarray, s: int):
     return dst, a * g1
 
 
-def tail(h, M, det, sgn, terms):
+def tail(h, M, det, sgn, terms, store=None, idx=0):
+    """The last M modes of a lane; with store, each term is also recorded
+    under its subset index (bit M-1 of the tail's part = the decision when M
+    modes are left)."""
     if M == 0:
         terms.append(sgn / math.sqrt(det))
+        if store is not None:
+            assert idx not in store
+            store[idx] = terms[-1]
         return
-    tail(h, M - 1, det, -sgn, terms)
+    tail(h, M - 1, det, -sgn, terms, store, idx)
     hn, pd = eliminate(h, M)
-    tail(hn, M - 1, det * pd, sgn, terms)
+    tail(hn, M - 1, det * pd, sgn, terms, store, idx | (1 << (M - 1)))
 
 
-def model_tor(O: np.ndarray, T: int = 3, B: int = 6, k: int = 0, real: bool = False, L: int = 1):
+def model_tor(O: np.ndarray, T: int = 3, B: int = 6, k: int = 0, real: bool = False, L: int = 1, store=None):
+    """Tor, term count and sum |t| by the kernel's schedule.  With a dict
+    store, every term is also recorded under the subset index the storing
+    kernel writes it to: bit N-1-l for the decision at level l, formed as the
+    root's k bits reversed, then the tier-A leaf x, then the lane, then the
+    tail's bits."""
     R = T + B
     C, N = pack_real(O, R) if real else pack(O, R)
     LA = N - R
@@ -170,5 +181,7 @@ def model_tor(O: np.ndarray, T: int = 3, B: int = 6, k: int = 0, real: bool = Fa
                         h = h[: E(M - 1)].copy()
                     includes += inc
                 excluded = (N - T) - includes
-                tail(h, T, det, -1.0 if excluded & 1 else 1.0, terms)
+                rrev = int(format(root, f"0{k}b")[::-1], 2) if k else 0
+                base = (rrev << (N - k)) | (x << R) | (lane << T)
+                tail(h, T, det, -1.0 if excluded & 1 else 1.0, terms, store, base)
     return math.fsum(terms), len(terms), math.fsum(abs(t) for t in terms)

@@ -1,8 +1,11 @@
 """The kernel's work split and sign bookkeeping, modelled in numpy
 (tests/kernel_model.py), reproduces the oracle on small inputs."""
+import math
+
 import numpy as np
 import pytest
 
+import kernel_model as km
 from kernel_model import model_tor
 from oracle import oracle as orc
 from paper_2109_04528_amd import inputs as gen
@@ -53,3 +56,26 @@ def test_quad_config_model_matches_oracle(n, k):
     q = orc.tor(O, mode=orc.QUAD)
     assert cnt == 1 << max(n, 9)
     assert abs(v - q.value) <= 64 * 1.1e-16 * max(n, 9) * q.sum_abs, (v, q.value)
+
+
+@pytest.mark.parametrize("n,k", [(12, 0), (13, 2), (14, 1)])
+def test_stored_term_indices(n, k):
+    """Every subset's term lands once at the index the storing kernel uses
+    (bit N-1-l = mode l included), with the sign and value of Eq. 2: the
+    model's store against a direct numpy determinant per subset."""
+    import itertools
+    O = gen.random_O(n, 7, 0.5, 1.0, 0.7)
+    store = {}
+    km.model_tor(O, T=5, B=6, k=k, real=True, L=2, store=store)
+    N = max(n, 11)
+    assert sorted(store) == list(range(1 << N))
+    C = np.eye(2 * n) - O
+    rng = np.random.default_rng(0)
+    for idx in rng.choice(1 << N, 300, replace=False).tolist() + [0, (1 << N) - 1]:
+        modes = [l for l in range(N) if (idx >> (N - 1 - l)) & 1]
+        real_modes = [m for m in modes if m < n]
+        sel = real_modes + [m + n for m in real_modes]
+        d = np.linalg.det(C[np.ix_(sel, sel)]).real if real_modes else 1.0
+        d *= 0.25 ** (len(modes) - len(real_modes))  # padding blocks I/2
+        want = (-1) ** (N - len(modes)) / math.sqrt(d)
+        assert abs(store[idx] - want) <= 1e-9 * abs(want)
