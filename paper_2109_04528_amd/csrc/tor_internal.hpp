@@ -136,7 +136,8 @@ __host__ __device__ constexpr long long Gsum(long long s) { return s <= 0 ? 0 : 
 //    only rewrites blocks of the modes that remain, each by the lane that
 //    reads it);
 //  * tier-A slots l = k+1 .. LA-1, slot l holding a node of N - l modes with
-//    its own stride NB(N - l);
+//    its own stride NB(N - l) (the real path keeps level LA-1 in LDS and
+//    leaves slot LA-1 unused);
 //  * the running determinants of the tier-A levels (LA + 1 real values).
 // Scalar offset of tier-A slot l (also of the determinants, at l = LA).
 __host__ __device__ constexpr long long tslot_off(int N, int k, int l)

@@ -21,7 +21,10 @@
 //    from an atomic counter and recomputes the root's Schur complement);
 //  * tier A: the wave walks the levels k..N-R-1 depth first; each step that
 //    changes the path is one wave-parallel rank-2 update, stacked per level
-//    in a private global scratch area (L2-resident);
+//    in a private global scratch area (L2-resident).  On the real path the
+//    node one level above the tier-A leaf (R+1 modes) is kept whole in LDS,
+//    so the last tier-A level is included in place in LDS and has no stack
+//    slot;
 //  * tier B: from each tier-A leaf (R = T + B modes left) the wave expands
 //    B-L levels breadth first in LDS, every include node of a level updated
 //    together (all lanes busy);
@@ -53,7 +56,7 @@ namespace tor {
 // the start of each of its granule arrays, as a 16-byte slot modulo 8 (and
 // modulo 16), differs from that of the other nodes read by the same group of
 // lanes; failing that, to the place with the fewest such clashes.
-template <int R, int BL, int ESZ, int L>
+template <int R, int BL, int ESZ, int L, int X0 = 0>
 struct NodePlacement {
     static constexpr int NN = 1 << BL;
     int off[NN + 1];
@@ -86,14 +89,14 @@ struct NodePlacement {
         int slot[NN] = {};
         int pos = 0;
         for (int t = 0; t < NN; ++t) {
-            const int nb = NB(R - level(t));
+            const int nb = t == 0 ? NB(R + X0) : NB(R - level(t));
             const int b0 = (pos + 15) & ~15;
             int best = b0, bestc = 1 << 30;
             for (int k = 0; k < 16 && bestc > 0; ++k) {
                 const int st = (b0 >> 4) + k;
                 int c = 0;
                 for (int u = 0; u < t; ++u) {
-                    const int unb = NB(R - level(u));
+                    const int unb = u == 0 ? NB(R + X0) : NB(R - level(u));
                     for (int mdl = 0; mdl < 2; ++mdl) {
                         const int G = grp[mdl] > 1 ? grp[mdl] : 1;
                         if (reader(u) / G != reader(t) / G)
@@ -110,7 +113,7 @@ struct NodePlacement {
             }
             off[t] = best;
             slot[t] = best >> 4;
-            pos = best + ESZ * NSZ(R - level(t));
+            pos = best + ESZ * (t == 0 ? NSZ(R + X0) : NSZ(R - level(t)));
         }
         off[NN] = pos;
     }
@@ -413,15 +416,15 @@ __device__ __forceinline__ void copy_node(const S *src, int snb, S *dst, int dnb
 // view of, that node's blocks per granule array, and the slot of its
 // determinant (0xff: the tier-A leaf).  The include node (lev, idx) keeps
 // its determinant at (2^(lev-1) - 1) + idx.
-template <int R, int B, int ESZ, int L>
+template <int R, int B, int ESZ, int L, int X0>
 __device__ __forceinline__ void view_entry(int t, int &off, int &nb, int &det)
 {
-    static constexpr NodePlacement<R, B - 1, ESZ, L> place{};
+    static constexpr NodePlacement<R, B - 1, ESZ, L, X0> place{};
     const int jl = 31 - __clz(t + 1);
     const int i = t + 1 - (1 << jl);
     if (i == 0) {
         off = 0;
-        nb = NB(R);
+        nb = NB(R + X0);
         det = 0xff;
     } else {
         const int tz = __builtin_ctz(i);
@@ -442,9 +445,10 @@ __device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcNB, u
                                              unsigned long long *nodeRec, uint32_t *blkRec, int lane)
 {
     constexpr int esz = (int)sizeof(S);
+    constexpr int X0 = std::is_same<S, double>::value ? 1 : 0;
     for (int t = lane; t < (1 << B) - 1; t += 64) {
         int off, nb, det;
-        view_entry<R, B, esz, L>(t, off, nb, det);
+        view_entry<R, B, esz, L, X0>(t, off, nb, det);
         srcOff[t] = (uint16_t)off;
         srcNB[t] = (uint8_t)nb;
         srcDet[t] = (uint8_t)det;
@@ -455,8 +459,8 @@ __device__ __forceinline__ void build_tables(uint16_t *srcOff, uint8_t *srcNB, u
         const int J = 32 - __clz(t + 1);  // t = (2^(J-1) - 1) + i
         const int i = t + 1 - (1 << (J - 1));
         int poff, pnb, pdet, coff, cnb, cdet;
-        view_entry<R, B, esz, L>(t, poff, pnb, pdet);
-        view_entry<R, B, esz, L>((1 << J) + 2 * i, coff, cnb, cdet);
+        view_entry<R, B, esz, L, X0>(t, poff, pnb, pdet);
+        view_entry<R, B, esz, L, X0>((1 << J) + 2 * i, coff, cnb, cdet);
         nodeRec[t] = (unsigned long long)(poff * esz) | ((unsigned long long)(16 * pnb) << 16) |
                      ((unsigned long long)(coff * esz) << 32);
     }
@@ -768,7 +772,10 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
     constexpr int R = T + B;
     constexpr int BL = B - L;                // levels expanded in LDS
     constexpr int NN_MAX = 1 << (BL - 1);    // include nodes of the last LDS level
-    constexpr int kBufScalars = NodePlacement<R, BL, (int)sizeof(S), L>{}.off[1 << BL] / (int)sizeof(S);
+    // real path: node 0 holds the level-(LA-1) node (R+1 modes), whose
+    // exclude view is the tier-A leaf and whose include child the next one
+    constexpr int X0 = std::is_same<S, double>::value ? 1 : 0;
+    constexpr int kBufScalars = NodePlacement<R, BL, (int)sizeof(S), L, X0>{}.off[1 << BL] / (int)sizeof(S);
     __shared__ S bufB[kBufScalars];
     __shared__ S nBa[NN_MAX];
     __shared__ RT<S> nInv[2 * NN_MAX];
@@ -866,11 +873,17 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
             RT<S> ldet;
             int linc;
             if (x == 0) {
-                // the first R modes of the root node, restrided to NB(R)
-                constexpr int GA = EPG((int)sizeof(S)) * NB(R);  // scalars per granule array
-                for (int e = lane; e < NSZ(R); e += 64) {
-                    const int g = e / GA;
-                    bufB[e] = ld_g(&rsrc[g * EPG((int)sizeof(S)) * rnb + (e - g * GA)]);
+                if constexpr (X0) {
+                    // the first R+1 modes of the root node (R when the root
+                    // is the leaf), restrided to NB(R + 1)
+                    copy_node<S, true, false>(rsrc, rnb, bufB, NB(R + 1), min(R + 1, N - k), lane);
+                } else {
+                    // the first R modes of the root node, restrided to NB(R)
+                    constexpr int GA = EPG((int)sizeof(S)) * NB(R);  // scalars per granule array
+                    for (int e = lane; e < NSZ(R); e += 64) {
+                        const int g = e / GA;
+                        bufB[e] = ld_g(&rsrc[g * EPG((int)sizeof(S)) * rnb + (e - g * GA)]);
+                    }
                 }
                 ldet = rdet;
                 linc = rinc;
@@ -898,12 +911,18 @@ __global__ void __launch_bounds__(64) tor_main(MainParams prm)
                     // the tier-A decisions above sl, bits LA-1-l of x
                     si = rinc + __popcll((unsigned long long)x >> (LA - sl));
                 }
-                // the deepest slot (level LA) is never the source of a later
-                // step: that child goes to LDS only; shallower ones also go to
-                // their stack slot
-                S *dst = (lvl + 1 < LA) ? wscr + tslot_off(N, k, lvl + 1) : nullptr;
                 RT<S> pd;
-                elim_global<S>(s, snb, dst, NB(N - lvl - 1), bufB, NB(R), N - lvl, lane, pd, bad);
+                if (X0 && t == 0) {
+                    // the include at level LA-1: its source, the level-(LA-1)
+                    // node of this path, is LDS node 0, updated in place
+                    elim_lds<S>(bufB, NB(R + 1), R + 1, lane, pd, bad);
+                } else {
+                    // the deepest slot a later step reads (level LA, or LA-1
+                    // when node 0 holds that level) gets the child in LDS
+                    // only; shallower ones also go to their stack slot
+                    S *dst = (lvl + 1 < LA - X0) ? wscr + tslot_off(N, k, lvl + 1) : nullptr;
+                    elim_global<S>(s, snb, dst, NB(N - lvl - 1), bufB, NB(R + X0), N - lvl, lane, pd, bad);
+                }
                 ldet = rmul(sd, pd);
                 linc = si + 1;
                 if (lane == 0)
