@@ -458,3 +458,27 @@ def test_serving_errors(ctx):
     assert ctx.poll(t) is not None
     with pytest.raises(TorError):
         ctx.poll(t)  # released after the first successful poll
+
+
+@pytest.mark.parametrize("n", [12, 14, 17])
+def test_split_depth_does_not_change_the_result(n):
+    """Each term is the same sequence of pivots whichever tier takes a level,
+    and the sums are exact for Gaussian-state input, so every split depth --
+    down to one tier-A leaf per root (k = n - 11 on the real path, and k = 0
+    with no root decisions) -- gives the same Torontonian bit for bit, on the
+    real and the complex path (the sum of |t|, a plain FP64 sum grouped by
+    root, to its rounding)."""
+    from paper_2109_04528_amd import TOR_FORCE_COMPLEX, Context
+    O = gen.random_O(n, 60 + n, 0.5, 1.0, 0.7)
+    for flags, R in ((0, 11), (TOR_FORCE_COMPLEX, 9)):
+        vals = {}
+        for k in sorted({0, 1, max(n - R - 1, 0), n - R}):
+            with Context(device=0, split_k=k, flags=flags) as c:
+                r = c.eval(O)
+            assert r.status == 0
+            vals[k] = (r.tor, r.tor_lo, r.sum_abs)
+        say(f"case split depths n={n} flags={flags}: {sorted(vals)} -> {set(vals.values())}")
+        assert len({v[:2] for v in vals.values()}) == 1
+        # the sum of |t| is a plain FP64 sum, grouped by root
+        sa = [v[2] for v in vals.values()]
+        assert max(sa) - min(sa) <= 1e-13 * max(sa)
