@@ -39,5 +39,43 @@ def build(verbose: bool = False, extra=None) -> str:
     return LIB
 
 
+SAN_DIR = os.path.join(HERE, "san")
+SAN_LIB = os.path.join(SAN_DIR, "libtor_san.so")
+SAN_EXE = os.path.join(SAN_DIR, "runtime_sanitized")
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """The same library with AddressSanitizer and UndefinedBehaviorSanitizer
+    on its host code (each -fsanitize after -Xarch_host, so the kernels are
+    the usual ones), and the C driver of tests/runtime_sanitize_main.c that
+    calls every entry point through it."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    san = []
+    for f in ("-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"):
+        san += ["-Xarch_host", f]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O2", "-g", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-fno-fast-math", "-Wno-unused-function"] + san + \
+          ["-I", os.path.join(HERE, "..", "include"), "-x", "hip"] + [os.path.join(CSRC, s) for s in SOURCES] + \
+          ["-o", SAN_LIB + ".tmp", "-lpthread"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(SAN_LIB + ".tmp", SAN_LIB)
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang"
+    drv = [clang, "-O1", "-g", "-std=gnu11", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fno-omit-frame-pointer", "-I", os.path.join(HERE, "..", "include"),
+           os.path.join(HERE, "..", "tests", "runtime_sanitize_main.c"),
+           "-L", SAN_DIR, "-ltor_san", "-Wl,-rpath,$ORIGIN", "-lm", "-o", SAN_EXE]
+    if verbose:
+        print(" ".join(drv), flush=True)
+    subprocess.run(drv, check=True)
+    return SAN_EXE
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    if "--sanitized" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))

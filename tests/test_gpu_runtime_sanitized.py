@@ -1,0 +1,57 @@
+"""The host runtime under AddressSanitizer and UndefinedBehaviorSanitizer
+(GPU).  paper_2109_04528_amd.build.build_sanitized() compiles the library
+with both sanitizers on its host code (the kernels are the usual ones) and
+the C driver tests/runtime_sanitize_main.c, which calls every entry point of
+the ABI -- single, batched, static, partial, plain, removal-order, click and
+served evaluation, forced root failures, the autotuner and its cache, and the
+error paths -- with any sanitizer report fatal.  Its values must equal the
+regular library's bit for bit (same kernels, same host arithmetic)."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2109_04528_amd import build as tb
+from paper_2109_04528_amd import inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [5, 8, 10, 12, 14, 16, 20]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.skipif(not os.path.exists(tb.SAN_EXE), reason="sanitized driver not built (build_sanitized)")
+def test_runtime_under_asan_and_ubsan(tmp_path):
+    mats = {n: np.ascontiguousarray(gen.random_O(n, 70 + n, 0.5, 1.0, 0.7)) for n in SIZES}
+    for n, O in mats.items():
+        O.tofile(str(tmp_path / f"m{n}.bin"))
+    np.ascontiguousarray(gen.random_O(12, 81, 0.5, 1.0, 0.7)).tofile(str(tmp_path / "s12.bin"))
+    env = dict(os.environ,
+               ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:verify_asan_link_order=0:exitcode=23",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    say("case sanitized runtime: running the driver")
+    res = subprocess.run([tb.SAN_EXE, str(tmp_path)], capture_output=True, text=True, env=env, timeout=240)
+    say(res.stdout[-2000:])
+    assert res.returncode == 0, res.stderr[-4000:]
+    assert "ERROR: AddressSanitizer" not in res.stderr and "runtime error" not in res.stderr, res.stderr[-4000:]
+    lines = {ln.split()[0]: ln.split()[1:] for ln in res.stdout.splitlines() if ln.strip()}
+    assert lines["done"] == ["0"]
+    from paper_2109_04528_amd import Context
+    with Context(device=0, max_n=34) as c:
+        for n in SIZES:
+            r = c.eval(mats[n])
+            for tag in (f"eval{n}", f"batch{n}", f"served{n}"):
+                st, tor, lo, sa = lines[tag][:4]
+                assert int(st) == 0 and float(tor) == r.tor and float(lo) == r.tor_lo, (tag, lines[tag], r)
+                if tag != f"served{n}":
+                    assert float(sa) == r.sum_abs
+        r = c.eval(mats[14])
+        assert float(lines["static14"][1]) == r.tor and float(lines["static14"][2]) == r.tor_lo
+        r = c.eval(mats[20])
+        assert float(lines["recovered20"][1]) == r.tor and int(lines["recovered20"][5]) == 2
