@@ -509,8 +509,19 @@ __device__ __forceinline__ void tierB_level(const TierB<S> &tb, RT<S> leafDet, i
     // with arrays st bytes apart: buf + p + g st + o
     char *const lb = reinterpret_cast<char *>(tb.buf);
     constexpr int GPB = 4 / EPG((int)sizeof(S));  // granules per block
+    // 16-byte scalars: each node's blocks start on a 16-lane boundary (NS
+    // lanes per node), so the 16 lanes one LDS cycle serves of a 128-bit
+    // access never span two nodes, whose neighbouring 16-byte words would
+    // meet in the same banks.  This costs no pass at the levels of the
+    // complex and double-double kernels and halves their LDS bank-conflict
+    // cycles; the 8-byte path keeps packed nodes (its passes hold two
+    // granules per block, and the extra index registers cost it waves).
+    constexpr bool AL = !std::is_same<S, double>::value;
+    constexpr int NS = AL ? (NBO + 15) / 16 * 16 : NBO;  // lanes per node in a pass
     auto pass = [&](int it) {
-        const int i = (int)((unsigned)it / NBO), bi = it - i * NBO;
+        const int i = (int)((unsigned)it / NS), bi = it - i * NS;
+        if (AL && bi >= NBO)
+            return;
         const unsigned long long rec = tb.nodeRec[NN - 1 + i];
         const uint32_t br = tb.blkRec[bi];
         const int par = (int)(rec & 0xffffu), st = (int)((rec >> 16) & 0xffffu), cof = (int)(rec >> 32);
@@ -545,7 +556,7 @@ __device__ __forceinline__ void tierB_level(const TierB<S> &tb, RT<S> leafDet, i
             *reinterpret_cast<Gran<S> *>(pc + g * 16 * NBO) = q;
         }
     };
-    constexpr int TOT = NN * NBO, FULL = TOT / 64;
+    constexpr int TOT = NN * NS, FULL = TOT / 64;
     // real path: an empty asm hides that the lane index is the same in every
     // leaf, so the passes' node and block indices are recomputed per leaf
     // instead of being held in registers across the whole leaf loop (10
