@@ -17,6 +17,7 @@ from ._lib import (  # noqa: F401
     TOR_E_NOMEM, TOR_E_DEVICE, TOR_E_TIMEOUT, TOR_E_UNKNOWN, TOR_E_SCRATCH,
     TOR_ACCUM_DD, TOR_ACCUM_FP64, TOR_INPUT_DEVICE, TOR_CHECK_HERMITIAN, TOR_FORCE_COMPLEX,
     TOR_FACTOR_DD, TOR_OUTPUT_DEVICE, TOR_TUNE_REAL, TOR_TUNE_COMPLEX, TOR_TUNE_QUAD,
+    TOR_CLICK_ALL_MAX_M,
 )
 
 

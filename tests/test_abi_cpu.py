@@ -35,6 +35,21 @@ def test_strerror_covers_codes():
     assert lib.tor_strerror(-99).decode() == "unrecognised status code"
 
 
+def test_constants_match_header():
+    """Every integer #define of the header that the binding mirrors has the
+    header's value, and the binding mirrors every flag and error code."""
+    src = open(HEADER).read()
+    defs = {}
+    for name, val in re.findall(r"^#define (TOR_\w+)\s+\(?(-?(?:0x)?[0-9a-fA-F]+)u?\)?", src, flags=re.M):
+        defs[name] = int(val, 0)
+    assert len(defs) >= 20
+    for name, val in defs.items():
+        if name.startswith(("TOR_E_", "TOR_ACCUM_", "TOR_TUNE_")) or name in (
+                "TOR_OK", "TOR_PENDING", "TOR_INPUT_DEVICE", "TOR_CHECK_HERMITIAN", "TOR_FORCE_COMPLEX",
+                "TOR_FACTOR_DD", "TOR_OUTPUT_DEVICE", "TOR_CLICK_ALL_MAX_M"):
+            assert getattr(_lib, name) == val, name
+
+
 def test_struct_layouts_match_header():
     # tor_options: int, ptr, ptr, size_t, 4 ints, unsigned -> 56 bytes on x86-64
     assert ctypes.sizeof(_lib.tor_options) == 56

@@ -214,3 +214,55 @@ def test_device_outputs_equal_host_outputs(ctx):
         assert (rd.tor, rd.tor_lo) == (r.tor, r.tor_lo)
         p0, _, _ = c.click_all(torch.zeros((0, 0), dtype=torch.complex128, device="cuda:0"))
         assert p0.cpu().tolist() == [1.0]
+
+
+def test_largest_state(ctx):
+    """The largest state the call takes (M = 30: 2^30 terms, 24 GB of
+    workspace), outputs left on the device.  A pattern that holds the last
+    mode, and has enough modes that its own staged form needs no padding
+    modes (11 on the real path), forms every term exactly as a call for that
+    pattern alone does (the same include steps, the same last-level
+    determinant, exact sums), so the two agree bit for bit; small patterns
+    are checked against the FP64 oracle at the statistical bound; the
+    probabilities sum to one."""
+    import torch
+    from paper_2109_04528_amd import TOR_CLICK_ALL_MAX_M, TOR_OUTPUT_DEVICE, Context
+    M = TOR_CLICK_ALL_MAX_M
+    O = state(M, 56)
+    say(f"case click_all largest state M={M}")
+    with Context(device=0, flags=TOR_OUTPUT_DEVICE) as c:
+        pd, (hd, ld), r = c.click_all(O, tor=True)
+        torch.cuda.synchronize(0)
+        e = ctx.eval(O)
+        full = (1 << M) - 1
+        say(f"  whole state {r.tor!r},{r.tor_lo!r} eval {e.tor!r},{e.tor_lo!r} ms={r.device_ms:.1f}")
+        assert r.status == 0 and (r.tor, r.tor_lo) == (e.tor, e.tor_lo)
+        assert (hd[full].item(), ld[full].item()) == (e.tor, e.tor_lo)
+        s = torch.sum(pd).item()
+        say(f"  sum of 2^{M} probabilities - 1 = {s - 1.0:.3e}; min {torch.min(pd).item():.3e}")
+        assert abs(s - 1.0) <= 1e-10
+        rng = np.random.default_rng(56)
+        last = 1 << (M - 1)
+        pats = [last, full] + [int(x) | last for x in rng.integers(0, last, 10)]
+        pats += [int(x) for x in rng.integers(0, last, 6)]
+        pats = [S for S in pats if S != full]
+        idx = torch.tensor(pats, dtype=torch.int64, device=pd.device)
+        gh, gl, gp = hd[idx].cpu().numpy(), ld[idx].cpu().numpy(), pd[idx].cpu().numpy()
+    p1, res = ctx.click_probs(O, pats)
+    sq = sqrt_det(O)
+    bitwise = 0
+    for j, S in enumerate(pats):
+        rr = res[j]
+        assert rr.status == 0
+        if S & last and bin(S).count("1") >= 11:
+            assert (gh[j], gl[j]) == (rr.tor, rr.tor_lo), S
+            assert gp[j] == p1[j]
+            bitwise += 1
+        elif bin(S).count("1") <= 16:
+            modes = [i for i in range(M) if (S >> i) & 1]
+            q = orc.tor(gen.click_submatrix(O, modes), mode=orc.F64)
+            tol = bounds.sum_bound(q.sum_sq, bounds.U64, bounds.U64)
+            assert abs((gh[j] - q.hi) + (gl[j] - q.lo)) <= tol
+            assert abs(gp[j] - q.value * sq) <= tol * sq + 4e-16 * abs(q.value * sq)
+    say(f"  {len(pats)} sampled patterns checked, {bitwise} of them bit for bit")
+    assert bitwise >= 8
