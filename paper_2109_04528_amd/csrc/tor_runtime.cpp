@@ -749,8 +749,11 @@ void fill_result(const Mat &st, int path, const double *r, float ms, tor_result 
 }
 
 // Split depths for a launch of several matrices: roots of about equal work,
-// about four per persistent wave over the whole launch (a lone matrix keeps
-// its own tuned or default depth).
+// about eight per persistent wave over the whole launch (a lone matrix keeps
+// its own tuned or default depth).  With four, the waves that draw the last
+// roots still run one when the others have none left; eight such roots
+// shorten that end by about as much as their extra root set-ups cost, and
+// sixteen or thirty-two gain nothing more.
 void batch_ks(const tor_ctx *ctx, int path, const std::vector<Mat *> &grp, std::vector<int> &ks)
 {
     if (grp.size() == 1 || ctx->opt.split_k > 0) {
@@ -764,7 +767,7 @@ void batch_ks(const tor_ctx *ctx, int path, const std::vector<Mat *> &grp, std::
         work += std::ldexp(1.0, m->N);
         Nmax = std::max(Nmax, m->N);
     }
-    const double per_root = std::max(work / (4.0 * launch_grid(ctx, path, Nmax)), 1.0);
+    const double per_root = std::max(work / (8.0 * launch_grid(ctx, path, Nmax)), 1.0);
     const int lg = (int)std::floor(std::log2(per_root) + 0.5);
     for (size_t j = 0; j < grp.size(); j++) {
         const int N = grp[j]->N;
