@@ -312,3 +312,46 @@ def test_every_term_against_oracle(ctx, M, sample):
         assert rel <= tol, (Z, tg, tq)
         assert (tg > 0) == (tq > 0)
     say(f"  {len(Zs)} terms; cond(I - O) = {cond:.1f}; worst relative error / bound = {worst:.3g}")
+
+
+def test_terms_of_the_headline_workload(ctx):
+    """Sampled terms of the n = 30 precision workload (r ~ U[.3, 1.2],
+    eta = .9, seed 0; the benchmark's matrix, R about 1.5e14), each against
+    the __float128 oracle's term for its subset.  A term t[Z] is the
+    alternating sum of the exact subset sums g[S] over the 2^|Z| patterns S
+    inside Z, so subsets of up to 14 modes are read back from the device."""
+    import itertools
+    import torch
+    from paper_2109_04528_amd import TOR_OUTPUT_DEVICE, Context
+    M = 30
+    O = gen.random_O(M, 0, 0.3, 1.2, 0.9)
+    say("case terms of the n=30 precision workload")
+    rng = np.random.default_rng(30)
+    Zs = [0, 1 << 29, 1 << 17, (1 << 29) | 1]
+    for size in (2, 3, 5, 8, 11, 14):
+        for _ in range(3):
+            Zs.append(int(sum(1 << int(i) for i in rng.choice(M, size, replace=False))))
+    ev = np.linalg.eigvalsh(np.eye(2 * M) - O)
+    cond = ev.max() / ev.min()
+    worst = 0.0
+    with Context(device=0, flags=TOR_OUTPUT_DEVICE) as c:
+        _, (hd, ld), r = c.click_all(O, tor=True, probs=False)
+        torch.cuda.synchronize(0)
+        assert r.status == 0
+        for Z in Zs:
+            bits = [i for i in range(M) if (Z >> i) & 1]
+            subs = [sum(1 << b for b, on in zip(bits, sel) if on) for sel in itertools.product((0, 1), repeat=len(bits))]
+            idx = torch.tensor(subs, dtype=torch.int64, device=hd.device)
+            gh, gl = hd[idx].cpu().numpy(), ld[idx].cpu().numpy()
+            tot = 0
+            for S, h, l in zip(subs, gh, gl):
+                # g[S] = (-1)^(M-|S|) Tor(O_S); t[Z] = sum over S of (-1)^(|Z|-|S|) g[S]
+                sign = -1 if (M - len(bits)) & 1 else 1
+                tot += sign * (int(h * 2.0 ** 52) + int(l * 2.0 ** 52))
+            tg = tot / 2.0 ** 52
+            d, tq = orc.det(O, Z, mode=orc.QUAD)
+            tol = (2 * len(bits) + 2) ** 2 * bounds.U64 * cond
+            rel = abs(tg - tq) / abs(tq)
+            worst = max(worst, rel / tol)
+            assert rel <= tol, (Z, tg, tq)
+    say(f"  {len(Zs)} terms; cond(I - O) = {cond:.1f}; worst relative error / bound = {worst:.3g}")
