@@ -273,3 +273,27 @@ def test_same_host_pointer_with_different_sizes(ctxs):
     a, b = h.eval(O), h.eval(sub)
     assert same_value(got[0], a) and same_value(got[2], a)
     assert same_value(got[1], b)
+
+
+def test_mixed_batch_statuses_and_values(ctxs):
+    """One batch of both arithmetic paths (two launches), an input rejected
+    by the staging checks, the empty matrix and a matrix that fails the
+    pivot test: each matrix gets its own status, and every valid one the
+    value it has alone, bit for bit."""
+    from paper_2109_04528_amd import TOR_E_INVAL, TOR_E_NOT_PD, TOR_OK
+    h, _ = ctxs
+    real14 = gen.random_O(14, 61, 0.5, 1.0, 0.7)
+    herm12 = gen.random_hpd_O(12, 62, 0.05, 0.9)
+    nan8 = gen.random_O(8, 63, 0.5, 1.0, 0.7)
+    nan8[5, 2] = np.nan  # lower triangle: read and rejected
+    real20 = gen.random_O(20, 64, 0.3, 1.2, 0.9)
+    bad10 = gen.random_O(10, 65, 0.3, 1.2, 0.9) + 2.0 * np.eye(20)
+    empty = gen.vacuum_O(0)
+    Os = [real14, nan8, herm12, empty, bad10, real20]
+    say("case mixed batch: both paths, NaN input, empty, not positive definite")
+    rs = h.eval_batch(Os, check=False)
+    assert [r.status for r in rs] == [TOR_OK, TOR_E_INVAL, TOR_OK, TOR_OK, TOR_E_NOT_PD, TOR_OK]
+    assert [rs[i].path for i in (0, 2, 5)] == [1, 2, 1]
+    for i in (0, 2, 3, 5):
+        assert same_value(rs[i], h.eval(Os[i])), i
+    assert rs[3].tor == 1.0
