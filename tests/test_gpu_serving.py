@@ -160,3 +160,29 @@ def test_serve_config_rejects_bad_values():
                    {"max_queue": 0}):
             with pytest.raises(TorError):
                 ctx.serve_config(**kw)
+
+
+def test_destroy_with_requests_in_flight():
+    """Closing a context while its scheduler has work: the launch on the GPU
+    finishes, the requests still waiting are dropped, and the call returns
+    after that scheduler round, not after the 9 s of work that was queued.
+    The device stays usable (a new context evaluates as before)."""
+    from paper_2109_04528_amd import Context
+    big = [gen.random_O(n, 700 + n, 0.5, 1.0, 0.7) for n in (32, 32, 31, 31, 30, 30)]
+    small = [gen.random_O(n, 720 + n, 0.5, 1.0, 0.7) for n in range(8, 20)]
+    probe = gen.random_O(16, 740, 0.5, 1.0, 0.7)
+    with Context(device=0) as ref:
+        want = ref.eval(probe)
+    say("case destroy with requests in flight")
+    c = Context(device=0)
+    for O in big * 250 + small:
+        c.submit(O)
+    time.sleep(0.05)  # the scheduler is inside its first launches
+    t0 = time.perf_counter()
+    c.close()
+    dt = time.perf_counter() - t0
+    say(f"  close took {1e3 * dt:.1f} ms with about 9 s of queued work")
+    assert dt < 1.0
+    with Context(device=0) as again:
+        got = again.eval(probe)
+    assert same_value(got, want)
