@@ -186,3 +186,41 @@ def test_destroy_with_requests_in_flight():
     with Context(device=0) as again:
         got = again.eval(probe)
     assert same_value(got, want)
+
+
+def test_both_paths_and_the_double_double_factor_served():
+    """Requests of both arithmetic paths in one stream (Gaussian-state
+    matrices on the real quadrature form, general Hermitian ones on the
+    complex form), chunked: every result equals the same matrix evaluated
+    alone, bit for bit.  A double-double context serving its own: its terms
+    are double-doubles, whose sums are not exact, and serving splits a
+    request into finer roots than a lone evaluation, so the two results
+    agree to the double-double rounding of the sum (2^-90 of sum |t|)."""
+    from paper_2109_04528_amd import TOR_FACTOR_DD, Context
+    real = [gen.random_O(n, 950 + n, 0.5, 1.0, 0.7) for n in (22, 13, 25)]
+    herm = [gen.random_hpd_O(n, 960 + n, 0.05, 0.9) for n in (21, 11, 24)]
+    mats = [real[0], herm[0], real[1], herm[1], real[2], herm[2]]
+    with Context(device=0) as ctx:
+        ctx.serve_config(chunk_subsets=1 << 21, oldest_share=0.5, express_subsets=1 << 14)
+        say("case serving both paths")
+        ts = [ctx.submit(O) for O in mats]
+        got = collect(ctx, ts)
+        paths = []
+        for O, t in zip(mats, ts):
+            r = got[t]
+            paths.append(r.path)
+            assert same_value(r, ctx.eval(O))
+        assert paths == [1, 2, 1, 2, 1, 2]
+        assert got[ts[4]].launches >= 2 and got[ts[5]].launches >= 2
+    dd = [gen.random_O(n, 970 + n, 0.5, 1.0, 0.7) for n in (18, 10, 22)]
+    with Context(device=0, flags=TOR_FACTOR_DD) as qctx:
+        qctx.serve_config(chunk_subsets=1 << 19, oldest_share=0.5, express_subsets=1 << 12)
+        say("case serving, double-double factor")
+        ts = [qctx.submit(O) for O in dd]
+        got = collect(qctx, ts)
+        for O, t in zip(dd, ts):
+            r, alone = got[t], qctx.eval(O)
+            assert r.path == 3 and r.status == 0
+            d = abs((r.tor - alone.tor) + (r.tor_lo - alone.tor_lo))
+            assert d <= 2.0 ** -90 * alone.sum_abs, (d, alone.sum_abs)
+        assert got[ts[2]].launches >= 2
