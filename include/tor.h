@@ -248,13 +248,15 @@ int tor_click_probs(tor_ctx *ctx, int M, const double *O, long ld, int count,
  * stays a host record).  O is as for tor_click_probs.  The terms are those of the FP64 real quadrature path, and
  * each Tor(O_S) is their exact sum while its partial sums stay below 2^53
  * (for a Gaussian state every subset determinant of I - O is at most 1, so
- * every term is a double of magnitude at least 1, a multiple of 2^-52).  Device workspace: about 24 * 2^N + 24 *
- * 2^M bytes beyond what tor_eval of the state needs, N = max(M, 11).
+ * every term is a double of magnitude at least 1, a multiple of 2^-52).  Device workspace: about 24 * 2^N bytes
+ * beyond what tor_eval of the state needs, N = max(M, 11), plus 8 * 2^M bytes
+ * for each output that goes to host memory (96 GiB at M = 32 with the
+ * outputs on the device).
  * Errors: TOR_E_INVAL (M > TOR_CLICK_ALL_MAX_M or > max_n, a null O, no
  * output, only one of tor_hi and tor_lo, a context with TOR_FORCE_COMPLEX or TOR_FACTOR_DD, or an O without
  * the block structure of a Gaussian state), TOR_E_NOT_PD, TOR_E_NUMERIC (a
  * non-finite term; no re-run), TOR_E_NOMEM. */
-#define TOR_CLICK_ALL_MAX_M 30
+#define TOR_CLICK_ALL_MAX_M 32
 int tor_click_all(tor_ctx *ctx, int M, const double *O, long ld, double *probs, double *tor_hi, double *tor_lo,
                   tor_result *out);
 

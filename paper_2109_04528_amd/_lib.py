@@ -37,7 +37,7 @@ TOR_FORCE_COMPLEX = 0x4
 TOR_FACTOR_DD = 0x8
 TOR_OUTPUT_DEVICE = 0x10
 
-TOR_CLICK_ALL_MAX_M = 30  # the most modes tor_click_all takes
+TOR_CLICK_ALL_MAX_M = 32  # the most modes tor_click_all takes
 
 # every symbol include/tor.h declares
 EXPORTS = [

@@ -1774,13 +1774,15 @@ int tor_click_all(tor_ctx *ctx, int M, const double *O, long ld, double *probs, 
     const int N = mats[0].N;
     const int k = choose_k(ctx, N, PATH_REAL);
     // after the staged matrix: root slots, the 2^N terms, their subset sums,
-    // the device outputs, then what run_launch needs
+    // staging arrays for the outputs that go to the host (none with
+    // TOR_OUTPUT_DEVICE), then what run_launch needs
     const long long nS = 1ll << N, nP = 1ll << M;
     const size_t oSlots = align_up(end, 256);
     const size_t oTerms = align_up(oSlots + sizeof(double) * 4 * ((size_t)1 << k), 256);
     const size_t oG = align_up(oTerms + sizeof(double) * (size_t)nS, 256);
     const size_t oOut = align_up(oG + sizeof(ddr) * (size_t)nS, 256);
-    const size_t off = align_up(oOut + 3 * sizeof(double) * (size_t)nP, 256);
+    const int nstage = dev_out ? 0 : (probs ? 1 : 0) + (tor_hi ? 2 : 0);
+    const size_t off = align_up(oOut + nstage * sizeof(double) * (size_t)nP, 256);
     const long long stack = wave_stack_bytes(PATH_REAL, N, k);
     const int fit = std::max(1, std::min(main_store_occupancy(), ctx->fit[PATH_REAL]));
     const int grid = ctx->num_cu * fit;
@@ -1789,7 +1791,7 @@ int tor_click_all(tor_ctx *ctx, int M, const double *O, long ld, double *probs, 
         return rc;
     double *dTerms = (double *)(ctx->ws + oTerms);
     ddr *dG = (ddr *)(ctx->ws + oG);
-    double *dP = (double *)(ctx->ws + oOut), *dH = dP + nP, *dL = dH + nP;
+    double *dP = (double *)(ctx->ws + oOut), *dH = dP + (probs ? nP : 0), *dL = dH + nP;
     dDet = (double *)(ctx->ws + bO + bScr);  // the workspace may have moved
     std::vector<ProblemDesc> descs(1);
     ProblemDesc &d = descs[0];
@@ -1812,12 +1814,11 @@ int tor_click_all(tor_ctx *ctx, int M, const double *O, long ld, double *probs, 
     if (e == hipSuccess)
         e = launch_zeta(dTerms, dG, N, ctx->stream);
     // where the kernel writes: the caller's device arrays, or the workspace
-    // (then copied to the caller's host arrays); the whole state's Tor for
-    // out is read from wherever tor_hi and tor_lo go
+    // (then copied to the caller's host arrays)
     double *pP = probs ? (dev_out ? probs : dP) : nullptr;
-    double *pH = tor_hi ? (dev_out ? tor_hi : dH) : (out ? dH : nullptr);
-    double *pL = tor_lo ? (dev_out ? tor_lo : dL) : (out ? dL : nullptr);
-    if (e == hipSuccess)
+    double *pH = tor_hi ? (dev_out ? tor_hi : dH) : nullptr;
+    double *pL = tor_lo ? (dev_out ? tor_lo : dL) : nullptr;
+    if (e == hipSuccess && (pP || pH))
         e = launch_click_out(dG, N, M, dDet, pP, pH, pL, ctx->stream);
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev1, ctx->stream);
@@ -1827,11 +1828,12 @@ int tor_click_all(tor_ctx *ctx, int M, const double *O, long ld, double *probs, 
         e = hipMemcpyAsync(tor_hi, dH, sizeof(double) * nP, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess && tor_lo && !dev_out)
         e = hipMemcpyAsync(tor_lo, dL, sizeof(double) * nP, hipMemcpyDeviceToHost, ctx->stream);
-    double full[2] = {0.0, 0.0};
+    // the whole state's Tor for out: the subset sum of the pattern of every
+    // mode (index bit N-1-q for mode q: the top M bits), with the sign
+    // (-1)^(N-M) that turns a subset sum into a Torontonian
+    ddr full{0.0, 0.0};
     if (e == hipSuccess && out)
-        e = hipMemcpyAsync(&full[0], pH + (nP - 1), sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess && out)
-        e = hipMemcpyAsync(&full[1], pL + (nP - 1), sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+        e = hipMemcpyAsync(&full, dG + ((nP - 1) << (N - M)), sizeof(ddr), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess)
@@ -1840,7 +1842,8 @@ int tor_click_all(tor_ctx *ctx, int M, const double *O, long ld, double *probs, 
     if (out) {
         // the result of the whole state (every mode clicks), with the sum of
         // |t| over all subsets and the device time of both steps
-        const double r[4] = {full[0], full[1], res[2], 0.0};
+        const double sg = ((N - M) & 1) ? -1.0 : 1.0;
+        const double r[4] = {sg * full.hi, sg * full.lo, res[2], 0.0};
         fill_result(mats[0], PATH_REAL, r, ms_main + ms_zeta, out);
     }
     return TOR_OK;

@@ -198,7 +198,9 @@ int main(int argc, char **argv)
     expect(tor_eval(ctx, 35, m[0], 70, &r) == TOR_E_INVAL, "n > max_n");
     expect(tor_eval(ctx, 5, m[0], 9, &r) == TOR_E_INVAL, "ld < 2n");
     expect(tor_serve_config(ctx, 10, 0, 0.5, 1) == TOR_E_INVAL, "bad chunk");
-    expect(tor_click_all(ctx, 31, m[0], 62, NULL, NULL, NULL, &r) == TOR_E_INVAL, "M too large");
+    expect(tor_click_all(ctx, TOR_CLICK_ALL_MAX_M + 1, m[0], 2 * (TOR_CLICK_ALL_MAX_M + 1), NULL, NULL, NULL, &r) ==
+               TOR_E_INVAL,
+           "M too large");
     for (int c = -9; c <= 1; c++)
         expect(tor_strerror(c) != NULL && tor_strerror(c)[0] != 0, "tor_strerror");
     {

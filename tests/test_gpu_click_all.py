@@ -189,6 +189,10 @@ def test_click_all_errors(ctx):
     with pytest.raises(TorError) as ei:
         ctx.click_all(herm)
     assert ei.value.code == TOR_E_INVAL
+    from paper_2109_04528_amd import TOR_CLICK_ALL_MAX_M
+    with pytest.raises(TorError) as ei:  # refused before anything is read or allocated
+        ctx.click_all(np.zeros((2 * TOR_CLICK_ALL_MAX_M + 2,) * 2, dtype=np.complex128))
+    assert ei.value.code == TOR_E_INVAL
     for flags in (TOR_FORCE_COMPLEX, TOR_FACTOR_DD):
         with Context(device=0, flags=flags) as c:
             with pytest.raises(TorError) as ei:
@@ -217,8 +221,8 @@ def test_device_outputs_equal_host_outputs(ctx):
 
 
 def test_largest_state(ctx):
-    """The largest state the call takes (M = 30: 2^30 terms, 24 GB of
-    workspace), outputs left on the device.  A pattern that holds the last
+    """The largest state the call takes (M = 32: 2^32 terms, 96 GiB of
+    workspace and 96 GiB of outputs left on the device).  A pattern that holds the last
     mode, and has enough modes that its own staged form needs no padding
     modes (11 on the real path), forms every term exactly as a call for that
     pattern alone does (the same include steps, the same last-level
