@@ -232,8 +232,9 @@ def main():
                     help="the n=24 pair workload by the append form, the paper's removal order and plain")
     ap.add_argument("--click", type=int, default=1024,
                     help="click-pattern probabilities of one 32-mode state (0: skip)")
-    ap.add_argument("--click-all", type=int, default=1,
-                    help="every click pattern of a 16- and a 24-mode state at once")
+    ap.add_argument("--click-all", type=int, default=2,
+                    help="every click pattern of a 16- and a 24-mode state at once (1), and of the "
+                         "32-mode state of the click block (2)")
     ap.add_argument("--quad", type=int, default=1,
                     help="also time the same n=30 Torontonian with the double-double factor")
     ap.add_argument("--precision", type=int, default=1,
@@ -477,6 +478,24 @@ def main():
                 row["max_prob_difference"] = float(np.max(np.abs(pa - pd)))
             click_all[f"M{M}"] = row
         actx.close()
+        if args.click_all > 1:
+            # every pattern of the 32-mode state of the click block (r ~ U[.5, 1],
+            # eta = .7, seed 9): 96 GiB of workspace, the probabilities left
+            # in device memory (32 GiB), one call after a sizing call
+            from paper_2109_04528_amd import TOR_OUTPUT_DEVICE, TorError
+            Ob = inputs.random_O(32, 9, 0.5, 1.0, 0.7)
+            try:
+                with Context(device=0, stream=stream, flags=TOR_OUTPUT_DEVICE) as bctx:
+                    bctx.click_all(Ob)
+                    t0 = time.perf_counter()
+                    pb, _, rb = bctx.click_all(Ob)
+                    t1 = time.perf_counter()
+                    click_all["M32"] = {"modes": 32, "patterns": 1 << 32, "seconds": t1 - t0,
+                                        "device_ms": rb.device_ms, "sum_of_probs": float(torch.sum(pb).item()),
+                                        "outputs": "device"}
+                    del pb
+            except TorError as err:
+                click_all["M32"] = {"error": str(err)}
         print("bench: every click pattern done", file=sys.stderr, flush=True)
 
     serve = None
