@@ -17,9 +17,16 @@
 // one by one.
 //
 // The transform adds along one index bit at a time (g[S] += g[S without bit b]
-// for every S with bit b set).  The low ZB bits run in LDS, one block of 2^ZB
-// entries per workgroup; the higher bits in global passes of 4 bits, each
-// thread holding the 16 entries that differ only in those bits.
+// for every S with bit b set).  The low 10 to 12 bits run in LDS, one block
+// of 1024 to 4096 entries per workgroup; the higher bits in global passes of
+// up to ZG = 5 bits, each thread holding the 32 entries that differ only in
+// those bits.  Every pass reads and writes all 2^M sums once, so the launch
+// takes as few passes as 12 bits in LDS allow, with the smallest LDS block
+// that reaches that count: a 4096-entry block (64 KB) leaves room for two
+// workgroups per CU and keeps fewer loads in flight than the 1024-entry one
+// (16 KB).  At M = 32 that is 12 bits in LDS and four 5-bit passes, against
+// 10 bits and six passes of 4 bits (226 ms to 172 ms for all 2^32 patterns);
+// at M = 24 and 28, 10 bits in LDS.
 //
 // Exactness: for a Gaussian state every subset determinant is at most 1
 // (sqrt(det(I - O)) / sqrt(det (I - O)_Z) is the probability that no mode
@@ -35,9 +42,8 @@ namespace tor {
 
 namespace {
 
-constexpr int ZB = 10;  // index bits transformed in LDS (blocks of 1024 entries)
-constexpr int ZT = 256; // threads per LDS block
-constexpr int ZG = 4;   // index bits per global pass
+constexpr int ZB_MAX = 12;  // most index bits transformed in LDS (blocks of 4096 entries)
+constexpr int ZG = 5;       // index bits per global pass
 
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
 {
@@ -58,7 +64,9 @@ __device__ __forceinline__ void dd_acc(double &ah, double &al, double bh, double
     two_sum(s, e, ah, al);
 }
 
-// bits 0 .. nb-1 of a block of 2^nb entries (nb <= ZB), terms in, double-double out
+// bits 0 .. nb-1 of a block of 2^nb entries (nb <= ZB), terms in,
+// double-double out; ZT threads
+template <int ZB, int ZT>
 __global__ void __launch_bounds__(ZT) tor_zeta_lds(const double *t, ddr *g, int nb)
 {
     __shared__ double hs[1 << ZB], ls[1 << ZB];
@@ -176,8 +184,17 @@ __global__ void __launch_bounds__(256) tor_click_out(const ddr *g, int N, int M,
 
 hipError_t launch_zeta(const double *t, ddr *g, int nbits, hipStream_t s)
 {
-    const int nb = nbits < ZB ? nbits : ZB;
-    hipLaunchKernelGGL(tor_zeta_lds, dim3((unsigned)(1ll << (nbits - nb))), dim3(ZT), 0, s, t, g, nb);
+    // global passes after zb bits in LDS
+    auto passes = [&](int zb) { return nbits > zb ? (nbits - zb + ZG - 1) / ZG : 0; };
+    const int zb = passes(10) == passes(ZB_MAX) ? 10 : passes(11) == passes(ZB_MAX) ? 11 : ZB_MAX;
+    const int nb = nbits < zb ? nbits : zb;
+    const dim3 grid((unsigned)(1ll << (nbits - nb)));
+    if (zb == 10)
+        hipLaunchKernelGGL((tor_zeta_lds<10, 256>), grid, dim3(256), 0, s, t, g, nb);
+    else if (zb == 11)
+        hipLaunchKernelGGL((tor_zeta_lds<11, 512>), grid, dim3(512), 0, s, t, g, nb);
+    else
+        hipLaunchKernelGGL((tor_zeta_lds<12, 1024>), grid, dim3(1024), 0, s, t, g, nb);
     hipError_t e = hipGetLastError();
     for (int b0 = nb; e == hipSuccess && b0 < nbits; b0 += ZG) {
         const int w = nbits - b0 < ZG ? nbits - b0 : ZG;

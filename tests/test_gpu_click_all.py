@@ -60,7 +60,7 @@ def exact_zeta(t):
     return a
 
 
-@pytest.mark.parametrize("nbits", [1, 4, 10, 11, 13, 16])
+@pytest.mark.parametrize("nbits", [1, 4, 10, 12, 13, 16, 17, 20])
 def test_subset_sum_transform_is_exact(ctx, nbits):
     rng = np.random.default_rng(nbits)
     n = 1 << nbits
