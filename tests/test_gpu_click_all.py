@@ -88,10 +88,12 @@ def test_whole_state_equals_eval_bitwise(ctx, M):
     assert r.sum_abs == e.sum_abs
 
 
-def test_every_pattern_against_click_probs(ctx):
-    M = 12
+@pytest.mark.parametrize("M", [12, 13])
+def test_every_pattern_against_click_probs(ctx, M):
+    """M = 12 takes the transform in LDS alone, M = 13 a register pass after
+    it."""
     O = state(M, 52)
-    say("case click_all vs click_probs M=12 (4096 patterns)")
+    say(f"case click_all vs click_probs M={M} ({1 << M} patterns)")
     probs, (th, tl), _ = ctx.click_all(O, tor=True)
     p2, res = ctx.click_probs(O, range(1 << M))
     assert all(r.status == 0 for r in res)
