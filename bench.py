@@ -205,14 +205,21 @@ def precision_report(stream, ws):
                          "dd_rel_error": abs(dq) / abs(want), "dd_err_est": rq.err_est,
                          "dd_bound_rel": 24 * math.hypot(2.0 ** -100, unit[g["oracle_mode"]]) * sq / abs(want),
                          "dd_kernel_ms": rq.device_ms})
+    # one group per size and reference ("24" alone, or "24-ld" and "24-quad"
+    # where a size has references of both kinds)
+    refs = {}
+    for row in rows:
+        refs.setdefault(row["n"], set()).add(row["reference"])
     by_n = {}
     for row in rows:
-        by_n.setdefault(row["n"], []).append(row)
-    summary = {str(k): {"cases": len(v), "reference": v[0]["reference"],
+        key = str(row["n"]) if len(refs[row["n"]]) == 1 else f"{row['n']}-{row['reference']}"
+        by_n.setdefault(key, []).append(row)
+    summary = {k: {"cases": len(v), "reference": v[0]["reference"],
                         "fp64_rel_error_max": max(x["fp64_rel_error"] for x in v),
                         "fp64_rel_error_median": float(np.median([x["fp64_rel_error"] for x in v])),
                         "dd_rel_error_max": max(x["dd_rel_error"] for x in v),
-                        "R_max": max(x["R"] for x in v)} for k, v in sorted(by_n.items())}
+                        "R_max": max(x["R"] for x in v)}
+               for k, v in sorted(by_n.items(), key=lambda kv: (int(kv[0].split("-")[0]), kv[0]))}
     return {"source": GOLDEN, "summary_by_n": summary, "cases": rows}
 
 

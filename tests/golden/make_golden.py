@@ -6,10 +6,11 @@ here comes from the GPU path.  Each entry records the generator arguments,
 the SHA-256 of the O bytes, the oracle mode, its double-double result, the
 sum of |t| and the sum of t^2.
 
-Modes: "quad" (__float128 throughout) where it finishes in minutes (n <= 20),
-"f64" (the FP64 floor the GPU's FP64 path shares), and "ld" (x87 extended,
-64-bit significand) as the accurate reference at n = 24 and 30, where
-__float128 would take days.
+Modes: "quad" (__float128 throughout) where it finishes in minutes (n <= 20)
+and for one n = 24 seed (about 40 minutes on 8 threads), "f64" (the FP64
+floor the GPU's FP64 path shares), and "ld" (x87 extended, 64-bit
+significand) as the accurate reference at n = 24 and 30, where __float128
+would take hours to days.
 
     python tests/golden/make_golden.py [--only NAME ...] [--threads T] [--out FILE]
 """
@@ -38,6 +39,9 @@ for s in range(8):
     CASES[f"pair_n24_s{s}"] = (24, s, 0.5, 1.0, 0.7, "f64")
 for s in range(8):
     CASES[f"pair_n24_s{s}_ld"] = (24, s, 0.5, 1.0, 0.7, "ld")
+# the hardest n = 24 seed (R = 1.2e15) once more in __float128: the extended
+# reference's own floor there is about 1e-8 relative
+CASES["pair_n24_s3_q"] = (24, 3, 0.5, 1.0, 0.7, "quad")
 CASES["prec_n30_s0"] = (30, 0, 0.3, 1.2, 0.9, "f64")
 CASES["prec_n30_s0_ld"] = (30, 0, 0.3, 1.2, 0.9, "ld")
 
