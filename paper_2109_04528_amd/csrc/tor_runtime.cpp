@@ -185,6 +185,13 @@ int choose_k(const tor_ctx *ctx, int N, int path)
     // against 10.9 at 13); double-double n = 30 k = 14 (24.1 against 24.9).
     const int lo = path == PATH_REAL ? g : g - 1;
     const int hi = path == PATH_REAL ? g + 2 : g + 3;
+    // real path, LA from g - 1 to g + 2 (n = 21..24 on the 2048-wave grid):
+    // the grid cannot be filled with roots of many leaves, and one leaf per
+    // root leaves each wave's root set-up unshared; roots of two to eight
+    // leaves at g - 1 measured fastest (n = 22: 0.052 ms against 0.079 at
+    // k = g = LA, n = 23: 0.069 against 0.078)
+    if (path == PATH_REAL && LA >= g - 1 && LA <= g + 2)
+        return std::min(LA - 1, g - 1);
     return std::min(LA, std::max(lo, std::min(hi, LA - 6)));
 }
 
