@@ -176,10 +176,11 @@ int choose_k(const tor_ctx *ctx, int N, int path)
         ++g;
     // Every root first recomputes its k eliminations in global memory, which a
     // short root does not amortise, so no more roots than leave each about
-    // 64 tier-A leaves (k <= LA - 6), within [g, g + 2] on the real path (one
-    // to four roots per wave of the 2^g grid) and [g - 1, g + 3] on the
-    // 16-byte paths, whose leaves are a quarter the size and whose launches
-    // end more evenly with more roots.  The autotuner's picks this follows:
+    // 64 tier-A leaves on the real path (k <= LA - 6) and 32 on the 16-byte
+    // paths (k <= LA - 5), within [g, g + 2] on the real path (one to four
+    // roots per wave of the 2^g grid) and [g - 1, g + 3] on the 16-byte
+    // paths, whose leaves are a quarter the size and whose launches end more
+    // evenly with more roots.  The autotuner's picks this follows:
     // real n = 26 k = 11 (0.26 ms against 0.34 at k = 13), n = 30 k = 13;
     // complex n = 24 k = 10 (0.26 against 0.33 at 13), n = 30 k = 14 (10.1
     // against 10.9 at 13); double-double n = 30 k = 14 (24.1 against 24.9).
@@ -192,7 +193,11 @@ int choose_k(const tor_ctx *ctx, int N, int path)
     // k = g = LA, n = 23: 0.069 against 0.078)
     if (path == PATH_REAL && LA >= g - 1 && LA <= g + 2)
         return std::min(LA - 1, g - 1);
-    return std::min(LA, std::max(lo, std::min(hi, LA - 6)));
+    // the 16-byte paths' leaves are a quarter the size: 32 leaves per root
+    // (n = 26: complex 0.73 ms against 0.83 with 64, double-double 1.85
+    // against 2.07; n = 27 double-double 3.23 against 3.64)
+    const int leaves = path == PATH_REAL ? 6 : 5;
+    return std::min(LA, std::max(lo, std::min(hi, LA - leaves)));
 }
 
 int ensure_ws(tor_ctx *ctx, size_t bytes)
