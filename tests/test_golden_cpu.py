@@ -48,3 +48,21 @@ def test_fp64_oracle_within_its_floor_of_extended():
     # and the model is not vacuous: the FP64 oracle does carry an error of
     # the order of u sqrt(sum t^2)
     assert worst > 0.3
+
+
+def test_extended_oracle_within_its_floor_of_quad():
+    """The x87 extended reference of an n = 24 matrix against the __float128
+    one of the same matrix: they differ by about the extended rounding of
+    each term, 2^-64 sqrt(sum t^2), which is the floor the n = 24 and n = 30
+    extended references carry."""
+    pairs = [n for n in sorted(GOLD) if n.endswith("_q") and n[:-2] + "_ld" in GOLD]
+    assert pairs
+    for name in pairs:
+        q, e = GOLD[name], GOLD[name[:-2] + "_ld"]
+        assert q["sha256"] == e["sha256"] and q["oracle_mode"] == "quad" and e["oracle_mode"] == "ld"
+        vq, ve = q["tor_hi"] + q["tor_lo"], e["tor_hi"] + e["tor_lo"]
+        tol = bounds.sum_bound(q["sum_sq"], bounds.ULD, bounds.UQ)
+        assert abs(ve - vq) <= tol, (name, ve, vq, tol)
+        # not vacuous: the extended value does carry its own rounding
+        assert abs(ve - vq) >= 0.05 * bounds.ULD * math.sqrt(q["sum_sq"])
+        assert abs(q["sum_abs"] - e["sum_abs"]) <= 1e-15 * q["sum_abs"]
