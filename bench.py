@@ -501,7 +501,7 @@ def main():
                                         "device_ms": rb.device_ms, "sum_of_probs": float(torch.sum(pb).item()),
                                         "outputs": "device"}
                     del pb
-            except TorError as err:
+            except (TorError, RuntimeError) as err:  # the library's or torch's allocation
                 click_all["M32"] = {"error": str(err)}
         print("bench: every click pattern done", file=sys.stderr, flush=True)
 
