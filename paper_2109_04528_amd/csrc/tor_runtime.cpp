@@ -19,6 +19,7 @@
 // remaining work first, so requests that arrive while others run join the
 // next launch instead of waiting for the longest one to finish.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <chrono>
@@ -74,7 +75,8 @@ struct Request {
     char *dC = nullptr;
     double *dSlots = nullptr;
     float device_ms = 0.f;
-    int launches = 0;  // serving launches that ran part of it
+    int launches = 0;       // serving launches that ran part of it
+    bool in_flight = false;  // has roots in a serving launch still running
 };
 
 // Serving policy (tor_serve_config).  Written under the serving lock; the
@@ -83,6 +85,21 @@ struct ServeCfg {
     long long chunk_subsets = 1ll << 29;   // work per chunked serving launch
     long long express_subsets = 1ll << 24; // requests this small run ahead, whole (0: none)
     double oldest_share = 0.5;             // of a chunk, guaranteed to the oldest request
+};
+
+// A set of launch resources of its own: serving runs its launches on two
+// of these.  `stream` is limited by a CU mask to `cus` CUs (0: no mask could
+// be set, and it runs on every CU); `side`, when made, has the same mask
+// (serving stages requests there, beside the lane's launches); `wide`, when
+// made, runs on every CU; `cur` is the one the lane's current launch goes to.
+struct LaunchLane {
+    hipStream_t stream = nullptr, side = nullptr, wide = nullptr, cur = nullptr;
+    int cus = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    char *hup = nullptr, *hdown = nullptr;
+    size_t hup_bytes = 0, hdown_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
 };
 
 struct TuneEntry {
@@ -131,6 +148,8 @@ struct tor_ctx {
     char *pool = nullptr;
     size_t pool_bytes = 256ull << 20;
     std::map<size_t, size_t> pool_free;  // offset -> length
+    LaunchLane chunk;  // serving's chunked launches (created on first use)
+    LaunchLane quick;  // serving's express launches (created on first use)
 };
 
 namespace {
@@ -368,8 +387,10 @@ StageLayout stage_layout(const std::vector<StageIn> &in, bool on_device, unsigne
 }
 
 int stage_enqueue(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, unsigned sflags, int min_cplx,
-                  size_t base, std::vector<Mat> &mats, size_t *end, size_t *down_end)
+                  size_t base, std::vector<Mat> &mats, size_t *end, size_t *down_end, hipStream_t stream = nullptr)
 {
+    if (!stream)
+        stream = ctx->stream;
     const int count = (int)in.size();
     mats.assign(count, Mat{});
     *end = base;
@@ -454,11 +475,11 @@ int stage_enqueue(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, 
     hipError_t e = hipSetDevice(ctx->device);
     // the infos' bytes are part of the copy (their values do not matter)
     if (e == hipSuccess)
-        e = hipMemcpyAsync(dbase, h, up_bytes, hipMemcpyHostToDevice, ctx->stream);
+        e = hipMemcpyAsync(dbase, h, up_bytes, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
-        e = launch_stage((const StageDesc *)dbase, count, ctx->stream);
+        e = launch_stage((const StageDesc *)dbase, count, stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(ctx->hdown, dbase + b_desc, sizeof(StageInfo) * count, hipMemcpyDeviceToHost, ctx->stream);
+        e = hipMemcpyAsync(ctx->hdown, dbase + b_desc, sizeof(StageInfo) * count, hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess)
         return hip_status(e);
     *end = base + L.total;
@@ -478,15 +499,15 @@ void stage_collect(const tor_ctx *ctx, std::vector<Mat> &mats)
     }
 }
 
-// Stage, wait, collect.
+// Stage, wait, collect (on the context's stream unless one is given).
 int stage_sync(tor_ctx *ctx, const std::vector<StageIn> &in, bool on_device, unsigned sflags, int min_cplx,
-               size_t base, std::vector<Mat> &mats, size_t *end)
+               size_t base, std::vector<Mat> &mats, size_t *end, hipStream_t stream = nullptr)
 {
     size_t down_end = 0;
-    int rc = stage_enqueue(ctx, in, on_device, sflags, min_cplx, base, mats, end, &down_end);
+    int rc = stage_enqueue(ctx, in, on_device, sflags, min_cplx, base, mats, end, &down_end, stream);
     if (rc != TOR_OK || in.empty())
         return rc;
-    hipError_t e = hipStreamSynchronize(ctx->stream);
+    hipError_t e = hipStreamSynchronize(stream ? stream : ctx->stream);
     if (e != hipSuccess)
         return hip_status(e);
     stage_collect(ctx, mats);
@@ -522,6 +543,29 @@ LaunchLayout launch_layout(int count, int nred, long long stride)
     return L;
 }
 
+// Workspace of a launch lane: grown (never shrunk) between launches, when
+// nothing is in flight on its stream.
+int lane_ws(LaunchLane &L, size_t bytes)
+{
+    if (bytes <= L.ws_bytes)
+        return TOR_OK;
+    if (L.ws) {
+        for (hipStream_t st : {L.stream, L.side, L.wide})
+            if (st)
+                (void)hipStreamSynchronize(st);
+        (void)hipFree(L.ws);
+        L.ws = nullptr;
+        L.ws_bytes = 0;
+    }
+    const size_t want = align_up(bytes + (bytes >> 3), 1 << 20);
+    if (hipMalloc((void **)&L.ws, want) != hipSuccess) {
+        L.ws = nullptr;
+        return TOR_E_NOMEM;
+    }
+    L.ws_bytes = want;
+    return TOR_OK;
+}
+
 // One persistent launch over the root ranges in descs (C, slots, N, k,
 // root_begin, nroots filled in), followed by the reduction of the matrices
 // listed in reduce (indices into descs, or none), into results (4 doubles
@@ -529,9 +573,12 @@ LaunchLayout launch_layout(int count, int nred, long long stride)
 // results and the per-wave tier-A stacks.  When ws_off > 0 the bytes below it
 // hold data the descriptors point to, and the caller has already sized the
 // workspace (a reallocation here would move that data).
+// With a lane, the launch goes to the lane's stream, workspace and pinned
+// buffers, and the call returns once it is enqueued: the lane's done event
+// follows the read-back of the results, which lane_collect then takes.
 int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const std::vector<int> &reduce,
                size_t ws_off, int grid, std::vector<double> *results, float *ms, long long fail_item1 = 0,
-               double *terms = nullptr)
+               double *terms = nullptr, LaunchLane *lane = nullptr)
 {
     const int count = (int)descs.size();
     long long total = 0, stack = 0;
@@ -546,12 +593,18 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     const int nred = (int)red.size();
     const LaunchLayout Lo = launch_layout(count, nred, stack);
     const size_t need = ws_off + Lo.total(grid);
-    if (ws_off > 0 && need > ctx->ws_bytes)
+    if (ws_off > 0 && need > (lane ? lane->ws_bytes : ctx->ws_bytes))
         return TOR_E_NOMEM;  // the caller sizes the workspace first
-    int rc = ensure_ws(ctx, need);
+    int rc = lane ? lane_ws(*lane, need) : ensure_ws(ctx, need);
     if (rc != TOR_OK)
         return rc;
-    char *dProbs = ctx->ws + ws_off;
+    const hipStream_t stream = lane ? lane->cur : ctx->stream;
+    char *&hup = lane ? lane->hup : ctx->hup;
+    char *&hdown = lane ? lane->hdown : ctx->hdown;
+    size_t &hup_bytes = lane ? lane->hup_bytes : ctx->hup_bytes;
+    size_t &hdown_bytes = lane ? lane->hdown_bytes : ctx->hdown_bytes;
+    const hipEvent_t ev0 = lane ? lane->ev0 : ctx->ev0, ev1 = lane ? lane->ev1 : ctx->ev1;
+    char *dProbs = (lane ? lane->ws : ctx->ws) + ws_off;
     char *dRed = dProbs + Lo.b_probs;
     unsigned long long *dCounter = (unsigned long long *)(dRed + Lo.b_red);
     double *dRes = (double *)((char *)dCounter + Lo.b_counter);
@@ -561,19 +614,19 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     // the zeroed queue counter after them: one copy from pinned memory (the
     // previous use of the buffer has been synchronised)
     const size_t up = Lo.b_probs + Lo.b_red + sizeof(unsigned long long);
-    rc = pin_grow(ctx->hup, ctx->hup_bytes, up);
+    rc = pin_grow(hup, hup_bytes, up);
     if (rc == TOR_OK)
-        rc = pin_grow(ctx->hdown, ctx->hdown_bytes, sizeof(double) * 4 * (size_t)std::max(nred, 1));
+        rc = pin_grow(hdown, hdown_bytes, sizeof(double) * 4 * (size_t)std::max(nred, 1));
     if (rc != TOR_OK)
         return rc;
-    std::memset(ctx->hup, 0, up);
-    std::memcpy(ctx->hup, descs.data(), sizeof(ProblemDesc) * count);
+    std::memset(hup, 0, up);
+    std::memcpy(hup, descs.data(), sizeof(ProblemDesc) * count);
     if (nred)
-        std::memcpy(ctx->hup + Lo.b_probs, red.data(), sizeof(ProblemDesc) * nred);
+        std::memcpy(hup + Lo.b_probs, red.data(), sizeof(ProblemDesc) * nred);
 
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(dProbs, ctx->hup, up, hipMemcpyHostToDevice, ctx->stream);
+        e = hipMemcpyAsync(dProbs, hup, up, hipMemcpyHostToDevice, stream);
     MainParams mp{};
     mp.probs = (const ProblemDesc *)dProbs;
     mp.nprob = count;
@@ -586,29 +639,102 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     // the double-double factor always sums in double-double
     const bool dd = ctx->opt.accum != TOR_ACCUM_FP64 || path == PATH_QUAD;
     if (e == hipSuccess)
-        e = hipEventRecord(ctx->ev0, ctx->stream);
+        e = hipEventRecord(ev0, stream);
     // no more persistent waves than queue items: a launch of few roots (a
     // small matrix) does not pay for starting the whole grid
     if (e == hipSuccess && total > 0)
-        e = terms ? launch_main_store(mp, (int)std::min<long long>(grid, total), ctx->stream)
-                  : launch_main(path, dd, mp, (int)std::min<long long>(grid, total), ctx->stream);
+        e = terms ? launch_main_store(mp, (int)std::min<long long>(grid, total), stream)
+                  : launch_main(path, dd, mp, (int)std::min<long long>(grid, total), stream);
     if (e == hipSuccess)
-        e = hipEventRecord(ctx->ev1, ctx->stream);  // device_ms: the main kernel alone
-    const double *hres = (const double *)ctx->hdown;
+        e = hipEventRecord(ev1, stream);  // device_ms: the main kernel alone
+    const double *hres = (const double *)hdown;
     if (e == hipSuccess && nred > 0) {
-        e = launch_reduce((const ProblemDesc *)dRed, nred, dRes, dd, ctx->stream);
+        e = launch_reduce((const ProblemDesc *)dRed, nred, dRes, dd, stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(ctx->hdown, dRes, sizeof(double) * 4 * nred, hipMemcpyDeviceToHost, ctx->stream);
+            e = hipMemcpyAsync(hdown, dRes, sizeof(double) * 4 * nred, hipMemcpyDeviceToHost, stream);
+    }
+    if (lane) {
+        if (e == hipSuccess)
+            e = hipEventRecord(lane->done, stream);
+        if (e != hipSuccess)
+            (void)hipStreamSynchronize(stream);  // nothing still reads the pinned buffers
+        return hip_status(e);
     }
     if (e == hipSuccess)
-        e = hipStreamSynchronize(ctx->stream);
+        e = hipStreamSynchronize(stream);
     if (e != hipSuccess)
         return hip_status(e);
     if (ms)
-        (void)hipEventElapsedTime(ms, ctx->ev0, ctx->ev1);
+        (void)hipEventElapsedTime(ms, ev0, ev1);
     if (results)
         results->assign(hres, hres + 4 * (size_t)nred);
     return TOR_OK;
+}
+
+// Results (4 doubles per reduced matrix) and main-kernel time of a lane's
+// launch, once its done event has been reached.
+void lane_collect(const LaunchLane &L, int nred, std::vector<double> &results, float *ms)
+{
+    if (ms)
+        (void)hipEventElapsedTime(ms, L.ev0, L.ev1);
+    const double *h = (const double *)L.hdown;
+    results.assign(h, h + 4 * (size_t)nred);
+}
+
+void lane_close(LaunchLane &L)
+{
+    for (hipStream_t st : {L.stream, L.side, L.wide})
+        if (st)
+            (void)hipStreamSynchronize(st);
+    if (L.ws)
+        (void)hipFree(L.ws);
+    if (L.hup)
+        (void)hipHostFree(L.hup);
+    if (L.hdown)
+        (void)hipHostFree(L.hdown);
+    for (hipEvent_t ev : {L.ev0, L.ev1, L.done})
+        if (ev)
+            (void)hipEventDestroy(ev);
+    for (hipStream_t st : {L.stream, L.side, L.wide})
+        if (st)
+            (void)hipStreamDestroy(st);
+    L = LaunchLane{};
+}
+
+// Streams and events of a lane, made on its first use: `stream` limited to
+// the ncu CUs from bit `first` of the device's CU mask on (the runtime spreads
+// the mask's bits over the dies), a plain stream if the mask is refused;
+// with `side` a second stream of the same mask (only if the mask is set),
+// with `wide` a plain stream beside them.  Every stream has the default
+// priority.
+int lane_open(LaunchLane &L, int num_cu, int first, int ncu, bool side, bool wide)
+{
+    if (L.stream)
+        return TOR_OK;
+    uint32_t mask[32] = {};
+    const uint32_t words = (uint32_t)((num_cu + 31) / 32);
+    hipError_t e = hipErrorInvalidValue;
+    if (ncu > 0 && first >= 0 && first + ncu <= num_cu && num_cu <= 1024) {
+        for (int c = first; c < first + ncu; c++)
+            mask[c / 32] |= 1u << (c % 32);
+        e = hipExtStreamCreateWithCUMask(&L.stream, words, mask);
+    }
+    L.cus = e == hipSuccess ? ncu : 0;
+    if (e != hipSuccess && hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess)
+        L.stream = nullptr;
+    bool ok = L.stream != nullptr;
+    if (ok && side && L.cus > 0)
+        ok = hipExtStreamCreateWithCUMask(&L.side, words, mask) == hipSuccess;
+    if (ok && wide)
+        ok = hipStreamCreateWithFlags(&L.wide, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreate(&L.ev0) == hipSuccess && hipEventCreate(&L.ev1) == hipSuccess &&
+         hipEventCreateWithFlags(&L.done, hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+        L.cur = L.stream;
+        return TOR_OK;
+    }
+    lane_close(L);
+    return TOR_E_DEVICE;
 }
 
 // Synchronous path: all roots of every staged matrix in one launch, matrices
@@ -950,28 +1076,82 @@ size_t request_bytes(int n, unsigned sflags)
     return request_form_bytes(n, sflags) + slots;
 }
 
-// One scheduling round for one path: pick root ranges for a launch, run it,
-// retire the finished requests.  With express set, the launch takes only the
-// requests whose remaining work is at most cfg.express_subsets, whole.
-// Called with ctx->mu held.
+// CUs that the chunked serving launches leave to the express launches beside
+// them (4.7 % of a 256-CU part).  The express launches there fill each CU
+// to half the waves it holds, so that staging (a 1024-thread workgroup with
+// 52 KB of LDS, on a stream of the same CU mask) finds room beside them and
+// never waits for a chunk.
+constexpr int SERVE_QUICK_CUS = 12;
+
+// A serving launch in flight on one of the context's serving lanes.
+struct ServeLaunch {
+    bool busy = false;
+    int path = PATH_REAL;
+    std::vector<Request *> used;  // one entry per root range (a request may hold two)
+    std::vector<int> red;         // entries of used whose request the launch completes
+};
+
+// Book a finished serving launch (rc its status; res 4 doubles per entry of
+// red): every request in it counts the launch once and takes its share of
+// the kernel time; the ones it completed, or all of them on failure, move
+// to finished.
+void retire_launch(int path, const std::vector<Request *> &used, const std::vector<int> &red, int rc,
+                   const std::vector<double> &res, float ms, std::vector<Request *> &finished)
+{
+    std::vector<Request *> uniq;
+    for (Request *r : used)
+        if (std::find(uniq.begin(), uniq.end(), r) == uniq.end())
+            uniq.push_back(r);
+    for (Request *r : uniq) {
+        r->in_flight = false;
+        r->device_ms += ms / (float)uniq.size();
+        ++r->launches;
+    }
+    if (rc != TOR_OK) {
+        for (Request *r : uniq) {
+            r->res = tor_result{};
+            r->res.status = rc;
+            r->next_root = r->nroots;
+            finished.push_back(r);
+        }
+        return;
+    }
+    for (size_t j = 0; j < red.size(); j++) {
+        Request *r = used[red[j]];
+        fill_result(r->st, path, &res[4 * j], r->device_ms, &r->res);
+        r->res.launches = r->launches;
+        finished.push_back(r);
+    }
+}
+
+enum { TAKE_SMALL, TAKE_LARGE, TAKE_ANY };  // which requests a serving round takes
+
+// One scheduling round for one path: pick root ranges of about `budget`
+// subsets, the oldest request's share first, then the requests with the
+// least remaining work (the small ones whole), and enqueue a launch of them on
+// lane, with the tuned waves per CU of their largest size (at most wpc_max
+// when positive) on `cus` CUs; rec records it.  TAKE_SMALL takes only the requests whose remaining work
+// is at most cfg.express_subsets, TAKE_LARGE only the others.  Requests
+// with roots in a launch in flight are left out.  Called with ctx->mu held.
 int serve_round(tor_ctx *ctx, const ServeCfg &cfg, int path, std::vector<Request *> &active,
-                std::vector<Request *> &finished, bool express)
+                std::vector<Request *> &finished, int take_kind, long long budget, int cus, int wpc_max,
+                LaunchLane &lane, ServeLaunch &rec)
 {
     std::vector<Request *> cand;
-    for (Request *r : active)
-        if (r->path == path && r->next_root < r->nroots &&
-            (!express || (r->nroots - r->next_root) * r->root_work <= cfg.express_subsets))
+    for (Request *r : active) {
+        if (r->path != path || r->in_flight || r->next_root >= r->nroots)
+            continue;
+        const bool small = (r->nroots - r->next_root) * r->root_work <= cfg.express_subsets;
+        if (take_kind == TAKE_ANY || small == (take_kind == TAKE_SMALL))
             cand.push_back(r);
+    }
     if (cand.empty())
         return TOR_OK;
-    // the oldest request always gets its share of the budget (oldest_share);
-    // the rest goes to the requests with the least remaining work
     Request *oldest = *std::min_element(cand.begin(), cand.end(),
                                         [](Request *a, Request *b) { return a->ticket < b->ticket; });
     std::stable_sort(cand.begin(), cand.end(), [](Request *a, Request *b) {
         return (a->nroots - a->next_root) * a->root_work < (b->nroots - b->next_root) * b->root_work;
     });
-    long long budget = express ? (long long)1 << 62 : cfg.chunk_subsets;
     std::vector<ProblemDesc> descs;
     std::vector<Request *> used;
     auto take = [&](Request *r, long long share) {
@@ -989,50 +1169,86 @@ int serve_round(tor_ctx *ctx, const ServeCfg &cfg, int path, std::vector<Request
         r->next_root += n;
         budget -= n * r->root_work;
     };
-    take(oldest, (long long)(cfg.oldest_share * (double)budget));
+    // a small request is taken whole or not at all, so that it takes one
+    // launch; a large one's share may end anywhere
+    auto left = [](const Request *r) { return (r->nroots - r->next_root) * r->root_work; };
+    auto small = [&](const Request *r) { return left(r) <= cfg.express_subsets; };
+    take(oldest, small(oldest) ? left(oldest) : (long long)(cfg.oldest_share * (double)budget));
     for (Request *r : cand) {
         if (budget <= 0)
             break;
-        if (r->next_root < r->nroots)
+        if (r->next_root >= r->nroots)
+            continue;
+        if (!small(r))
             take(r, budget);
+        else if (left(r) <= budget)
+            take(r, left(r));
     }
     int Nmax = 0;
     for (auto &d : descs)
         Nmax = std::max(Nmax, d.N);
+    int wpc = launch_grid(ctx, path, Nmax) / ctx->num_cu;
+    if (wpc_max > 0)
+        wpc = std::min(wpc, wpc_max);
+    const int grid = wpc * cus;
     // reduce the requests that this launch completes
     std::vector<int> red;
     for (size_t i = 0; i < used.size(); i++)
         if (used[i]->next_root == used[i]->nroots && std::find(used.begin(), used.begin() + i, used[i]) == used.begin() + i)
             red.push_back((int)i);
-    std::vector<double> res;
-    float ms = 0.f;
-    int rc = run_launch(ctx, path, descs, red, 0, launch_grid(ctx, path, Nmax), &res, &ms);
-    for (Request *r : used) {
-        r->device_ms += ms / (float)used.size();
-        ++r->launches;
-    }
+    const int rc = run_launch(ctx, path, descs, red, 0, grid, nullptr, nullptr, 0, nullptr, &lane);
     if (rc != TOR_OK) {
-        for (Request *r : used) {
-            r->res = tor_result{};
-            r->res.status = rc;
-            r->next_root = r->nroots;
-            if (std::find(finished.begin(), finished.end(), r) == finished.end())
-                finished.push_back(r);
-        }
+        retire_launch(path, used, red, rc, {}, 0.f, finished);
         return rc;
     }
-    for (size_t j = 0; j < red.size(); j++) {
-        Request *r = used[red[j]];
-        fill_result(r->st, path, &res[4 * j], r->device_ms, &r->res);
-        r->res.launches = r->launches;
-        finished.push_back(r);
-    }
+    for (Request *r : used)
+        r->in_flight = true;
+    rec.busy = true;
+    rec.path = path;
+    rec.used = std::move(used);
+    rec.red = std::move(red);
     return TOR_OK;
 }
 
+// Retire a serving launch if its lane's done event has been reached (or the
+// query failed).  Called with ctx->mu held.
+void poll_launch(const LaunchLane &lane, ServeLaunch &rec, std::vector<Request *> &finished)
+{
+    if (!rec.busy)
+        return;
+    const hipError_t q = hipEventQuery(lane.done);
+    if (q == hipErrorNotReady)
+        return;
+    std::vector<double> res;
+    float ms = 0.f;
+    const int rc = hip_status(q);
+    if (rc == TOR_OK)
+        lane_collect(lane, (int)rec.red.size(), res, &ms);
+    retire_launch(rec.path, rec.used, rec.red, rc, res, ms, finished);
+    rec = ServeLaunch{};
+}
+
+// The scheduler.  Two launch lanes, each with at most one launch in flight:
+// the chunk lane runs chunked launches of at most cfg.chunk_subsets on all
+// CUs but SERVE_QUICK_CUS of them; the quick lane runs express launches of
+// small requests, on those SERVE_QUICK_CUS CUs while a chunk is in flight
+// (half full, with about as much work as they do in a chunk's time), on the
+// whole device otherwise.  Staging runs on those CUs too while a chunk is in
+// flight, on the context's stream otherwise.
+// Each round retires the launches that have ended, enqueues the next chunk,
+// stages the newly admitted requests, enqueues an express launch, and
+// publishes the finished requests; while launches are in flight it polls
+// their events.  A chunk takes the requests too large for express launches,
+// and small ones only while the express lane is busy.  So a small request
+// waits for neither the chunk in flight nor a large request: only for the
+// express launch before it.
 void serve_loop(tor_ctx *ctx)
 {
     std::vector<Request *> active;
+    ServeLaunch chunk, quick;
+    int next_chunk = 0, next_quick = 0;  // each lane takes the paths in turn
+    static const int kPaths[NPATH] = {PATH_REAL, PATH_CPLX, PATH_QUAD};
+    (void)prctl(PR_SET_TIMERSLACK, 1000ul, 0ul, 0ul, 0ul);  // polling sleeps of tens of microseconds
     // retire finished requests: release their pool memory and wake pollers
     auto publish = [&](std::vector<Request *> &fin) {
         if (fin.empty())
@@ -1054,9 +1270,15 @@ void serve_loop(tor_ctx *ctx)
         ServeCfg cfg;
         {
             std::unique_lock<std::mutex> lk(ctx->smu);
-            ctx->scv.wait(lk, [&] { return ctx->stop || !ctx->pending.empty() || !active.empty(); });
+            auto ready = [&] {
+                return ctx->stop || !ctx->pending.empty() || (!chunk.busy && !quick.busy && !active.empty());
+            };
+            if (chunk.busy || quick.busy)  // poll the events, waking early for new requests
+                ctx->scv.wait_for(lk, std::chrono::microseconds(20), ready);
+            else
+                ctx->scv.wait(lk, ready);
             if (ctx->stop)
-                return;
+                return;  // tor_destroy drains the serving lanes
             cfg = ctx->serve;  // this round's policy
             // admission by device footprint, in arrival order
             const unsigned sfl = stage_flags(ctx->opt.flags);
@@ -1096,6 +1318,34 @@ void serve_loop(tor_ctx *ctx)
         std::vector<Request *> finished;
         {
             std::lock_guard<std::mutex> g(ctx->mu);
+            int rc = hipSetDevice(ctx->device) == hipSuccess ? TOR_OK : TOR_E_DEVICE;
+            if (rc == TOR_OK)
+                rc = lane_open(ctx->chunk, ctx->num_cu, 0, ctx->num_cu - SERVE_QUICK_CUS, false, false);
+            if (rc == TOR_OK)
+                rc = lane_open(ctx->quick, ctx->num_cu, ctx->num_cu - SERVE_QUICK_CUS, SERVE_QUICK_CUS, true, true);
+            // express launches beside a chunk need both masks
+            const bool beside = rc == TOR_OK && ctx->chunk.cus > 0 && ctx->quick.cus > 0;
+            poll_launch(ctx->chunk, chunk, finished);
+            poll_launch(ctx->quick, quick, finished);
+            // the next chunk: the large requests, or, while the express lane
+            // is busy, any (the paths in turn)
+            auto start_chunk = [&] {
+                for (int kind : {TAKE_LARGE, TAKE_ANY}) {
+                    if (kind == TAKE_ANY && cfg.express_subsets > 0 && !quick.busy)
+                        break;
+                    for (int i = 0; i < NPATH && !chunk.busy; i++) {
+                        const int path = kPaths[(next_chunk + i) % NPATH];
+                        serve_round(ctx, cfg, path, active, finished, kind, cfg.chunk_subsets,
+                                    ctx->chunk.cus > 0 ? ctx->chunk.cus : ctx->num_cu, 0, ctx->chunk, chunk);
+                        if (chunk.busy)
+                            next_chunk = (next_chunk + i + 1) % NPATH;
+                    }
+                    if (chunk.busy)
+                        break;
+                }
+            };
+            if (rc == TOR_OK && !chunk.busy)
+                start_chunk();
             // stage the admitted requests on the device, straight into their
             // pool slots; the path and size of each are known from here on
             const unsigned sfl = stage_flags(ctx->opt.flags);
@@ -1108,7 +1358,11 @@ void serve_loop(tor_ctx *ctx)
             }
             std::vector<Mat> mats;
             size_t end = 0;
-            const int src = admit.empty() ? TOR_OK : stage_sync(ctx, in, false, sfl, CPLX_R, 0, mats, &end);
+            // on the express CUs while a chunk holds the others (an unmasked
+            // workgroup can be handed to a shader engine whose CUs the chunk
+            // fills, and wait there for the whole chunk)
+            const hipStream_t sst = chunk.busy && ctx->quick.side ? ctx->quick.side : ctx->stream;
+            const int src = admit.empty() ? TOR_OK : stage_sync(ctx, in, false, sfl, CPLX_R, 0, mats, &end, sst);
             for (size_t j = 0; j < admit.size(); j++) {
                 Request *r = admit[j];
                 const int st = src != TOR_OK ? src : mats[j].status;
@@ -1129,15 +1383,34 @@ void serve_loop(tor_ctx *ctx)
                 std::vector<double>().swap(r->raw);
                 active.push_back(r);
             }
-            // small requests first, in launches of their own, and their
-            // results published before the chunked launch starts, so that
-            // they wait for at most one large launch
-            if (cfg.express_subsets > 0)
-                for (int path : {PATH_REAL, PATH_CPLX, PATH_QUAD})
-                    serve_round(ctx, cfg, path, active, finished, true);
-            publish(finished);
-            for (int path : {PATH_REAL, PATH_CPLX, PATH_QUAD})
-                serve_round(ctx, cfg, path, active, finished, false);
+            if (rc != TOR_OK) {
+                // no serving lanes: every admitted request fails
+                for (Request *r : active)
+                    if (!r->in_flight) {
+                        r->res = tor_result{};
+                        r->res.status = rc;
+                        finished.push_back(r);
+                    }
+            } else {
+                // small requests: beside the chunk in flight on the express
+                // lane's own CUs, with about the work those CUs do in a
+                // chunk's time, or on the whole device when no chunk runs
+                if (cfg.express_subsets > 0 && !quick.busy && (!chunk.busy || beside)) {
+                    ctx->quick.cur = chunk.busy ? ctx->quick.stream : ctx->quick.wide;
+                    const int cus = chunk.busy ? ctx->quick.cus : ctx->num_cu;
+                    const long long budget =
+                        chunk.busy ? std::max(1ll, cfg.chunk_subsets / ctx->num_cu * cus) : (1ll << 62);
+                    for (int i = 0; i < NPATH && !quick.busy; i++) {
+                        const int path = kPaths[(next_quick + i) % NPATH];
+                        serve_round(ctx, cfg, path, active, finished, TAKE_SMALL, budget, cus,
+                                    chunk.busy ? std::max(1, ctx->fit[path] / 2) : 0, ctx->quick, quick);
+                        if (quick.busy)
+                            next_quick = (next_quick + i + 1) % NPATH;
+                    }
+                }
+                if (!chunk.busy)
+                    start_chunk();
+            }
         }
         publish(finished);
     }
@@ -1494,6 +1767,8 @@ void tor_destroy(tor_ctx *ctx)
         (void)hipSetDevice(ctx->device);
         if (ctx->stream)
             (void)hipStreamSynchronize(ctx->stream);
+        lane_close(ctx->chunk);  // each waits for a serving launch still in flight
+        lane_close(ctx->quick);
         if (ctx->own_ws && ctx->ws)
             (void)hipFree(ctx->ws);
         if (ctx->pool)

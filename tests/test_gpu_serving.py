@@ -132,7 +132,8 @@ def test_chunking_forced_at_small_n():
 
 def test_express_and_chunked_in_one_stream():
     """Default express threshold with a small chunk: small requests run whole
-    ahead of each chunked launch, large ones are chunked; all equal alone."""
+    in express launches (beside the chunked ones), large ones are chunked;
+    all equal alone."""
     from paper_2109_04528_amd import Context
     state = gen.random_O(40, 7002, 0.5, 1.0, 0.6)
     rng = np.random.default_rng(23)
