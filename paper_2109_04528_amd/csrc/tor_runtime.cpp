@@ -76,7 +76,9 @@ struct Request {
     double *dSlots = nullptr;
     float device_ms = 0.f;
     int launches = 0;       // serving launches that ran part of it
-    bool in_flight = false;  // has roots in a serving launch still running
+    int flights = 0;            // serving launches in flight that hold some of its roots
+    bool quick_flight = false;  // one of them is an express launch
+    bool failed = false;        // a launch of it failed: retired with that status
 };
 
 // Serving policy (tor_serve_config).  Written under the serving lock; the
@@ -92,14 +94,19 @@ struct ServeCfg {
 // be set, and it runs on every CU); `side`, when made, has the same mask
 // (serving stages requests there, beside the lane's launches); `wide`, when
 // made, runs on every CU; `cur` is the one the lane's current launch goes to.
+// Two slots of pinned buffers and events let a second launch be queued on
+// the lane's stream behind the one running (both share the workspace, which
+// the second launch's first copy rewrites only after the first launch's
+// last copy, in stream order); `slot` is the one the next launch uses.
 struct LaunchLane {
     hipStream_t stream = nullptr, side = nullptr, wide = nullptr, cur = nullptr;
     int cus = 0;
     char *ws = nullptr;
     size_t ws_bytes = 0;
-    char *hup = nullptr, *hdown = nullptr;
-    size_t hup_bytes = 0, hdown_bytes = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
+    int slot = 0;
+    char *hup[2] = {}, *hdown[2] = {};
+    size_t hup_bytes[2] = {}, hdown_bytes[2] = {};
+    hipEvent_t ev0[2] = {}, ev1[2] = {}, done[2] = {};
 };
 
 struct TuneEntry {
@@ -573,9 +580,10 @@ int lane_ws(LaunchLane &L, size_t bytes)
 // results and the per-wave tier-A stacks.  When ws_off > 0 the bytes below it
 // hold data the descriptors point to, and the caller has already sized the
 // workspace (a reallocation here would move that data).
-// With a lane, the launch goes to the lane's stream, workspace and pinned
-// buffers, and the call returns once it is enqueued: the lane's done event
-// follows the read-back of the results, which lane_collect then takes.
+// With a lane, the launch goes to the lane's current stream, its workspace
+// and the pinned buffers of its current slot, and the call returns once it
+// is enqueued: the slot's done event follows the read-back of the results,
+// which lane_collect then takes.
 int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const std::vector<int> &reduce,
                size_t ws_off, int grid, std::vector<double> *results, float *ms, long long fail_item1 = 0,
                double *terms = nullptr, LaunchLane *lane = nullptr)
@@ -599,11 +607,12 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     if (rc != TOR_OK)
         return rc;
     const hipStream_t stream = lane ? lane->cur : ctx->stream;
-    char *&hup = lane ? lane->hup : ctx->hup;
-    char *&hdown = lane ? lane->hdown : ctx->hdown;
-    size_t &hup_bytes = lane ? lane->hup_bytes : ctx->hup_bytes;
-    size_t &hdown_bytes = lane ? lane->hdown_bytes : ctx->hdown_bytes;
-    const hipEvent_t ev0 = lane ? lane->ev0 : ctx->ev0, ev1 = lane ? lane->ev1 : ctx->ev1;
+    const int sl = lane ? lane->slot : 0;
+    char *&hup = lane ? lane->hup[sl] : ctx->hup;
+    char *&hdown = lane ? lane->hdown[sl] : ctx->hdown;
+    size_t &hup_bytes = lane ? lane->hup_bytes[sl] : ctx->hup_bytes;
+    size_t &hdown_bytes = lane ? lane->hdown_bytes[sl] : ctx->hdown_bytes;
+    const hipEvent_t ev0 = lane ? lane->ev0[sl] : ctx->ev0, ev1 = lane ? lane->ev1[sl] : ctx->ev1;
     char *dProbs = (lane ? lane->ws : ctx->ws) + ws_off;
     char *dRed = dProbs + Lo.b_probs;
     unsigned long long *dCounter = (unsigned long long *)(dRed + Lo.b_red);
@@ -655,7 +664,7 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
     }
     if (lane) {
         if (e == hipSuccess)
-            e = hipEventRecord(lane->done, stream);
+            e = hipEventRecord(lane->done[sl], stream);
         if (e != hipSuccess)
             (void)hipStreamSynchronize(stream);  // nothing still reads the pinned buffers
         return hip_status(e);
@@ -672,12 +681,12 @@ int run_launch(tor_ctx *ctx, int path, std::vector<ProblemDesc> &descs, const st
 }
 
 // Results (4 doubles per reduced matrix) and main-kernel time of a lane's
-// launch, once its done event has been reached.
-void lane_collect(const LaunchLane &L, int nred, std::vector<double> &results, float *ms)
+// launch in slot sl, once its done event has been reached.
+void lane_collect(const LaunchLane &L, int sl, int nred, std::vector<double> &results, float *ms)
 {
     if (ms)
-        (void)hipEventElapsedTime(ms, L.ev0, L.ev1);
-    const double *h = (const double *)L.hdown;
+        (void)hipEventElapsedTime(ms, L.ev0[sl], L.ev1[sl]);
+    const double *h = (const double *)L.hdown[sl];
     results.assign(h, h + 4 * (size_t)nred);
 }
 
@@ -688,13 +697,15 @@ void lane_close(LaunchLane &L)
             (void)hipStreamSynchronize(st);
     if (L.ws)
         (void)hipFree(L.ws);
-    if (L.hup)
-        (void)hipHostFree(L.hup);
-    if (L.hdown)
-        (void)hipHostFree(L.hdown);
-    for (hipEvent_t ev : {L.ev0, L.ev1, L.done})
-        if (ev)
-            (void)hipEventDestroy(ev);
+    for (int sl = 0; sl < 2; sl++) {
+        if (L.hup[sl])
+            (void)hipHostFree(L.hup[sl]);
+        if (L.hdown[sl])
+            (void)hipHostFree(L.hdown[sl]);
+        for (hipEvent_t ev : {L.ev0[sl], L.ev1[sl], L.done[sl]})
+            if (ev)
+                (void)hipEventDestroy(ev);
+    }
     for (hipStream_t st : {L.stream, L.side, L.wide})
         if (st)
             (void)hipStreamDestroy(st);
@@ -727,8 +738,9 @@ int lane_open(LaunchLane &L, int num_cu, int first, int ncu, bool side, bool wid
         ok = hipExtStreamCreateWithCUMask(&L.side, words, mask) == hipSuccess;
     if (ok && wide)
         ok = hipStreamCreateWithFlags(&L.wide, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipEventCreate(&L.ev0) == hipSuccess && hipEventCreate(&L.ev1) == hipSuccess &&
-         hipEventCreateWithFlags(&L.done, hipEventDisableTiming) == hipSuccess;
+    for (int sl = 0; sl < 2; sl++)
+        ok = ok && hipEventCreate(&L.ev0[sl]) == hipSuccess && hipEventCreate(&L.ev1[sl]) == hipSuccess &&
+             hipEventCreateWithFlags(&L.done[sl], hipEventDisableTiming) == hipSuccess;
     if (ok) {
         L.cur = L.stream;
         return TOR_OK;
@@ -1082,11 +1094,19 @@ size_t request_bytes(int n, unsigned sflags)
 // 52 KB of LDS, on a stream of the same CU mask) finds room beside them and
 // never waits for a chunk.
 constexpr int SERVE_QUICK_CUS = 12;
+// How long before the running chunk's expected end the next one is queued
+// behind it: the scheduler's polling interval and a launch's host time,
+// with room to spare.
+constexpr double SERVE_QUEUE_LEAD_S = 200e-6;
 
 // A serving launch in flight on one of the context's serving lanes.
 struct ServeLaunch {
     bool busy = false;
+    bool quick = false;  // on the express lane
     int path = PATH_REAL;
+    int slot = 0;                 // the lane slot of its buffers and events
+    long long subsets = 0;        // its work
+    double end_est = 0.0;         // when it should end (steady-clock seconds; 0: unknown)
     std::vector<Request *> used;  // one entry per root range (a request may hold two)
     std::vector<int> red;         // entries of used whose request the launch completes
 };
@@ -1094,21 +1114,28 @@ struct ServeLaunch {
 // Book a finished serving launch (rc its status; res 4 doubles per entry of
 // red): every request in it counts the launch once and takes its share of
 // the kernel time; the ones it completed, or all of them on failure, move
-// to finished.
-void retire_launch(int path, const std::vector<Request *> &used, const std::vector<int> &red, int rc,
-                   const std::vector<double> &res, float ms, std::vector<Request *> &finished)
+// to finished, once (a request that failed in an earlier launch is not
+// reported again).  A failed launch is booked only once nothing still runs
+// on its lane, since the requests' memory goes back to the pool.
+void retire_launch(const ServeLaunch &L, int rc, const std::vector<double> &res, float ms,
+                   std::vector<Request *> &finished)
 {
     std::vector<Request *> uniq;
-    for (Request *r : used)
+    for (Request *r : L.used)
         if (std::find(uniq.begin(), uniq.end(), r) == uniq.end())
             uniq.push_back(r);
     for (Request *r : uniq) {
-        r->in_flight = false;
+        --r->flights;
+        if (L.quick)
+            r->quick_flight = false;
         r->device_ms += ms / (float)uniq.size();
         ++r->launches;
     }
     if (rc != TOR_OK) {
         for (Request *r : uniq) {
+            if (r->failed)
+                continue;
+            r->failed = true;
             r->res = tor_result{};
             r->res.status = rc;
             r->next_root = r->nroots;
@@ -1116,9 +1143,11 @@ void retire_launch(int path, const std::vector<Request *> &used, const std::vect
         }
         return;
     }
-    for (size_t j = 0; j < red.size(); j++) {
-        Request *r = used[red[j]];
-        fill_result(r->st, path, &res[4 * j], r->device_ms, &r->res);
+    for (size_t j = 0; j < L.red.size(); j++) {
+        Request *r = L.used[L.red[j]];
+        if (r->failed)
+            continue;
+        fill_result(r->st, L.path, &res[4 * j], r->device_ms, &r->res);
         r->res.launches = r->launches;
         finished.push_back(r);
     }
@@ -1128,18 +1157,22 @@ enum { TAKE_SMALL, TAKE_LARGE, TAKE_ANY };  // which requests a serving round ta
 
 // One scheduling round for one path: pick root ranges of about `budget`
 // subsets, the oldest request's share first, then the requests with the
-// least remaining work (the small ones whole), and enqueue a launch of them on
-// lane, with the tuned waves per CU of their largest size (at most wpc_max
-// when positive) on `cus` CUs; rec records it.  TAKE_SMALL takes only the requests whose remaining work
-// is at most cfg.express_subsets, TAKE_LARGE only the others.  Requests
-// with roots in a launch in flight are left out.  Called with ctx->mu held.
+// least remaining work (the small ones whole), and enqueue a launch of them
+// on lane's current stream and slot, with the tuned waves per CU of their
+// largest size (at most wpc_max when positive) on `cus` CUs; rec records
+// it.  TAKE_SMALL takes only the requests whose remaining work is at most
+// cfg.express_subsets, TAKE_LARGE only the others.  An express launch (quick
+// set) leaves out every request with roots in flight; a chunked one only
+// those in an express launch, since chunks run one after another on their
+// lane's stream, so a request may hold roots in two queued chunks (and the
+// later one reduces it).  Called with ctx->mu held.
 int serve_round(tor_ctx *ctx, const ServeCfg &cfg, int path, std::vector<Request *> &active,
                 std::vector<Request *> &finished, int take_kind, long long budget, int cus, int wpc_max,
-                LaunchLane &lane, ServeLaunch &rec)
+                LaunchLane &lane, bool quick, ServeLaunch &rec)
 {
     std::vector<Request *> cand;
     for (Request *r : active) {
-        if (r->path != path || r->in_flight || r->next_root >= r->nroots)
+        if (r->path != path || r->failed || r->next_root >= r->nroots || r->quick_flight || (quick && r->flights > 0))
             continue;
         const bool small = (r->nroots - r->next_root) * r->root_work <= cfg.express_subsets;
         if (take_kind == TAKE_ANY || small == (take_kind == TAKE_SMALL))
@@ -1154,6 +1187,7 @@ int serve_round(tor_ctx *ctx, const ServeCfg &cfg, int path, std::vector<Request
     });
     std::vector<ProblemDesc> descs;
     std::vector<Request *> used;
+    long long work = 0;
     auto take = [&](Request *r, long long share) {
         long long n = std::max(1ll, share / std::max(r->root_work, 1ll));
         n = std::min(n, r->nroots - r->next_root);
@@ -1168,6 +1202,7 @@ int serve_round(tor_ctx *ctx, const ServeCfg &cfg, int path, std::vector<Request
         used.push_back(r);
         r->next_root += n;
         budget -= n * r->root_work;
+        work += n * r->root_work;
     };
     // a small request is taken whole or not at all, so that it takes one
     // launch; a large one's share may end anywhere
@@ -1196,36 +1231,59 @@ int serve_round(tor_ctx *ctx, const ServeCfg &cfg, int path, std::vector<Request
     for (size_t i = 0; i < used.size(); i++)
         if (used[i]->next_root == used[i]->nroots && std::find(used.begin(), used.begin() + i, used[i]) == used.begin() + i)
             red.push_back((int)i);
-    const int rc = run_launch(ctx, path, descs, red, 0, grid, nullptr, nullptr, 0, nullptr, &lane);
-    if (rc != TOR_OK) {
-        retire_launch(path, used, red, rc, {}, 0.f, finished);
-        return rc;
-    }
-    for (Request *r : used)
-        r->in_flight = true;
-    rec.busy = true;
+    rec = ServeLaunch{};
+    rec.quick = quick;
     rec.path = path;
+    rec.slot = lane.slot;
+    rec.subsets = work;
     rec.used = std::move(used);
     rec.red = std::move(red);
+    for (size_t i = 0; i < rec.used.size(); i++)
+        if (std::find(rec.used.begin(), rec.used.begin() + i, rec.used[i]) == rec.used.begin() + i) {
+            ++rec.used[i]->flights;
+            rec.used[i]->quick_flight |= quick;
+        }
+    const int rc = run_launch(ctx, path, descs, rec.red, 0, grid, nullptr, nullptr, 0, nullptr, &lane);
+    if (rc != TOR_OK) {
+        // its requests may hold roots in a launch queued before it
+        for (hipStream_t st : {lane.stream, lane.side, lane.wide})
+            if (st)
+                (void)hipStreamSynchronize(st);
+        retire_launch(rec, rc, {}, 0.f, finished);
+        rec = ServeLaunch{};
+        return rc;
+    }
+    lane.slot ^= 1;
+    rec.busy = true;
     return TOR_OK;
 }
 
-// Retire a serving launch if its lane's done event has been reached (or the
-// query failed).  Called with ctx->mu held.
-void poll_launch(const LaunchLane &lane, ServeLaunch &rec, std::vector<Request *> &finished)
+// Retire the launch if its done event has been reached, or on a failed
+// query, once its lane has drained.  Called with ctx->mu held.
+bool poll_launch(const LaunchLane &lane, ServeLaunch &rec, std::vector<Request *> &finished, double *ms_per_subset)
 {
     if (!rec.busy)
-        return;
-    const hipError_t q = hipEventQuery(lane.done);
+        return false;
+    const hipError_t q = hipEventQuery(lane.done[rec.slot]);
     if (q == hipErrorNotReady)
-        return;
+        return false;
     std::vector<double> res;
     float ms = 0.f;
     const int rc = hip_status(q);
-    if (rc == TOR_OK)
-        lane_collect(lane, (int)rec.red.size(), res, &ms);
-    retire_launch(rec.path, rec.used, rec.red, rc, res, ms, finished);
+    if (rc == TOR_OK) {
+        lane_collect(lane, rec.slot, (int)rec.red.size(), res, &ms);
+        if (ms_per_subset && rec.subsets > 0 && ms > 0.f) {
+            const double x = ms / (double)rec.subsets;
+            *ms_per_subset = *ms_per_subset > 0.0 ? 0.75 * *ms_per_subset + 0.25 * x : x;
+        }
+    } else {
+        for (hipStream_t st : {lane.stream, lane.side, lane.wide})
+            if (st)
+                (void)hipStreamSynchronize(st);
+    }
+    retire_launch(rec, rc, res, ms, finished);
     rec = ServeLaunch{};
+    return true;
 }
 
 // The scheduler.  Two launch lanes, each with at most one launch in flight:
@@ -1245,8 +1303,13 @@ void poll_launch(const LaunchLane &lane, ServeLaunch &rec, std::vector<Request *
 void serve_loop(tor_ctx *ctx)
 {
     std::vector<Request *> active;
-    ServeLaunch chunk, quick;
+    std::deque<ServeLaunch> chunks;  // in flight on the chunk lane, in stream order (at most two)
+    ServeLaunch quick;               // in flight on the express lane
+    double rate[NPATH] = {};         // kernel ms per subset of the recent chunks, per path
     int next_chunk = 0, next_quick = 0;  // each lane takes the paths in turn
+    auto now_s = [] {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    };
     static const int kPaths[NPATH] = {PATH_REAL, PATH_CPLX, PATH_QUAD};
     (void)prctl(PR_SET_TIMERSLACK, 1000ul, 0ul, 0ul, 0ul);  // polling sleeps of tens of microseconds
     // retire finished requests: release their pool memory and wake pollers
@@ -1271,9 +1334,9 @@ void serve_loop(tor_ctx *ctx)
         {
             std::unique_lock<std::mutex> lk(ctx->smu);
             auto ready = [&] {
-                return ctx->stop || !ctx->pending.empty() || (!chunk.busy && !quick.busy && !active.empty());
+                return ctx->stop || !ctx->pending.empty() || (chunks.empty() && !quick.busy && !active.empty());
             };
-            if (chunk.busy || quick.busy)  // poll the events, waking early for new requests
+            if (!chunks.empty() || quick.busy)  // poll the events, waking early for new requests
                 ctx->scv.wait_for(lk, std::chrono::microseconds(20), ready);
             else
                 ctx->scv.wait(lk, ready);
@@ -1325,26 +1388,43 @@ void serve_loop(tor_ctx *ctx)
                 rc = lane_open(ctx->quick, ctx->num_cu, ctx->num_cu - SERVE_QUICK_CUS, SERVE_QUICK_CUS, true, true);
             // express launches beside a chunk need both masks
             const bool beside = rc == TOR_OK && ctx->chunk.cus > 0 && ctx->quick.cus > 0;
-            poll_launch(ctx->chunk, chunk, finished);
-            poll_launch(ctx->quick, quick, finished);
+            if (rc == TOR_OK) {
+                while (!chunks.empty() && poll_launch(ctx->chunk, chunks.front(), finished, &rate[chunks.front().path]))
+                    chunks.pop_front();
+                poll_launch(ctx->quick, quick, finished, nullptr);
+            }
             // the next chunk: the large requests, or, while the express lane
-            // is busy, any (the paths in turn)
+            // is busy, any (the paths in turn).  It is queued behind the one
+            // running when that one is due to end within SERVE_QUEUE_LEAD_S
+            // (by the rate of recent chunks), so the lane does not sit idle
+            // while the host sees the end and launches the next.
             auto start_chunk = [&] {
+                if (chunks.size() >= 2 ||
+                    (chunks.size() == 1 && !(chunks.back().end_est > 0.0 && now_s() >= chunks.back().end_est - SERVE_QUEUE_LEAD_S)))
+                    return;
+                ServeLaunch rec;
                 for (int kind : {TAKE_LARGE, TAKE_ANY}) {
                     if (kind == TAKE_ANY && cfg.express_subsets > 0 && !quick.busy)
                         break;
-                    for (int i = 0; i < NPATH && !chunk.busy; i++) {
+                    for (int i = 0; i < NPATH && !rec.busy; i++) {
                         const int path = kPaths[(next_chunk + i) % NPATH];
                         serve_round(ctx, cfg, path, active, finished, kind, cfg.chunk_subsets,
-                                    ctx->chunk.cus > 0 ? ctx->chunk.cus : ctx->num_cu, 0, ctx->chunk, chunk);
-                        if (chunk.busy)
+                                    ctx->chunk.cus > 0 ? ctx->chunk.cus : ctx->num_cu, 0, ctx->chunk, false, rec);
+                        if (rec.busy)
                             next_chunk = (next_chunk + i + 1) % NPATH;
                     }
-                    if (chunk.busy)
+                    if (rec.busy)
                         break;
                 }
+                if (!rec.busy)
+                    return;
+                const double t = now_s();
+                const bool known = rate[rec.path] > 0.0 && (chunks.empty() || chunks.back().end_est > 0.0);
+                const double start = chunks.empty() ? t : std::max(t, chunks.back().end_est);
+                rec.end_est = known ? start + 1e-3 * rate[rec.path] * (double)rec.subsets : 0.0;
+                chunks.push_back(std::move(rec));
             };
-            if (rc == TOR_OK && !chunk.busy)
+            if (rc == TOR_OK)
                 start_chunk();
             // stage the admitted requests on the device, straight into their
             // pool slots; the path and size of each are known from here on
@@ -1361,7 +1441,7 @@ void serve_loop(tor_ctx *ctx)
             // on the express CUs while a chunk holds the others (an unmasked
             // workgroup can be handed to a shader engine whose CUs the chunk
             // fills, and wait there for the whole chunk)
-            const hipStream_t sst = chunk.busy && ctx->quick.side ? ctx->quick.side : ctx->stream;
+            const hipStream_t sst = !chunks.empty() && ctx->quick.side ? ctx->quick.side : ctx->stream;
             const int src = admit.empty() ? TOR_OK : stage_sync(ctx, in, false, sfl, CPLX_R, 0, mats, &end, sst);
             for (size_t j = 0; j < admit.size(); j++) {
                 Request *r = admit[j];
@@ -1386,7 +1466,8 @@ void serve_loop(tor_ctx *ctx)
             if (rc != TOR_OK) {
                 // no serving lanes: every admitted request fails
                 for (Request *r : active)
-                    if (!r->in_flight) {
+                    if (r->flights == 0 && !r->failed) {
+                        r->failed = true;
                         r->res = tor_result{};
                         r->res.status = rc;
                         finished.push_back(r);
@@ -1395,21 +1476,21 @@ void serve_loop(tor_ctx *ctx)
                 // small requests: beside the chunk in flight on the express
                 // lane's own CUs, with about the work those CUs do in a
                 // chunk's time, or on the whole device when no chunk runs
-                if (cfg.express_subsets > 0 && !quick.busy && (!chunk.busy || beside)) {
-                    ctx->quick.cur = chunk.busy ? ctx->quick.stream : ctx->quick.wide;
-                    const int cus = chunk.busy ? ctx->quick.cus : ctx->num_cu;
+                const bool chunk_busy = !chunks.empty();
+                if (cfg.express_subsets > 0 && !quick.busy && (!chunk_busy || beside)) {
+                    ctx->quick.cur = chunk_busy ? ctx->quick.stream : ctx->quick.wide;
+                    const int cus = chunk_busy ? ctx->quick.cus : ctx->num_cu;
                     const long long budget =
-                        chunk.busy ? std::max(1ll, cfg.chunk_subsets / ctx->num_cu * cus) : (1ll << 62);
+                        chunk_busy ? std::max(1ll, cfg.chunk_subsets / ctx->num_cu * cus) : (1ll << 62);
                     for (int i = 0; i < NPATH && !quick.busy; i++) {
                         const int path = kPaths[(next_quick + i) % NPATH];
                         serve_round(ctx, cfg, path, active, finished, TAKE_SMALL, budget, cus,
-                                    chunk.busy ? std::max(1, ctx->fit[path] / 2) : 0, ctx->quick, quick);
+                                    chunk_busy ? std::max(1, ctx->fit[path] / 2) : 0, ctx->quick, true, quick);
                         if (quick.busy)
                             next_quick = (next_quick + i + 1) % NPATH;
                     }
                 }
-                if (!chunk.busy)
-                    start_chunk();
+                start_chunk();
             }
         }
         publish(finished);
