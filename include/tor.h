@@ -122,7 +122,7 @@ typedef struct {
                                   requests: their share of the launches they ran in)    */
     int launches;              /* launches of the recursive kernel that computed it: 1,
                                   2 when failed roots ran once more (tor_eval), or for a
-                                  served request the chunked launches it took part in  */
+                                  served request the serving launches it took part in  */
 } tor_result;
 
 /* Defaults for every field (device 0, library stream and workspace, max_n 40). */
@@ -133,10 +133,10 @@ void tor_default_options(tor_options *opt);
  * aligned to 256 bytes), TOR_E_DEVICE (no GPU), TOR_E_NOMEM. */
 int tor_create(tor_ctx **out, const tor_options *opt);
 
-/* Stop the serving scheduler after the launch it has on the GPU, cancel the
- * served requests that have not completed (their tickets are released), wait
- * for the context's stream, then free every device and host resource.  A
- * request must not be polled after its context is destroyed. */
+/* Stop the serving scheduler, cancel the served requests that have not
+ * completed (their tickets are released), wait for the context's stream and
+ * for the serving launches still on the GPU, then free every device and host
+ * resource.  A request must not be polled after its context is destroyed. */
 void tor_destroy(tor_ctx *ctx);
 
 /* Device bytes a caller-provided workspace needs for matrices up to max_n
@@ -308,18 +308,22 @@ int tor_debug_fail_root(tor_ctx *ctx, long long root, int runs);
 int tor_debug_zeta(tor_ctx *ctx, int nbits, const double *t, double *g_hi, double *g_lo);
 
 /* Serving policy.  Each chunked serving launch runs at most chunk_subsets
- * subsets (default 2^29, about 2.5 ms at n = 30 rates) taken from the
- * admitted requests: oldest_share of it (default 0.5) goes to the oldest
- * request, the rest to the requests with the least remaining work, so a
- * request larger than a chunk is split over several launches (root ranges
- * of its subtree roots) while requests that arrive meanwhile join the next
- * launch.  Before each chunked launch, the requests with at most
- * express_subsets subsets of work left (default 2^24, n <= 24; 0 disables
- * it) run whole in a launch of their own, and their results can be polled
- * before the chunked launch starts.  max_queue bounds the requests held
- * (admitted or waiting); tor_submit beyond it returns TOR_E_BUSY.  Applies
- * from the scheduler's next round on.  Errors: TOR_E_INVAL (chunk_subsets
- * < 1024, express_subsets < 0, oldest_share outside [0, 1], max_queue < 1). */
+ * subsets (default 2^29, about 1.5 ms at n = 30 rates) taken from the
+ * admitted requests with more than express_subsets subsets of work left:
+ * oldest_share of it (default 0.5) goes to the oldest request, the rest to
+ * the requests with the least remaining work, so a request larger than a
+ * chunk is split over several launches (root ranges of its subtree roots)
+ * while requests that arrive meanwhile join a later launch.  Chunked
+ * launches run on all CUs but 12, one after another on a stream of their
+ * own.  The requests with at most express_subsets subsets of work left
+ * (default 2^24, n <= 24; 0 disables it) run whole in express launches on a
+ * second stream: beside a chunked launch on the 12 CUs it leaves out, or on
+ * the whole device when none runs, so they wait for no chunk (a chunk takes
+ * them only while an express launch is busy).  max_queue bounds the
+ * requests held (admitted or waiting); tor_submit beyond it returns
+ * TOR_E_BUSY.  Applies from the scheduler's next round on.  Errors:
+ * TOR_E_INVAL (chunk_subsets < 1024, express_subsets < 0, oldest_share
+ * outside [0, 1], max_queue < 1). */
 int tor_serve_config(tor_ctx *ctx, long long chunk_subsets, long long express_subsets,
                      double oldest_share, int max_queue);
 
