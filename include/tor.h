@@ -314,10 +314,10 @@ int tor_debug_zeta(tor_ctx *ctx, int nbits, const double *t, double *g_hi, doubl
  * the requests with the least remaining work, so a request larger than a
  * chunk is split over several launches (root ranges of its subtree roots)
  * while requests that arrive meanwhile join a later launch.  Chunked
- * launches run on all CUs but 12, one after another on a stream of their
+ * launches run on all CUs but 16, one after another on a stream of their
  * own.  The requests with at most express_subsets subsets of work left
  * (default 2^24, n <= 24; 0 disables it) run whole in express launches on a
- * second stream: beside a chunked launch on the 12 CUs it leaves out, or on
+ * second stream: beside a chunked launch on the 16 CUs it leaves out, or on
  * the whole device when none runs, so they wait for no chunk (a chunk takes
  * them only while an express launch is busy).  max_queue bounds the
  * requests held (admitted or waiting); tor_submit beyond it returns

@@ -1089,11 +1089,12 @@ size_t request_bytes(int n, unsigned sflags)
 }
 
 // CUs that the chunked serving launches leave to the express launches beside
-// them (4.7 % of a 256-CU part).  The express launches there fill each CU
+// them (two per die of an eight-die part, 6 % of its 256; 8 and 12 gave a
+// higher median latency at the same saturated rate).  The express launches there fill each CU
 // to half the waves it holds, so that staging (a 1024-thread workgroup with
 // 52 KB of LDS, on a stream of the same CU mask) finds room beside them and
 // never waits for a chunk.
-constexpr int SERVE_QUICK_CUS = 12;
+constexpr int SERVE_QUICK_CUS = 16;
 // How long before the running chunk's expected end the next one is queued
 // behind it: the scheduler's polling interval and a launch's host time,
 // with room to spare.
