@@ -308,7 +308,7 @@ int tor_debug_fail_root(tor_ctx *ctx, long long root, int runs);
 int tor_debug_zeta(tor_ctx *ctx, int nbits, const double *t, double *g_hi, double *g_lo);
 
 /* Serving policy.  Each chunked serving launch runs at most chunk_subsets
- * subsets (default 2^29, about 1.5 ms at n = 30 rates) taken from the
+ * subsets (default 2^30, about 2.9 ms at n = 30 rates) taken from the
  * admitted requests with more than express_subsets subsets of work left:
  * oldest_share of it (default 0.5) goes to the oldest request, the rest to
  * the requests with the least remaining work, so a request larger than a

@@ -493,7 +493,7 @@ class Context:
         if rc != TOR_OK:
             raise TorError(rc, "tor_drain")
 
-    def serve_config(self, chunk_subsets: int = 1 << 29, oldest_share: float = 0.5,
+    def serve_config(self, chunk_subsets: int = 1 << 30, oldest_share: float = 0.5,
                      max_queue: int = 1 << 16, express_subsets: int = 1 << 24) -> None:
         rc = self._lib.tor_serve_config(self._h, chunk_subsets, express_subsets, oldest_share, max_queue)
         if rc != TOR_OK:

@@ -84,7 +84,7 @@ struct Request {
 // Serving policy (tor_serve_config).  Written under the serving lock; the
 // scheduler takes a copy under the same lock before each round.
 struct ServeCfg {
-    long long chunk_subsets = 1ll << 29;   // work per chunked serving launch
+    long long chunk_subsets = 1ll << 30;   // work per chunked serving launch
     long long express_subsets = 1ll << 24; // requests this small run ahead, whole (0: none)
     double oldest_share = 0.5;             // of a chunk, guaranteed to the oldest request
 };
