@@ -140,7 +140,9 @@ int tor_create(tor_ctx **out, const tor_options *opt);
 void tor_destroy(tor_ctx *ctx);
 
 /* Device bytes a caller-provided workspace needs for matrices up to max_n
- * with up to max_inflight concurrent serving requests. */
+ * with up to max_inflight concurrent serving requests (serving stages its
+ * requests there; its request pool, 256 MiB, and the workspaces of its two
+ * launch streams it allocates itself on the first submission). */
 size_t tor_workspace_size(int max_n, int split_k, int max_inflight);
 
 /* Torontonian of one 2n x 2n matrix (Eq. 2), recursive GPU path.  Each of
