@@ -17,10 +17,11 @@
 // one by one.
 //
 // The transform adds along one index bit at a time (g[S] += g[S without bit b]
-// for every S with bit b set).  The low 10 to 12 bits run in LDS, one block
-// of 1024 to 4096 entries per workgroup; the higher bits in global passes of
-// up to ZG = 5 bits, each thread holding the 32 entries that differ only in
-// those bits.  Every pass reads and writes all 2^M sums once, so the launch
+// for every S with bit b set).  The low 10 to 12 bits run in one workgroup per
+// block of 1024 to 4096 entries, its threads adding along a few bits in
+// registers and exchanging the block through LDS between those rounds; the
+// higher bits in global passes of up to ZG = 5 bits, each thread holding the
+// 32 entries that differ only in those bits.  Every pass reads and writes all 2^M sums once, so the launch
 // takes as few passes as 12 bits in LDS allow, with the smallest LDS block
 // that reaches that count: a 4096-entry block (64 KB) leaves room for two
 // workgroups per CU and keeps fewer loads in flight than the 1024-entry one
@@ -44,6 +45,18 @@ namespace {
 
 constexpr int ZB_MAX = 12;  // most index bits transformed in LDS (blocks of 4096 entries)
 constexpr int ZG = 5;       // index bits per global pass
+// whole 12- and 10-bit blocks: threads and register bits of tor_zeta_lds_r
+// (threads 0: the bit-by-bit LDS kernel).  At M = 32, 256 threads of 16
+// entries gave 159.8 ms per call, 512 of 8 161.0, 1024 of 4 164.8, the
+// bit-by-bit kernel 167.5-168.8 (M = 24: 0.56 against 0.58 ms).
+#ifndef ZR12_T
+#define ZR12_T 256
+#define ZR12_RB 4
+#endif
+#ifndef ZR10_T
+#define ZR10_T 256
+#define ZR10_RB 2
+#endif
 
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
 {
@@ -91,6 +104,67 @@ __global__ void __launch_bounds__(ZT) tor_zeta_lds(const double *t, ddr *g, int 
     }
     for (int i = threadIdx.x; i < size; i += ZT)
         g[base + i] = ddr{hs[i], ls[i]};
+}
+
+// All ZB bits of a block of 2^ZB entries, with the additions in registers:
+// each of the ZT threads holds E = 2^RB entries that differ only in RB index
+// bits and adds along those bits; between rounds (bits from the highest down)
+// the block moves through LDS so that each thread holds the entries of the
+// next RB bits.  Per entry that is 4 doubles of LDS traffic per round and
+// two barriers, against 3 doubles and one barrier per bit.  The LDS index is
+// XOR-swizzled within each run of 16 entries, i ^ ((i >> RB) & 15), which
+// leaves no two of the 16 lanes that one cycle of a 64-bit access serves on
+// the same bank in any round or in the final copy.  The first round reads
+// the terms straight from global memory (consecutive lanes, consecutive
+// entries); the last one goes out through LDS so that the double-double
+// sums are written in consecutive runs.  Terms in, double-double out.
+template <int ZB, int ZT, int RB>
+__global__ void __launch_bounds__(ZT) tor_zeta_lds_r(const double *t, ddr *g)
+{
+    static_assert((ZT << RB) == (1 << ZB) && ZB % RB == 0, "a block is ZT threads of 2^RB entries");
+    constexpr int E = 1 << RB;
+    __shared__ double hs[1 << ZB], ls[1 << ZB];
+    const long long base = (long long)blockIdx.x << ZB;
+    const int q = threadIdx.x;
+    auto sw = [](int i) { return i ^ ((i >> RB) & 15); };
+    // entry j of thread q in the round of bits s .. s+RB-1
+    auto idx = [&](int s, int j) { return (q & ((1 << s) - 1)) | (j << s) | ((q >> s) << (s + RB)); };
+    double h[E], l[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        h[j] = t[base + idx(ZB - RB, j)];
+        l[j] = 0.0;
+    }
+#pragma unroll
+    for (int s = ZB - RB; s >= 0; s -= RB) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+#pragma unroll
+            for (int j = 0; j < E; ++j)
+                if ((j >> b) & 1)
+                    dd_acc(h[j], l[j], h[j ^ (1 << b)], l[j ^ (1 << b)]);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int i = sw(idx(s, j));
+            hs[i] = h[j];
+            ls[i] = l[j];
+        }
+        __syncthreads();
+        if (s == 0)
+            break;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int i = sw(idx(s - RB, j));
+            h[j] = hs[i];
+            l[j] = ls[i];
+        }
+        __syncthreads();  // every entry is read before the next round writes
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int i = q + k * ZT;
+        g[base + i] = ddr{hs[sw(i)], ls[sw(i)]};
+    }
 }
 
 // bits b0 .. b0+nb-1 (nb <= ZG) over all 2^nbits entries: thread q holds the
@@ -189,7 +263,22 @@ hipError_t launch_zeta(const double *t, ddr *g, int nbits, hipStream_t s)
     const int zb = passes(10) == passes(ZB_MAX) ? 10 : passes(11) == passes(ZB_MAX) ? 11 : ZB_MAX;
     const int nb = nbits < zb ? nbits : zb;
     const dim3 grid((unsigned)(1ll << (nbits - nb)));
-    if (zb == 10)
+    bool done = false;
+#if ZR12_T > 0
+    if (nb == 12) {
+        hipLaunchKernelGGL((tor_zeta_lds_r<12, ZR12_T, ZR12_RB>), grid, dim3(ZR12_T), 0, s, t, g);
+        done = true;
+    }
+#endif
+#if ZR10_T > 0
+    if (nb == 10) {
+        hipLaunchKernelGGL((tor_zeta_lds_r<10, ZR10_T, ZR10_RB>), grid, dim3(ZR10_T), 0, s, t, g);
+        done = true;
+    }
+#endif
+    if (done)
+        ;
+    else if (zb == 10)
         hipLaunchKernelGGL((tor_zeta_lds<10, 256>), grid, dim3(256), 0, s, t, g, nb);
     else if (zb == 11)
         hipLaunchKernelGGL((tor_zeta_lds<11, 512>), grid, dim3(512), 0, s, t, g, nb);
