@@ -21,13 +21,14 @@
 // block of 1024 to 4096 entries, its threads adding along a few bits in
 // registers and exchanging the block through LDS between those rounds; the
 // higher bits in global passes of up to ZG = 5 bits, each thread holding the
-// 32 entries that differ only in those bits.  Every pass reads and writes all 2^M sums once, so the launch
-// takes as few passes as 12 bits in LDS allow, with the smallest LDS block
-// that reaches that count: a 4096-entry block (64 KB) leaves room for two
-// workgroups per CU and keeps fewer loads in flight than the 1024-entry one
-// (16 KB).  At M = 32 that is 12 bits in LDS and four 5-bit passes, against
-// 10 bits and six passes of 4 bits (226 ms to 172 ms for all 2^32 patterns);
-// at M = 24 and 28, 10 bits in LDS.
+// 32 entries that differ only in those bits.  Every pass reads and writes
+// all 2^M sums once, so the launch takes as few passes as 12 bits in the
+// first stage allow, with the smallest block that reaches that count: a
+// 4096-entry block (64 KB of LDS) leaves room for two workgroups per CU and
+// keeps fewer loads in flight than a 1024-entry one (16 KB).  At M = 32 that
+// is 12 bits first and four 5-bit passes, against 10 bits and six passes of
+// 4 bits (226 ms to 172 ms for all 2^32 patterns); at M = 24 and 28, 10 bits
+// first.
 //
 // Exactness: for a Gaussian state every subset determinant is at most 1
 // (sqrt(det(I - O)) / sqrt(det (I - O)_Z) is the probability that no mode
