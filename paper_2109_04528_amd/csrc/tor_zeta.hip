@@ -170,6 +170,9 @@ __global__ void __launch_bounds__(ZT) tor_zeta_lds_r(const double *t, ddr *g)
 
 // bits b0 .. b0+nb-1 (nb <= ZG) over all 2^nbits entries: thread q holds the
 // 2^nb entries whose index has q's bits below b0 and above b0+nb-1
+// NT: streaming (non-temporal) loads and stores, for sums too large to stay
+// in the caches between passes
+template <bool NT>
 __global__ void __launch_bounds__(256) tor_zeta_bits(ddr *g, int nbits, int b0, int nb)
 {
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -181,9 +184,14 @@ __global__ void __launch_bounds__(256) tor_zeta_bits(ddr *g, int nbits, int b0, 
 #pragma unroll
     for (int j = 0; j < (1 << ZG); ++j)
         if (j < (1 << nb)) {
-            const ddr v = g[base + ((long long)j << b0)];
-            h[j] = v.hi;
-            l[j] = v.lo;
+            const double *pv = reinterpret_cast<const double *>(g + base + ((long long)j << b0));
+            if constexpr (NT) {
+                h[j] = __builtin_nontemporal_load(pv);
+                l[j] = __builtin_nontemporal_load(pv + 1);
+            } else {
+                h[j] = pv[0];
+                l[j] = pv[1];
+            }
         }
 #pragma unroll
     for (int b = 0; b < ZG; ++b)
@@ -195,8 +203,15 @@ __global__ void __launch_bounds__(256) tor_zeta_bits(ddr *g, int nbits, int b0, 
         }
 #pragma unroll
     for (int j = 0; j < (1 << ZG); ++j)
-        if (j < (1 << nb))
-            g[base + ((long long)j << b0)] = ddr{h[j], l[j]};
+        if (j < (1 << nb)) {
+            if constexpr (NT) {
+                double *pv = reinterpret_cast<double *>(g + base + ((long long)j << b0));
+                __builtin_nontemporal_store(h[j], pv);
+                __builtin_nontemporal_store(l[j], pv + 1);
+            } else {
+                g[base + ((long long)j << b0)] = ddr{h[j], l[j]};
+            }
+        }
 }
 
 // one pattern's outputs from its subset sum v
@@ -289,7 +304,16 @@ hipError_t launch_zeta(const double *t, ddr *g, int nbits, hipStream_t s)
     for (int b0 = nb; e == hipSuccess && b0 < nbits; b0 += ZG) {
         const int w = nbits - b0 < ZG ? nbits - b0 : ZG;
         const long long threads = 1ll << (nbits - w);
-        hipLaunchKernelGGL(tor_zeta_bits, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, g, nbits, b0, w);
+        // streaming accesses once the sums (16 B each) pass 1 GiB: at M = 28
+        // and 32 they took the call from 10.6 to 10.3 ms and from 159.6 to
+        // 156.0 ms, at M = 24 (268 MB, mostly held by the caches) from 0.56 to
+        // 0.59 ms the other way
+        if (nbits >= 26)
+            hipLaunchKernelGGL((tor_zeta_bits<true>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, g,
+                               nbits, b0, w);
+        else
+            hipLaunchKernelGGL((tor_zeta_bits<false>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, g,
+                               nbits, b0, w);
         e = hipGetLastError();
     }
     return e;
