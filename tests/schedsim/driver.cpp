@@ -1,7 +1,8 @@
 // Drives the serving scheduler of the library's host runtime, built for the
 // CPU against the HIP stand-in (tests/schedsim), through the scenarios the
-// GPU tests use and randomised streams, and checks that every request
-// completes, within a time limit, with the value of its lone evaluation.
+// GPU tests use, randomised streams and streams of both arithmetic paths,
+// and checks that every request completes, within a time limit, with the
+// value of its lone evaluation.
 // Exit status 0 when all scenarios pass; 1 on a wrong value or status; 3 when
 // a scenario does not finish in time (the scheduler hung).
 #include <atomic>
@@ -28,11 +29,13 @@ void check(bool ok, const char *what, int i = -1)
     }
 }
 
-// a 2n x 2n complex matrix whose first entry is c (the stand-in reads only that)
-std::vector<double> matrix(int n, double c)
+// a 2n x 2n complex matrix whose first entry is c, with imaginary part 1 for
+// general Hermitian input (the stand-in reads only that entry)
+std::vector<double> matrix(int n, double c, bool general = false)
 {
     std::vector<double> m(8 * (size_t)n * n, 0.0);
     m[0] = c;
+    m[1] = general ? 1.0 : 0.0;
     return m;
 }
 
@@ -139,8 +142,24 @@ int main(int argc, char **argv)
         }
         serve_and_check(ctx, rs, &rng, 500, "chunks only");
     }
-    // 5: destroy with requests in flight
+    // 5: both arithmetic paths in one stream (the lanes take the paths in turn)
     g_phase = 5;
+    {
+        check(tor_serve_config(ctx, 1 << 21, 1 << 14, 0.5, 1 << 16) == TOR_OK, "config");
+        std::vector<Req> rs;
+        std::uniform_int_distribution<int> nd(8, 24);
+        for (int i = 0; i < 200; i++) {
+            const int n = nd(rng);
+            rs.push_back(Req{n, matrix(n, 5.0 + i / 1024.0, i % 3 == 1)});
+        }
+        serve_and_check(ctx, rs, &rng, 100, "both paths");
+        int cplx = 0;
+        for (auto &r : rs)
+            cplx += r.served.path == 2;
+        check(cplx > 0 && cplx < (int)rs.size(), "both paths served");
+    }
+    // 6: destroy with requests in flight
+    g_phase = 6;
     {
         check(tor_serve_config(ctx, 1 << 20, 1 << 12, 0.5, 1 << 16) == TOR_OK, "config");
         std::vector<Req> rs;

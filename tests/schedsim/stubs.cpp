@@ -1,8 +1,10 @@
 // Stand-ins for the library's kernel launchers, for the CPU build of its host
 // runtime (tests/schedsim).  Each one queues host work on the stream in the
 // place of the kernel.  The staging stand-in puts the first real part of the
-// input into the staged form and takes every input as a Gaussian state's
-// (real quadrature path, N = max(n, REAL_R)); the recursive stand-in gives
+// input into the staged form and takes an input as a Gaussian state's (real
+// quadrature path, N = max(n, REAL_R)) unless the imaginary part of its first
+// entry is positive (then general Hermitian input: the complex path, N =
+// max(n, min_cplx)); the recursive stand-in gives
 // root r of a matrix of N modes split at depth k the slot (c 2^(N-k), 0,
 // 2^(N-k), 0), c that staged value, so a matrix's sum is c 2^N whatever its
 // split, and every root counts once: a root run twice or not at all, or a
@@ -47,10 +49,13 @@ hipError_t launch_stage(const StageDesc *descs, int count, hipStream_t s)
     fake_enqueue(s, [=] {
         for (int i = 0; i < count; i++) {
             const StageDesc &D = descs[i];
-            const bool cplx = (D.flags & STAGE_FORCE_CPLX) != 0;
             double c = 0.0;
-            if (D.O && D.n > 0)
+            bool general = false;
+            if (D.O && D.n > 0) {
                 c = D.O[0];
+                general = D.O[1] > 0.0;
+            }
+            const bool cplx = (D.flags & STAGE_FORCE_CPLX) != 0 || (general && !(D.flags & STAGE_DD));
             if (D.out)
                 std::memcpy(D.out, &c, sizeof c);
             D.info->status = (std::isfinite(c) ? 0 : STAGE_BAD_INPUT);

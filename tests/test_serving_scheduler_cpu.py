@@ -8,7 +8,8 @@ matrix's sum independent of its split and wrong if a root runs twice, not at
 all, or on another request's slots.  The driver serves the policy and sizes
 of the sanitized GPU driver, a mixed stream with arrivals over time, a
 saturated burst under the default policy, chunked launches with express
-launches off, and a destroy with requests in flight; every served value must
+launches off, a stream of both arithmetic paths, and a destroy with requests
+in flight; every served value must
 equal the lone evaluation's, and every scenario must finish in time.  It
 runs under AddressSanitizer with UndefinedBehaviorSanitizer and under
 ThreadSanitizer (clang's, which understands the condition-variable waits the
