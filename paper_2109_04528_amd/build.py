@@ -16,6 +16,12 @@ LIB = os.path.join(HERE, "libtor.so")
 ARCH = os.environ.get("TOR_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["tor_kernels.hip", "tor_compare.hip", "tor_stage.hip", "tor_zeta.hip", "tor_probe.hip", "tor_runtime.cpp"]
+# the double-double factor's kernel: its own translation unit, compiled with
+# the AMDGPU scheduler's register-pressure trackers, which schedule it about
+# 4 % faster (the FP64 kernels gain nothing from them)
+QUAD_SOURCE = "tor_kernels_quad.hip"
+QUAD_FLAGS = ["-mllvm", "-amdgpu-use-amdgpu-trackers"]
+OBJ_DIR = os.path.join(HERE, "_build")
 
 
 def hipcc() -> str:
@@ -26,15 +32,20 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, extra=None) -> str:
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-fno-fast-math", "-Wall", "-Wno-unused-function",
-           "-I", os.path.join(HERE, "..", "include"),
-           "-x", "hip"] + [os.path.join(CSRC, s) for s in SOURCES] + \
-          ["-o", LIB + ".tmp", "-lpthread"] + list(extra or [])
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    common = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+              "-fno-fast-math", "-Wall", "-Wno-unused-function",
+              "-I", os.path.join(HERE, "..", "include")]
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    quad_obj = os.path.join(OBJ_DIR, "tor_kernels_quad.o")
+    qcmd = common + QUAD_FLAGS + ["-c", "-x", "hip", os.path.join(CSRC, QUAD_SOURCE), "-o", quad_obj] + \
+        list(extra or [])
+    cmd = common + ["-shared", "-x", "hip"] + [os.path.join(CSRC, s) for s in SOURCES] + \
+        ["-x", "none", quad_obj, "-o", LIB + ".tmp", "-lpthread"] + list(extra or [])
+    for c in (qcmd, cmd):
+        if verbose:
+            print(" ".join(c), flush=True)
+        subprocess.run(c, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 
@@ -56,8 +67,8 @@ def build_sanitized(verbose: bool = False) -> str:
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O2", "-g", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-fno-fast-math", "-Wno-unused-function"] + san + \
-          ["-I", os.path.join(HERE, "..", "include"), "-x", "hip"] + [os.path.join(CSRC, s) for s in SOURCES] + \
-          ["-o", SAN_LIB + ".tmp", "-lpthread"]
+          ["-I", os.path.join(HERE, "..", "include"), "-x", "hip"] + \
+          [os.path.join(CSRC, s) for s in SOURCES + [QUAD_SOURCE]] + ["-o", SAN_LIB + ".tmp", "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

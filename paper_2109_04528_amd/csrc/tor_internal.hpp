@@ -203,5 +203,9 @@ hipError_t launch_stage(const StageDesc *descs, int count, hipStream_t s);
 hipError_t launch_sqrt_det(const double *O, long ld, int M, c64 *scratch, double *out, hipStream_t s);
 // resident one-wave workgroups of the main kernel per CU (0 on error)
 int main_occupancy(int path);
+// the double-double factor's main kernel and its occupancy, used by the two
+// above for PATH_QUAD (tor_kernels_quad.hip)
+hipError_t launch_main_quad(const MainParams &p, int grid, hipStream_t s);
+int main_occupancy_quad();
 
 }  // namespace tor

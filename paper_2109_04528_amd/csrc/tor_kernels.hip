@@ -36,6 +36,9 @@
 // Terms are summed per lane in double-double, reduced over the wave, and
 // written to the root's partial slot; a second kernel sums the slots of each
 // matrix in index order.
+// The double-double factor's instantiation of the main kernel is built in
+// tor_kernels_quad.hip, which includes this file with
+// TOR_KERNELS_TEMPLATES_ONLY defined (templates only, no launchers).
 #include <type_traits>
 
 #include "tor_device.hpp"
@@ -1043,6 +1046,10 @@ __global__ void __launch_bounds__(RED_THREADS) tor_reduce(const ProblemDesc *pro
     }
 }
 
+#ifndef TOR_KERNELS_TEMPLATES_ONLY
+// Everything below is built once, in this translation unit; the
+// double-double factor's kernel is instantiated and launched from
+// tor_kernels_quad.hip, which includes the templates above on their own.
 __global__ void tor_zero(unsigned long long *p, int count)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1068,7 +1075,7 @@ int main_store_occupancy()
 hipError_t launch_main(int path, bool dd, const MainParams &p, int grid, hipStream_t s)
 {
     if (path == PATH_QUAD) {
-        hipLaunchKernelGGL((tor_main<ddr, QUAD_T, QUAD_B, QUAD_L, AccQ>), dim3(grid), dim3(64), 0, s, p);
+        return launch_main_quad(p, grid, s);
     } else if (path == PATH_REAL) {
         if (dd)
             hipLaunchKernelGGL((tor_main<double, REAL_T, REAL_B, REAL_L, AccDD>), dim3(grid), dim3(64), 0, s, p);
@@ -1088,8 +1095,8 @@ int main_occupancy(int path)
     int n = 0;
     hipError_t e;
     if (path == PATH_QUAD)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tor_main<ddr, QUAD_T, QUAD_B, QUAD_L, AccQ>, 64, 0);
-    else if (path == PATH_REAL)
+        return main_occupancy_quad();
+    if (path == PATH_REAL)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tor_main<double, REAL_T, REAL_B, REAL_L, AccDD>, 64, 0);
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tor_main<c64, CPLX_T, CPLX_B, CPLX_L, AccDD>, 64, 0);
@@ -1110,5 +1117,6 @@ hipError_t launch_zero(unsigned long long *p, int count, hipStream_t s)
     hipLaunchKernelGGL(tor_zero, dim3((count + 63) / 64), dim3(64), 0, s, p, count);
     return hipGetLastError();
 }
+#endif  // TOR_KERNELS_TEMPLATES_ONLY
 
 }  // namespace tor
